@@ -1,0 +1,341 @@
+"""Pins of the FP64 CPU oracle against facts the paper and the mathematics fix.
+
+None of these re-types the oracle's recurrence: each checks it against a closed
+form (eq. (1), eq. (2)), a textbook method written from a different formulation
+(Gauss-Seidel on explicitly formed normal equations, Gauss-Seidel on the dual of
+eq. (3)), per-step invariants, special cases, the Gauss-Seidel rate, or a library
+routine (LAPACK solve, scipy's CSR->CSC).
+"""
+import numpy as np
+import pytest
+
+from paper_1902_08653_amd import inputs
+
+
+def crandn(rng, *shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)
+
+
+def lmmse_closed_form(H, y, lam):
+    """Minimiser of eq. (1): (H^H H + lam I)^-1 H^H y (LAPACK)."""
+    A = H.conj().T @ H + lam * np.eye(H.shape[1])
+    return np.linalg.solve(A, H.conj().T @ y)
+
+
+CASES = [(12, 6, 0.1, 1), (40, 20, 1e-3, 2), (64, 32, 1.0, 3), (33, 17, 0.1, 4), (30, 10, 0.0, 5)]
+
+
+@pytest.mark.parametrize("B,U,lam,seed", CASES)
+def test_converges_to_closed_form_of_eq1(orc, B, U, lam, seed):
+    inst = inputs.dense_uplink(B, U, seed)
+    ref = lmmse_closed_form(inst.H, inst.y, lam)
+    out = orc.local_cd(inst.H, inst.y, lam, T_max=5000, tol=1e-15)
+    err = np.linalg.norm(out["x"] - ref) / np.linalg.norm(ref)
+    assert err <= 1e-11, err
+    assert orc.normal_residual(inst.H, inst.y, lam, out["x"]) <= 1e-12
+
+
+@pytest.mark.parametrize("B,U,lam,seed", CASES[:4])
+def test_sweeps_equal_gauss_seidel_on_normal_equations(orc, B, U, lam, seed):
+    """CD with a running residual is Gauss-Seidel on (H^H H + lam I) x = H^H y, x0 = 0."""
+    inst = inputs.dense_uplink(B, U, seed)
+    H, y = inst.H, inst.y
+    A = H.conj().T @ H + lam * np.eye(U)
+    b = H.conj().T @ y
+    T = 6
+    out = orc.local_cd(H, y, lam, T_max=T, trace=True)
+    x = np.zeros(U, complex)
+    for t in range(T):
+        for u in range(U):
+            s = b[u] - A[u, :] @ x + A[u, u] * x[u]
+            x[u] = s / A[u, u]
+        got = out["sweep_x"][t]
+        assert np.linalg.norm(got - x) <= 1e-12 * max(1.0, np.linalg.norm(x)), (t, np.linalg.norm(got - x))
+
+
+def test_per_step_invariants(orc):
+    """After every coordinate step: r = y - H x; h_u^H r = lam x_u (exact coordinate
+    minimisation of eq. (1)); the objective of eq. (1) never increases."""
+    B, U, lam = 24, 10, 0.3
+    inst = inputs.dense_uplink(B, U, 11)
+    H, y = inst.H, inst.y
+    T = 4
+    out = orc.local_cd(H, y, lam, T_max=T, trace=True)
+
+    def f(x):
+        return np.linalg.norm(y - H @ x) ** 2 + lam * np.linalg.norm(x) ** 2
+
+    prev = f(np.zeros(U))
+    for t in range(T):
+        for u in range(U):
+            x = out["step_x"][t, u]
+            r = out["step_r"][t, u]
+            assert np.linalg.norm(r - (y - H @ x)) <= 1e-13 * np.linalg.norm(y)
+            assert abs(H[:, u].conj() @ r - lam * x[u]) <= 1e-13
+            cur = f(x)
+            assert cur <= prev * (1 + 1e-14) + 1e-15
+            prev = cur
+
+
+def test_single_user_is_exact_after_one_step(orc):
+    rng = np.random.default_rng(3)
+    h = crandn(rng, 16, 1)
+    y = crandn(rng, 16)
+    lam = 0.25
+    out = orc.local_cd(h, y, lam, T_max=1)
+    want = (h[:, 0].conj() @ y) / (np.linalg.norm(h) ** 2 + lam)
+    assert abs(out["x"][0] - want) <= 1e-15 * abs(want) + 1e-16
+
+
+def test_orthogonal_columns_exact_after_one_sweep(orc):
+    rng = np.random.default_rng(4)
+    Q, _ = np.linalg.qr(crandn(rng, 20, 7))
+    H = Q * np.array([0.5, 1.0, 2.0, 0.7, 1.3, 3.0, 0.2])
+    y = crandn(rng, 20)
+    lam = 0.1
+    out = orc.local_cd(H, y, lam, T_max=1)
+    ref = lmmse_closed_form(H, y, lam)
+    assert np.linalg.norm(out["x"] - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+def test_zero_receive_vector_gives_zero(orc):
+    inst = inputs.dense_uplink(10, 5, 0)
+    out = orc.local_cd(inst.H, np.zeros(10), 0.1, T_max=3)
+    assert np.all(out["x"] == 0)
+
+
+def test_warm_start_at_the_solution_stays(orc):
+    inst = inputs.dense_uplink(30, 12, 8)
+    ref = lmmse_closed_form(inst.H, inst.y, 0.1)
+    out = orc.local_cd(inst.H, inst.y, 0.1, T_max=2, x0=ref)
+    assert np.linalg.norm(out["x"] - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_zero_column_is_inactive_and_flagged(orc):
+    inst = inputs.dense_uplink(12, 6, 9)
+    H = np.array(inst.H)
+    H[:, 2] = 0
+    out = orc.local_cd(H, inst.y, 0.1, T_max=50, tol=1e-14)
+    assert out["x"][2] == 0
+    ref = lmmse_closed_form(H, inst.y, 0.1)
+    assert np.linalg.norm(out["x"] - ref) <= 1e-11 * np.linalg.norm(ref)
+    # lambda = 0 makes the coordinate undefined: the oracle skips it and flags it
+    out0 = orc.local_cd(H, inst.y, 0.0, T_max=3)
+    assert out0["flags"] & orc.FLAG_ZERO_COLUMN
+    assert out0["x"][2] == 0 and np.all(np.isfinite(out0["x"]))
+
+
+def test_error_contracts_at_the_gauss_seidel_rate(orc):
+    """The asymptotic error ratio equals the spectral radius of -(D+L)^-1 L^H,
+    the Gauss-Seidel iteration matrix of the normal equations."""
+    B, U, lam = 24, 12, 0.05
+    inst = inputs.dense_uplink(B, U, 21)
+    H, y = inst.H, inst.y
+    A = H.conj().T @ H + lam * np.eye(U)
+    DL = np.tril(A)
+    G = -np.linalg.solve(DL, np.triu(A, 1))
+    rho = max(abs(np.linalg.eigvals(G)))
+    ref = lmmse_closed_form(H, y, lam)
+    T = 60
+    out = orc.local_cd(H, y, lam, T_max=T, trace=True)
+    err = np.array([np.linalg.norm(out["sweep_x"][t] - ref) for t in range(T)])
+    k0, k1 = 30, 50
+    obs = (err[k1] / err[k0]) ** (1.0 / (k1 - k0))
+    assert abs(obs - rho) <= 0.03 * rho, (obs, rho)
+
+
+def test_exact_rational_brute_force_two_sweeps(orc):
+    """Gaussian-integer H, y and lambda = 1/2: Gauss-Seidel on the normal equations in
+    exact rational arithmetic (Fractions), compared with the FP64 oracle."""
+    from fractions import Fraction as Fr
+    rng = np.random.default_rng(5)
+    B, U = 5, 3
+    Hr = rng.integers(-3, 4, size=(B, U))
+    Hi = rng.integers(-3, 4, size=(B, U))
+    yr = rng.integers(-3, 4, size=B)
+    yi = rng.integers(-3, 4, size=B)
+    lam = Fr(1, 2)
+
+    def cmul(a, b):
+        return (a[0] * b[0] - a[1] * b[1], a[0] * b[1] + a[1] * b[0])
+
+    def conj(a):
+        return (a[0], -a[1])
+
+    Hc = [[(Fr(int(Hr[i, u])), Fr(int(Hi[i, u]))) for u in range(U)] for i in range(B)]
+    yc = [(Fr(int(yr[i])), Fr(int(yi[i]))) for i in range(B)]
+    A = [[None] * U for _ in range(U)]
+    for u in range(U):
+        for v in range(U):
+            s = (Fr(0), Fr(0))
+            for i in range(B):
+                p = cmul(conj(Hc[i][u]), Hc[i][v])
+                s = (s[0] + p[0], s[1] + p[1])
+            if u == v:
+                s = (s[0] + lam, s[1])
+            A[u][v] = s
+    b = []
+    for u in range(U):
+        s = (Fr(0), Fr(0))
+        for i in range(B):
+            p = cmul(conj(Hc[i][u]), yc[i])
+            s = (s[0] + p[0], s[1] + p[1])
+        b.append(s)
+    x = [(Fr(0), Fr(0)) for _ in range(U)]
+    for _ in range(2):
+        for u in range(U):
+            s = b[u]
+            for v in range(U):
+                if v != u:
+                    p = cmul(A[u][v], x[v])
+                    s = (s[0] - p[0], s[1] - p[1])
+            d = A[u][u][0]
+            x[u] = (s[0] / d, s[1] / d)
+    exact = np.array([float(a) + 1j * float(c) for a, c in x])
+    H = Hr + 1j * Hi
+    y = yr + 1j * yi
+    out = orc.local_cd(H.astype(complex), y.astype(complex), 0.5, T_max=2)
+    assert np.linalg.norm(out["x"] - exact) <= 1e-13 * np.linalg.norm(exact)
+
+
+def test_fusion_single_cluster_is_centralised_and_weights_sum_to_one(orc):
+    inst = inputs.dense_uplink(32, 8, 12)
+    one = orc.uplink_cd(inst.H, inst.y, N0=0.1, Ex=1.0, T_max=3, C_clusters=1)
+    loc = orc.local_cd(inst.H, inst.y, 0.1, T_max=3)
+    assert np.array_equal(one["x"], loc["x"])
+    four = orc.uplink_cd(inst.H, inst.y, N0=0.1, Ex=1.0, T_max=3, C_clusters=4)
+    assert abs(four["weights"].sum() - 1.0) <= 1e-15
+    # identical clusters get identical weights 1/C and the fused estimate is their mean
+    H4 = np.vstack([inst.H[:8]] * 4)
+    y4 = np.concatenate([inst.y[:8]] * 4)
+    same = orc.uplink_cd(H4, y4, N0=0.1, Ex=1.0, T_max=3, C_clusters=4)
+    assert np.allclose(same["weights"], 0.25, rtol=0, atol=1e-15)
+    assert np.allclose(same["x"], same["x_local"][0], rtol=1e-14, atol=0)
+    # each local estimate equals CD on its own row block
+    for c in range(4):
+        lc = orc.local_cd(inst.H[8 * c:8 * c + 8], inst.y[8 * c:8 * c + 8], 0.1, T_max=3)
+        assert np.array_equal(four["x_local"][c], lc["x"])
+
+
+# ----------------------------------------------------------------------------- downlink (Alg. 2)
+
+def zf_closed_form(H, s):
+    """eq. (2) with the downlink channel Hdl = H^H: x = Hdl^H (Hdl Hdl^H)^-1 s = H (H^H H)^-1 s."""
+    return H @ np.linalg.solve(H.conj().T @ H, s)
+
+
+def test_zf_converges_to_closed_form_of_eq2(orc):
+    rng = np.random.default_rng(6)
+    B, U = 32, 8
+    H = crandn(rng, B, U)
+    s = crandn(rng, U)
+    out = orc.local_zf_cd(H, s, T_max=4000, tol=1e-15)
+    ref = zf_closed_form(H, s)
+    assert np.linalg.norm(out["x"] - ref) <= 1e-11 * np.linalg.norm(ref)
+    assert np.linalg.norm(H.conj().T @ out["x"] - s) <= 1e-11 * np.linalg.norm(s)
+
+
+def test_zf_step_invariants_and_range(orc):
+    """After step u: hbar_u^H x = sbar_u (row u of the scaled constraint holds); x stays in
+    range(H) (x = Hbar^H z of eq. (3))."""
+    rng = np.random.default_rng(7)
+    B, U = 20, 6
+    H = crandn(rng, B, U)
+    s = crandn(rng, U)
+    out = orc.local_zf_cd(H, s, T_max=3, trace=True)
+    nrm = np.linalg.norm(H, axis=0)
+    P = H @ np.linalg.pinv(H)            # projector onto range(H)
+    for t in range(3):
+        for u in range(U):
+            x = out["step_x"][t, u]
+            assert abs(H[:, u].conj() @ x / nrm[u] - s[u] / nrm[u]) <= 1e-13
+            assert np.linalg.norm(P @ x - x) <= 1e-12 * max(1, np.linalg.norm(x))
+
+
+def test_zf_sweeps_equal_gauss_seidel_on_dual(orc):
+    """Eq. (3): CD on z with x = Hbar^H z is Gauss-Seidel on (Hbar Hbar^H) z = sbar (unit
+    diagonal); the primal iterate x = Hbar^H z after each sweep must match."""
+    rng = np.random.default_rng(8)
+    B, U = 24, 6
+    H = crandn(rng, B, U)
+    s = crandn(rng, U)
+    nrm = np.linalg.norm(H, axis=0)
+    Hbar_dl = (H / nrm).conj().T            # U x B, rows hbar_u^H
+    sbar = s / nrm
+    A = Hbar_dl @ Hbar_dl.conj().T
+    T = 5
+    out = orc.local_zf_cd(H, s, T_max=T, trace=True)
+    z = np.zeros(U, complex)
+    for t in range(T):
+        for u in range(U):
+            z[u] = (sbar[u] - A[u, :] @ z + A[u, u] * z[u]) / A[u, u]
+        x = Hbar_dl.conj().T @ z
+        assert np.linalg.norm(out["sweep_x"][t] - x) <= 1e-12 * np.linalg.norm(x)
+
+
+def test_zf_power_scaling_and_stacking(orc):
+    rng = np.random.default_rng(9)
+    B, U, C = 64, 8, 4
+    H = crandn(rng, B, U)
+    s = crandn(rng, U)
+    rho = 2.0
+    out = orc.downlink_cd(H, s, rho, T_max=3, C_clusters=C)
+    for c in range(C):
+        xc = out["x"][16 * c:16 * c + 16]
+        assert abs(np.linalg.norm(xc) - rho / np.sqrt(C)) <= 1e-14
+        loc = orc.local_zf_cd(H[16 * c:16 * c + 16], s, T_max=3)
+        assert np.allclose(xc, rho / np.sqrt(C) * loc["x"] / np.linalg.norm(loc["x"]), rtol=1e-14, atol=0)
+    assert abs(np.linalg.norm(out["x"]) - rho) <= 1e-13
+
+
+# ----------------------------------------------------------------------------- sparse
+
+def test_csr_to_csc_matches_scipy(orc):
+    import scipy.sparse as sp
+    ins = inputs.sparse_uplink(300, 140, 0.05, seed=3)
+    colptr, rowidx, cval = orc.csr_to_csc(ins.B, ins.U, ins.rowptr, ins.colidx, ins.val)
+    ref = sp.csr_matrix((ins.val, ins.colidx, ins.rowptr), shape=(ins.B, ins.U)).tocsc()
+    ref.sort_indices()
+    assert np.array_equal(colptr, ref.indptr.astype(np.int32))
+    assert np.array_equal(rowidx, ref.indices.astype(np.int32))
+    assert np.array_equal(cval, ref.data)
+
+
+def test_sparse_cd_equals_dense_cd_on_the_densified_matrix(orc):
+    ins = inputs.sparse_uplink(200, 90, 0.05, seed=4)
+    colptr, rowidx, cval = orc.csr_to_csc(ins.B, ins.U, ins.rowptr, ins.colidx, ins.val)
+    sp_out = orc.local_cd_csc(ins.B, ins.U, colptr, rowidx, cval, ins.y, 0.1, T_max=7)
+    de_out = orc.local_cd(ins.dense(), ins.y, 0.1, T_max=7)
+    assert np.array_equal(sp_out["x"], de_out["x"])
+
+
+# ----------------------------------------------------------------------------- stop rule, residual
+
+def test_tolerance_stop_rule(orc):
+    inst = inputs.dense_uplink(64, 32, 13)
+    tol = 1e-6
+    out = orc.local_cd(inst.H, inst.y, 0.1, T_max=200, tol=tol, trace=True)
+    T = out["sweeps"]
+    S = out["sweep_s"]
+    X = np.array([np.linalg.norm(out["sweep_x"][t]) ** 2 for t in range(T)])
+    assert np.sqrt(S[T - 1]) <= tol * np.sqrt(X[T - 1])
+    assert np.all(np.sqrt(S[:T - 1]) > tol * np.sqrt(X[:T - 1]))
+    assert abs(out["rel_step"] - np.sqrt(S[T - 1] / X[T - 1])) <= 1e-15
+    assert out["flags"] == 0
+    capped = orc.local_cd(inst.H, inst.y, 0.1, T_max=3, tol=1e-12)
+    assert capped["sweeps"] == 3 and capped["flags"] & orc.FLAG_NOT_CONVERGED
+
+
+def test_normal_residual_definition(orc):
+    inst = inputs.dense_uplink(40, 16, 14)
+    ref = lmmse_closed_form(inst.H, inst.y, 0.1)
+    assert orc.normal_residual(inst.H, inst.y, 0.1, ref) <= 1e-14
+    assert abs(orc.normal_residual(inst.H, inst.y, 0.1, np.zeros(16)) - 1.0) <= 1e-15
+
+
+def test_column_scalars(orc):
+    inst = inputs.dense_uplink(40, 16, 15)
+    e, m, n = orc.column_scalars(inst.H, 0.2)
+    assert np.allclose(e, np.linalg.norm(inst.H, axis=0) ** 2, rtol=1e-14)
+    assert np.allclose(m * (e + 0.2), 1.0, rtol=1e-15)
+    assert np.allclose(n, e / (e + 0.2), rtol=1e-15)
