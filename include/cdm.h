@@ -1,0 +1,191 @@
+/*
+ * cdm.h -- C ABI of the MI355X (gfx950) coordinate-descent MU-MIMO library.
+ *
+ * The library runs the coordinate-descent (CD) detector of Algorithm 1 and the CD
+ * precoder of Algorithm 2 of K. Li, O. Castaneda, C. Jeon, J. R. Cavallaro and
+ * C. Studer, "Decentralized Coordinate-Descent Data Detection and Precoding for
+ * Massive MU-MIMO" (arXiv 1902.08653), entirely in hand-written HIP kernels.
+ *
+ * General rules
+ *   - Every entry point returns a cdm_status (0 = CDM_OK, negative = error) and
+ *     never throws, aborts or exits.
+ *   - Pointers named "device" are HIP device pointers the caller owns; the library
+ *     never frees them.  Pointers named "host" are ordinary host memory.
+ *   - Complex values are interleaved (re, im): CDM_C128 = two doubles (16 B),
+ *     CDM_C64 = two floats (8 B).
+ *   - The channel H is always passed in the uplink orientation of Sec. II-A:
+ *     B x U (B antennas = rows, U users = columns), column-major with leading
+ *     dimension ldh >= B, so user column h_u is contiguous.  The downlink channel
+ *     of Sec. II-B is its conjugate transpose (reciprocity), so the same storage
+ *     serves Algorithm 2.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Solves are
+ *     asynchronous: they enqueue work and return; results and the cdm_info records
+ *     are valid once the stream has been synchronised.  A plan owns its device
+ *     workspace; concurrent solves on one plan race -- use one plan per stream.
+ *   - Data-dependent conditions (a zero column, NaN/Inf, no convergence within
+ *     T_max) are reported as bits in cdm_info.flags, not as errors.
+ */
+#ifndef CDM_H
+#define CDM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CDM_ABI_VERSION 1
+
+typedef enum cdm_status {
+    CDM_OK = 0,
+    CDM_EINVAL = -1,        /* NULL pointer or out-of-range scalar argument */
+    CDM_ESHAPE = -2,        /* inconsistent sizes (B, U, C, ldh, nnz, batch) */
+    CDM_EDTYPE = -3,        /* precision / problem / layout combination not supported */
+    CDM_ENOMEM = -4,        /* device workspace allocation failed */
+    CDM_EHIP = -5,          /* a HIP runtime call failed (message via cdm_last_error) */
+    CDM_EINFEASIBLE = -6,   /* lambda = 0 with B_c < U (eq. (1) not strictly convex), or
+                               a downlink cluster with B_c < U (eq. (2) infeasible) */
+    CDM_ENOTIMPL = -7,      /* valid request that this build does not implement */
+    CDM_ENODEV = -8         /* no gfx950 device is current */
+} cdm_status;
+
+/* Problem: Algorithm 1 (uplink L-MMSE detection, eq. (1)) or Algorithm 2 (downlink
+ * ZF precoding, eq. (2)-(4)). */
+typedef enum cdm_problem { CDM_UPLINK_LMMSE = 0, CDM_DOWNLINK_ZF = 1 } cdm_problem;
+
+/* Arithmetic of the sweep.  CDM_MIXED_* keep H, y and x in FP64 (C128 storage)
+ * and run the inner operator products from BF16 or FP8-e4m3 copies of H with an
+ * FP64 residual refinement outside (see cdm_solve). */
+typedef enum cdm_precision {
+    CDM_C128 = 0, CDM_C64 = 1, CDM_MIXED_BF16 = 2, CDM_MIXED_FP8 = 3
+} cdm_precision;
+
+typedef enum cdm_layout { CDM_DENSE = 0, CDM_CSR = 1 } cdm_layout;
+
+/* Engine selection: AUTO lets the plan choose from the shape.
+ * WG    - one workgroup per instance (cluster), residual held in registers.
+ * PANEL - one cooperative launch over all CUs for one large instance; columns are
+ *         processed in panels of `panel` users whose coupling is resolved exactly
+ *         (block form of the cyclic sweep, identical to U sequential updates). */
+typedef enum cdm_engine { CDM_ENGINE_AUTO = 0, CDM_ENGINE_WG = 1, CDM_ENGINE_PANEL = 2 } cdm_engine;
+
+/* Option bits for cdm_desc.flags. */
+#define CDM_F_RESIDUAL 1    /* also compute the FP64 normal-equation residual into cdm_info.resid */
+
+typedef struct cdm_desc {
+    int32_t problem;     /* cdm_problem */
+    int32_t precision;   /* cdm_precision */
+    int32_t layout;      /* cdm_layout */
+    int32_t engine;      /* cdm_engine */
+    int32_t B;           /* antennas = rows of H (sum of the cluster sizes), >= 1 */
+    int32_t U;           /* users = columns of H, >= 1 */
+    int32_t C;           /* antenna clusters (Sec. II-A), >= 1, B % C == 0; cluster c owns
+                            rows [c*B/C, (c+1)*B/C) */
+    int32_t T_max;       /* sweep cap T_max of Algorithms 1 and 2, 1..100000 */
+    double tol;          /* 0: run exactly T_max sweeps (the paper's mode); > 0: stop after
+                            sweep t once sqrt(sum_u |delta_u|^2) <= tol * ||x^(t)||_2 */
+    int64_t nnz;         /* CDM_CSR: number of stored entries of H (capacity), else 0 */
+    int32_t panel;       /* CDM_ENGINE_PANEL panel width (64 or 128); 0 = choose */
+    int32_t flags;       /* CDM_F_* */
+} cdm_desc;
+
+/* Per-instance (per-cluster) result record written to device memory by a solve.
+ * flags bits: */
+#define CDM_INFO_ZERO_COLUMN   1   /* ||h_u||^2 + lambda == 0 for some u: coordinate kept inactive */
+#define CDM_INFO_NONFINITE     2   /* the returned x holds NaN or Inf */
+#define CDM_INFO_NOT_CONVERGED 4   /* tol > 0 and T_max sweeps ran without meeting it */
+#define CDM_INFO_TIMEOUT       8   /* a cross-workgroup wait gave up (should never happen) */
+typedef struct cdm_info {
+    int32_t sweeps;      /* sweeps performed */
+    int32_t flags;       /* CDM_INFO_* */
+    double rel_step;     /* sqrt(sum_u |delta_u|^2) / ||x||_2 of the last sweep */
+    double resid;        /* ||H^H(y - Hx) - lambda x|| / ||H^H y|| in FP64 if CDM_F_RESIDUAL, else -1 */
+    double reserved;
+} cdm_info;              /* 32 bytes */
+
+typedef struct cdm_plan cdm_plan;
+
+/* ABI version of the loaded library (CDM_ABI_VERSION). */
+int32_t cdm_version(void);
+
+/* Static text for a status code. */
+const char* cdm_status_string(int32_t status);
+
+/* Text of the last HIP error seen by this thread (empty if none). */
+const char* cdm_last_error(void);
+
+/* Create a plan for single solves of the shape in *desc on the current device.
+ * Validates the descriptor, picks the engine and tiles, and allocates the whole
+ * device workspace, so that cdm_solve itself never allocates.
+ * Errors: CDM_EINVAL, CDM_ESHAPE, CDM_EDTYPE, CDM_EINFEASIBLE (downlink with
+ * B/C < U), CDM_ENOMEM, CDM_ENODEV.  *plan is set to NULL on error. */
+int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan);
+
+/* Solve one instance (Algorithm 1 or 2, Sec. III / Sec. IV).
+ *  H      device, CDM_DENSE: B x U column-major, leading dimension ldh >= B;
+ *         CDM_CSR: the nnz stored values in CSR order (rows = antennas)
+ *  ldh    CDM_DENSE: leading dimension in elements; CDM_CSR: ignored
+ *  rowptr device int32[B+1] (CDM_CSR only, else NULL)
+ *  colidx device int32[nnz], column indices strictly increasing within each row
+ *         (CDM_CSR only, else NULL)
+ *  rhs    device, uplink: y (B complex); downlink: s (U complex)
+ *  N0, Ex uplink: lambda = N0/Ex >= 0 regularises eq. (1) (Algorithm 1 input);
+ *         lambda == 0 requires B/C >= U
+ *  rho    downlink: total power constraint rho (each cluster scales to
+ *         rho/sqrt(C), Sec. IV-B); rho <= 0 skips the scaling
+ *  x0     device, optional warm start (U complex, uplink only), NULL = x^(0) = 0
+ *  x      device output; uplink: the fused estimate x_hat (U complex);
+ *         downlink: the stacked precoded vector [x_1; ...; x_C] (B complex)
+ *  info   device cdm_info[C] (one record per cluster)
+ *  stream hipStream_t
+ * Mixed precisions run the outer FP64 refinement loop: residual r = y - H x in
+ * FP64, inner CD sweeps on the correction problem from the low-precision copy of
+ * H, x += d, until ||d|| <= tol ||x|| (tol > 0 required) or T_max outer steps.
+ * Errors: CDM_EINVAL (NULL pointer, lambda < 0), CDM_ESHAPE (ldh < B),
+ * CDM_EINFEASIBLE, CDM_EHIP. */
+int32_t cdm_solve(cdm_plan* plan, const void* H, int64_t ldh, const int32_t* rowptr,
+                  const int32_t* colidx, const void* rhs, double N0, double Ex, double rho,
+                  const void* x0, void* x, void* info, void* stream);
+
+/* Create a plan for a batch of independent uplink instances of uneven size
+ * (Algorithm 1 with C = 1 per instance).  m, n: host int32[batch], rows (antennas)
+ * and columns (users) of each instance, 1 <= n, 1 <= m <= 16384.  Packing rule for
+ * the solve: instance i's H is m_i x n_i column-major with ld = m_i starting at
+ * element offset H_off[i] = sum_{k<i} m_k n_k of the packed H buffer; y_i starts at
+ * y_off[i] = sum_{k<i} m_k and x_i at x_off[i] = sum_{k<i} n_k.  The plan fixes the
+ * launch schedule (largest instances first) and the tiles per size bucket.
+ * desc->precision: CDM_C128 or CDM_C64; desc->T_max, tol as in cdm_desc. */
+int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m,
+                           const int32_t* n, cdm_plan** plan);
+
+/* The packing offsets of a batched plan (host int64[batch] each; any may be NULL). */
+int32_t cdm_batched_offsets(const cdm_plan* plan, int64_t* H_off, int64_t* y_off,
+                            int64_t* x_off);
+
+/* Solve every instance of a batched plan in one persistent launch.
+ *  H, y   device, packed as described at cdm_create_batched
+ *  x0     device optional packed warm starts (NULL = zero)
+ *  x      device packed outputs; info device cdm_info[batch].
+ * Enqueues kernels only (no allocation, no host synchronisation), so it may be
+ * captured into a HIP graph. */
+int32_t cdm_solve_batched(cdm_plan* plan, const void* H, const void* y, double N0, double Ex,
+                          const void* x0, void* x, void* info, void* stream);
+
+/* FP64 stationarity check of eq. (1) for a dense uplink plan:
+ * *out (device double) = ||H^H (y - H x) - lambda x|| / ||H^H y||, lambda = N0/Ex.
+ * Uses the plan's workspace; same argument conventions as cdm_solve. */
+int32_t cdm_residual(cdm_plan* plan, const void* H, int64_t ldh, const void* y, double N0,
+                     double Ex, const void* x, double* out, void* stream);
+
+/* Human-readable description of the plan's engine, tiles and workspace
+ * (NUL-terminated, truncated to len bytes). */
+int32_t cdm_plan_describe(const cdm_plan* plan, char* buf, int32_t len);
+
+/* Release the plan and its device workspace. NULL is accepted. */
+int32_t cdm_destroy(cdm_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDM_H */

@@ -1,0 +1,224 @@
+"""Thin Python binding of the C ABI in ``include/cdm.h`` (argument marshalling only).
+
+Every step of the solve runs in the gfx950 kernels of ``libcdm.so``.  PyTorch is
+used only to own device memory and to name the stream.  If the library is
+missing this module raises on use; there is no fallback of any kind.
+
+Channel layout: a B x U channel H is passed as a tensor ``Hc`` of shape (U, ld)
+(contiguous): row u of ``Hc`` is user column h_u (column-major H, ld >= B).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcdm.so")
+
+UPLINK_LMMSE, DOWNLINK_ZF = 0, 1
+C128, C64, MIXED_BF16, MIXED_FP8 = 0, 1, 2, 3
+DENSE, CSR = 0, 1
+ENGINE_AUTO, ENGINE_WG, ENGINE_PANEL = 0, 1, 2
+F_RESIDUAL = 1
+
+INFO_ZERO_COLUMN, INFO_NONFINITE, INFO_NOT_CONVERGED, INFO_TIMEOUT = 1, 2, 4, 8
+
+_PREC = {"c128": C128, "c64": C64, "bf16": MIXED_BF16, "fp8": MIXED_FP8}
+_ENGINE = {"auto": ENGINE_AUTO, "wg": ENGINE_WG, "panel": ENGINE_PANEL}
+
+
+class CdmError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        msg = lib().cdm_status_string(status).decode()
+        extra = lib().cdm_last_error().decode()
+        super().__init__("%s: %s (%d)%s" % (where, msg, status, (" -- " + extra) if extra else ""))
+
+
+class Desc(C.Structure):
+    _fields_ = [("problem", C.c_int32), ("precision", C.c_int32), ("layout", C.c_int32),
+                ("engine", C.c_int32), ("B", C.c_int32), ("U", C.c_int32), ("C", C.c_int32),
+                ("T_max", C.c_int32), ("tol", C.c_double), ("nnz", C.c_int64),
+                ("panel", C.c_int32), ("flags", C.c_int32)]
+
+
+INFO_DTYPE = np.dtype([("sweeps", np.int32), ("flags", np.int32), ("rel_step", np.float64),
+                       ("resid", np.float64), ("reserved", np.float64)])
+assert INFO_DTYPE.itemsize == 32
+
+EXPORTS = ["cdm_version", "cdm_status_string", "cdm_last_error", "cdm_create", "cdm_solve",
+           "cdm_create_batched", "cdm_batched_offsets", "cdm_solve_batched", "cdm_residual",
+           "cdm_plan_describe", "cdm_destroy"]
+
+_lib = None
+
+
+def lib():
+    """Load libcdm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcdm.so is not built (run __graft_entry__.build()); "
+                               "there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.cdm_version.restype = i32
+        L.cdm_status_string.argtypes = [i32]
+        L.cdm_status_string.restype = C.c_char_p
+        L.cdm_last_error.restype = C.c_char_p
+        L.cdm_create.argtypes = [C.POINTER(Desc), C.POINTER(P)]
+        L.cdm_create.restype = i32
+        L.cdm_solve.argtypes = [P, P, i64, P, P, P, f64, f64, f64, P, P, P, P]
+        L.cdm_solve.restype = i32
+        L.cdm_create_batched.argtypes = [C.POINTER(Desc), i32, P, P, C.POINTER(P)]
+        L.cdm_create_batched.restype = i32
+        L.cdm_batched_offsets.argtypes = [P, P, P, P]
+        L.cdm_batched_offsets.restype = i32
+        L.cdm_solve_batched.argtypes = [P, P, P, f64, f64, P, P, P, P]
+        L.cdm_solve_batched.restype = i32
+        L.cdm_residual.argtypes = [P, P, i64, P, f64, f64, P, P, P]
+        L.cdm_residual.restype = i32
+        L.cdm_plan_describe.argtypes = [P, C.c_char_p, i32]
+        L.cdm_plan_describe.restype = i32
+        L.cdm_destroy.argtypes = [P]
+        L.cdm_destroy.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(st, where):
+    if st != 0:
+        raise CdmError(st, where)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def parse_info(info_tensor):
+    """Device cdm_info records (uint8 tensor) -> structured NumPy array."""
+    raw = info_tensor.detach().cpu().numpy().tobytes()
+    return np.frombuffer(raw, dtype=INFO_DTYPE).copy()
+
+
+def _cdtype(precision):
+    import torch
+    return torch.complex128 if precision in ("c128", "bf16", "fp8") else torch.complex64
+
+
+class Plan:
+    """A plan for single solves (``cdm_create`` / ``cdm_solve`` / ``cdm_destroy``)."""
+
+    def __init__(self, B, U, C_clusters=1, precision="c128", T_max=200, tol=0.0, engine="auto",
+                 panel=0, residual=False, problem="uplink", layout="dense", nnz=0):
+        self.B, self.U, self.C = int(B), int(U), int(C_clusters)
+        self.precision = precision
+        self.problem = problem
+        d = Desc(problem=UPLINK_LMMSE if problem == "uplink" else DOWNLINK_ZF,
+                 precision=_PREC[precision], layout=DENSE if layout == "dense" else CSR,
+                 engine=_ENGINE[engine], B=self.B, U=self.U, C=self.C, T_max=int(T_max),
+                 tol=float(tol), nnz=int(nnz), panel=int(panel),
+                 flags=F_RESIDUAL if residual else 0)
+        self.desc = d
+        h = C.c_void_p()
+        _check(lib().cdm_create(C.byref(d), C.byref(h)), "cdm_create")
+        self._h = h
+
+    def describe(self):
+        buf = C.create_string_buffer(1024)
+        _check(lib().cdm_plan_describe(self._h, buf, 1024), "cdm_plan_describe")
+        return buf.value.decode()
+
+    def solve(self, Hc, rhs, N0=0.1, Ex=1.0, rho=0.0, x0=None, x=None, info=None, stream=None,
+              rowptr=None, colidx=None):
+        """Enqueue one solve.  Returns (x, info) device tensors; call parse_info(info)
+        after synchronising to read the records."""
+        import torch
+        dev = rhs.device
+        ldh = Hc.shape[1] if Hc.dim() == 2 else 0
+        if x is None:
+            n_out = self.U if self.problem == "uplink" else self.B
+            x = torch.empty(n_out, dtype=rhs.dtype, device=dev)
+        if info is None:
+            info = torch.empty(32 * self.C, dtype=torch.uint8, device=dev)
+        st = lib().cdm_solve(self._h, _ptr(Hc), int(ldh), _ptr(rowptr), _ptr(colidx), _ptr(rhs),
+                             float(N0), float(Ex), float(rho), _ptr(x0), _ptr(x), _ptr(info),
+                             _stream(stream))
+        _check(st, "cdm_solve")
+        return x, info
+
+    def residual(self, Hc, y, x, N0=0.1, Ex=1.0, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=y.device)
+        _check(lib().cdm_residual(self._h, _ptr(Hc), int(Hc.shape[1]), _ptr(y), float(N0), float(Ex),
+                                  _ptr(x), _ptr(out), _stream(stream)), "cdm_residual")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cdm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchedPlan:
+    """A plan for many independent uplink instances of uneven size."""
+
+    def __init__(self, m, n, precision="c64", T_max=200, tol=0.0):
+        m = np.ascontiguousarray(m, dtype=np.int32)
+        n = np.ascontiguousarray(n, dtype=np.int32)
+        self.batch = int(m.shape[0])
+        self.m, self.n = m, n
+        self.precision = precision
+        d = Desc(problem=UPLINK_LMMSE, precision=_PREC[precision], layout=DENSE, engine=ENGINE_WG,
+                 B=int(m.max()), U=int(n.max()), C=1, T_max=int(T_max), tol=float(tol), nnz=0,
+                 panel=0, flags=0)
+        h = C.c_void_p()
+        _check(lib().cdm_create_batched(C.byref(d), self.batch, m.ctypes.data, n.ctypes.data,
+                                        C.byref(h)), "cdm_create_batched")
+        self._h = h
+        self.H_off = np.zeros(self.batch, np.int64)
+        self.y_off = np.zeros(self.batch, np.int64)
+        self.x_off = np.zeros(self.batch, np.int64)
+        _check(lib().cdm_batched_offsets(h, self.H_off.ctypes.data, self.y_off.ctypes.data,
+                                         self.x_off.ctypes.data), "cdm_batched_offsets")
+
+    def describe(self):
+        buf = C.create_string_buffer(1024)
+        _check(lib().cdm_plan_describe(self._h, buf, 1024), "cdm_plan_describe")
+        return buf.value.decode()
+
+    def solve(self, H, y, N0=0.1, Ex=1.0, x0=None, x=None, info=None, stream=None):
+        import torch
+        if x is None:
+            x = torch.empty(int(self.n.astype(np.int64).sum()), dtype=y.dtype, device=y.device)
+        if info is None:
+            info = torch.empty(32 * self.batch, dtype=torch.uint8, device=y.device)
+        _check(lib().cdm_solve_batched(self._h, _ptr(H), _ptr(y), float(N0), float(Ex), _ptr(x0),
+                                       _ptr(x), _ptr(info), _stream(stream)), "cdm_solve_batched")
+        return x, info
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cdm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,120 @@
+// common.hpp -- device-side building blocks shared by the gfx950 kernels:
+// interleaved complex arithmetic, wave64 reductions, cross-workgroup counters.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cdm.h"
+
+namespace cdm {
+
+template <typename T> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+template <typename T> using cv = typename cvec<T>::type;
+
+template <typename T> __device__ __forceinline__ cv<T> czero() { cv<T> z; z.x = T(0); z.y = T(0); return z; }
+template <typename T> __device__ __forceinline__ cv<T> cmake(T re, T im) { cv<T> z; z.x = re; z.y = im; return z; }
+
+// a * b
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+    V z; z.x = a.x * b.x - a.y * b.y; z.y = a.x * b.y + a.y * b.x; return z;
+}
+// acc += conj(a) * b
+template <typename V> __device__ __forceinline__ void cfma_conj(V& acc, V a, V b) {
+    acc.x += a.x * b.x + a.y * b.y;
+    acc.y += a.x * b.y - a.y * b.x;
+}
+// acc -= a * b
+template <typename V> __device__ __forceinline__ void cfms(V& acc, V a, V b) {
+    acc.x -= a.x * b.x - a.y * b.y;
+    acc.y -= a.x * b.y + a.y * b.x;
+}
+// acc += a * b
+template <typename V> __device__ __forceinline__ void cfma(V& acc, V a, V b) {
+    acc.x += a.x * b.x - a.y * b.y;
+    acc.y += a.x * b.y + a.y * b.x;
+}
+template <typename V> __device__ __forceinline__ double cabs2d(V a) {
+    return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+}
+
+// Butterfly all-reduce over the 64 lanes of a wave.  Every lane ends with the
+// same bits: at each level a lane adds its partner's partial to its own, and the
+// two partials of a pair are identical sets, so commutativity makes them equal.
+template <typename T> __device__ __forceinline__ T wave_allsum(T v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Transpose-reduce of NV per-lane values (NV a power of two, 1 <= NV <= 64) over
+// the 64 lanes.  On return v[0] of lane L holds the full 64-lane sum of value
+// index  c = L >> (6 - log2(NV)); all lanes with that high part hold equal bits.
+// Cost: NV - 1 + (6 - log2 NV) shuffles instead of 6 NV.
+template <typename T, int NV> __device__ __forceinline__ void wave_transpose_sum(T (&v)[NV], int lane) {
+    static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two <= 64");
+    int mask = 32;
+#pragma unroll
+    for (int lvl = 0; (1 << lvl) < NV; ++lvl) {
+        const int half = NV >> (lvl + 1);
+        const bool upper = (lane & mask) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            T send = upper ? v[i] : v[i + half];
+            T keep = upper ? v[i + half] : v[i];
+            v[i] = keep + __shfl_xor(send, mask, 64);
+        }
+        mask >>= 1;
+    }
+#pragma unroll
+    for (; mask >= 1; mask >>= 1) v[0] += __shfl_xor(v[0], mask, 64);
+}
+
+// ---- cross-workgroup counters (device-wide, agent scope) --------------------
+__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fence_release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// All threads of the workgroup: make this workgroup's prior global writes visible
+// device-wide, then thread 0 bumps *ctr.
+__device__ __forceinline__ void wg_arrive(uint32_t* ctr) {
+    fence_release_agent();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// All threads of the workgroup: wait until *ctr >= target.  Thread 0 polls with a
+// wall-clock bound; on time-out it raises *abort_flag, and any waiter that sees
+// the flag raised gives up too, so every wave of the grid reaches the kernel end.
+// Returns false when the wait was abandoned.  `flag_s` is one LDS word.
+__device__ __forceinline__ bool wg_wait_geq(const uint32_t* ctr, uint32_t target, uint32_t* abort_flag,
+                                            uint64_t timeout_ticks, uint32_t* flag_s) {
+    if (threadIdx.x == 0) {
+        uint32_t ok = 1;
+        if (ld_relaxed(ctr) < target) {
+            const uint64_t t0 = wall_clock64();
+            while (ld_relaxed(ctr) < target) {
+                if (ld_relaxed(abort_flag)) { ok = 0; break; }
+                if (wall_clock64() - t0 > timeout_ticks) {
+                    st_relaxed(abort_flag, 1u);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        *flag_s = ok;
+    }
+    __syncthreads();
+    fence_acquire_agent();
+    return *flag_s != 0;
+}
+
+}  // namespace cdm

@@ -1,0 +1,261 @@
+// k_aux.hip -- initial residual, FP64 normal-equation residual, small helpers.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace cdm {
+
+// ---- init: r0 = y - H x0 (warm) or y (cold); x = x0 or 0 -------------------
+template <typename T>
+__global__ void k_init_cold(const cv<T>* __restrict__ y, cv<T>* __restrict__ r0, int B, cv<T>* __restrict__ x,
+                            const cv<T>* __restrict__ x0, int U) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < B) r0[i] = y[i];
+    if (i < U) x[i] = x0 ? x0[i] : czero<T>();
+}
+
+// rpart[chunk][row] = sum_{u in chunk} H[row, u] x0[u]  (rows across threads: coalesced)
+template <typename T>
+__global__ void k_matvec_chunk(const cv<T>* __restrict__ H, int64_t ld, int B, int U, const cv<T>* __restrict__ xv,
+                               int cols_per_chunk, cv<T>* __restrict__ rpart) {
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int u0 = blockIdx.y * cols_per_chunk;
+    const int u1 = min(U, u0 + cols_per_chunk);
+    if (row >= B) return;
+    cv<T> acc = czero<T>();
+    for (int u = u0; u < u1; ++u) cfma(acc, H[(int64_t)u * ld + row], xv[u]);
+    rpart[(int64_t)blockIdx.y * B + row] = acc;
+}
+
+template <typename T>
+__global__ void k_init_warm_reduce(const cv<T>* __restrict__ y, const cv<T>* __restrict__ rpart, int nchunk, int B,
+                                   cv<T>* __restrict__ r0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B) return;
+    cv<T> s = y[i];
+    for (int c = 0; c < nchunk; ++c) {
+        const cv<T> p = rpart[(int64_t)c * B + i];
+        s.x -= p.x;
+        s.y -= p.y;
+    }
+    r0[i] = s;
+}
+
+template <typename T> static hipError_t launch_init_t(const InitLaunch& L, hipStream_t st) {
+    const int n = L.B > L.U ? L.B : L.U;
+    hipLaunchKernelGGL(k_init_cold<T>, dim3((n + 255) / 256), dim3(256), 0, st, (const cv<T>*)L.y, (cv<T>*)L.r0,
+                       L.B, (cv<T>*)L.x, (const cv<T>*)L.x0, L.U);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !L.x0) return e;
+    const int cpc = (L.U + L.nchunk - 1) / L.nchunk;
+    hipLaunchKernelGGL(k_matvec_chunk<T>, dim3((L.B + 255) / 256, L.nchunk), dim3(256), 0, st, (const cv<T>*)L.H,
+                       L.ld, L.B, L.U, (const cv<T>*)L.x0, cpc, (cv<T>*)L.rpart);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_init_warm_reduce<T>, dim3((L.B + 255) / 256), dim3(256), 0, st, (const cv<T>*)L.y,
+                       (const cv<T>*)L.rpart, L.nchunk, L.B, (cv<T>*)L.r0);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const InitLaunch& L, hipStream_t st) {
+    return L.c128 ? launch_init_t<double>(L, st) : launch_init_t<float>(L, st);
+}
+
+// ---- FP64 residual ||H^H (y - H x) - lambda x|| / ||H^H y|| -----------------
+template <typename T>
+__global__ void k_resid_rows(const cv<T>* __restrict__ H, int64_t ld, int B, int U, const cv<T>* __restrict__ x,
+                             int cols_per_chunk, double2* __restrict__ rpart) {
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int u0 = blockIdx.y * cols_per_chunk;
+    const int u1 = min(U, u0 + cols_per_chunk);
+    if (row >= B) return;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int u = u0; u < u1; ++u) {
+        const cv<T> h = H[(int64_t)u * ld + row];
+        const cv<T> xv = x[u];
+        const double hr = h.x, hi = h.y, xr = xv.x, xi = xv.y;
+        acc.x += hr * xr - hi * xi;
+        acc.y += hr * xi + hi * xr;
+    }
+    rpart[(int64_t)blockIdx.y * B + row] = acc;
+}
+
+template <typename T>
+__global__ void k_resid_r(const cv<T>* __restrict__ y, const double2* __restrict__ rpart, int nchunk, int B,
+                          double2* __restrict__ r) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B) return;
+    const cv<T> yv = y[i];
+    double2 s = make_double2(yv.x, yv.y);
+    for (int c = 0; c < nchunk; ++c) {
+        const double2 p = rpart[(int64_t)c * B + i];
+        s.x -= p.x;
+        s.y -= p.y;
+    }
+    r[i] = s;
+}
+
+// one wave per column: a_u = h_u^H r - lambda x_u, b_u = h_u^H y; per-block sums of |a|^2, |b|^2
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_cols(const cv<T>* __restrict__ H, int64_t ld, int B, int U,
+                                                    const double2* __restrict__ r, const cv<T>* __restrict__ y,
+                                                    const cv<T>* __restrict__ x, double lambda,
+                                                    double* __restrict__ colpart) {
+    __shared__ double sa[4], sb[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int u = blockIdx.x * 4 + wid;
+    double na = 0.0, nb = 0.0;
+    if (u < U) {
+        double ar = 0, ai = 0, br = 0, bi = 0;
+        for (int i = lane; i < B; i += 64) {
+            const cv<T> h = H[(int64_t)u * ld + i];
+            const double hr = h.x, hi = h.y;
+            const double2 rv = r[i];
+            const cv<T> yv = y[i];
+            ar += hr * rv.x + hi * rv.y;
+            ai += hr * rv.y - hi * rv.x;
+            br += hr * (double)yv.x + hi * (double)yv.y;
+            bi += hr * (double)yv.y - hi * (double)yv.x;
+        }
+        ar = wave_allsum(ar);
+        ai = wave_allsum(ai);
+        br = wave_allsum(br);
+        bi = wave_allsum(bi);
+        const cv<T> xv = x[u];
+        ar -= lambda * (double)xv.x;
+        ai -= lambda * (double)xv.y;
+        na = ar * ar + ai * ai;
+        nb = br * br + bi * bi;
+    }
+    if (lane == 0) {
+        sa[wid] = na;
+        sb[wid] = nb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        colpart[2 * blockIdx.x + 0] = sa[0] + sa[1] + sa[2] + sa[3];
+        colpart[2 * blockIdx.x + 1] = sb[0] + sb[1] + sb[2] + sb[3];
+    }
+}
+
+__global__ void k_resid_final(const double* __restrict__ colpart, int nblk, double* __restrict__ out) {
+    __shared__ double sa[256], sb[256];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += 256) {
+        a += colpart[2 * k];
+        b += colpart[2 * k + 1];
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sa[threadIdx.x] += sa[threadIdx.x + s];
+            sb[threadIdx.x] += sb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sb[0] > 0.0 ? sqrt(sa[0] / sb[0]) : sqrt(sa[0]);
+}
+
+template <typename T> static hipError_t launch_resid_t(const ResidLaunch& L, hipStream_t st) {
+    const int cpc = (L.U + L.nchunk - 1) / L.nchunk;
+    hipLaunchKernelGGL(k_resid_rows<T>, dim3((L.B + 255) / 256, L.nchunk), dim3(256), 0, st, (const cv<T>*)L.H, L.ld,
+                       L.B, L.U, (const cv<T>*)L.x, cpc, (double2*)L.rpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_resid_r<T>, dim3((L.B + 255) / 256), dim3(256), 0, st, (const cv<T>*)L.y,
+                       (const double2*)L.rpart, L.nchunk, L.B, (double2*)L.r);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nblk = (L.U + 3) / 4;
+    hipLaunchKernelGGL(k_resid_cols<T>, dim3(nblk), dim3(256), 0, st, (const cv<T>*)L.H, L.ld, L.B, L.U,
+                       (const double2*)L.r, (const cv<T>*)L.y, (const cv<T>*)L.x, L.lambda, L.colpart);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, st, (const double*)L.colpart, nblk, L.out);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid(const ResidLaunch& L, hipStream_t st) {
+    return L.c128 ? launch_resid_t<double>(L, st) : launch_resid_t<float>(L, st);
+}
+
+// ---- fusion of the local estimates (uplink, C > 1) --------------------------
+template <typename T>
+__global__ void k_fuse(const cv<T>* __restrict__ xloc, const double* __restrict__ msum, int C, int U, double N0,
+                       cv<T>* __restrict__ x) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= U) return;
+    double tot = 0.0;
+    for (int c = 0; c < C; ++c) tot += 1.0 / ((N0 / (double)U) * msum[c]);
+    double re = 0.0, im = 0.0;
+    for (int c = 0; c < C; ++c) {
+        const double wc = (1.0 / ((N0 / (double)U) * msum[c])) / tot;
+        const cv<T> v = xloc[(int64_t)c * U + u];
+        re += wc * (double)v.x;
+        im += wc * (double)v.y;
+    }
+    x[u] = cmake<T>((T)re, (T)im);
+}
+hipError_t launch_fuse(bool c128, const void* xloc, const double* msum, int C, int U, double N0, void* x,
+                       hipStream_t st) {
+    if (c128)
+        hipLaunchKernelGGL(k_fuse<double>, dim3((U + 255) / 256), dim3(256), 0, st, (const double2*)xloc, msum, C,
+                           U, N0, (double2*)x);
+    else
+        hipLaunchKernelGGL(k_fuse<float>, dim3((U + 255) / 256), dim3(256), 0, st, (const float2*)xloc, msum, C, U,
+                           N0, (float2*)x);
+    return hipGetLastError();
+}
+
+// ---- helpers ---------------------------------------------------------------
+__global__ void k_zero_u32(uint32_t* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+// Merge device-side status bits into info[0] and flag non-finite output.
+template <typename T>
+__global__ void k_finalize(const cv<T>* __restrict__ x, int U, const uint32_t* __restrict__ status,
+                           cdm_info* __restrict__ info) {
+    __shared__ int nf;
+    if (threadIdx.x == 0) nf = 0;
+    __syncthreads();
+    int bad = 0;
+    for (int u = threadIdx.x; u < U; u += blockDim.x) {
+        const cv<T> v = x[u];
+        if (!isfinite(v.x) || !isfinite(v.y)) bad = 1;
+    }
+    if (bad) atomicOr(&nf, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // status[0]: a cross-workgroup wait was abandoned; status[1]: CDM_INFO_* bits
+        int fl = info[0].flags | (int)status[1];
+        if (status[0]) fl |= CDM_INFO_TIMEOUT;
+        if (nf) fl |= CDM_INFO_NONFINITE;
+        info[0].flags = fl;
+    }
+}
+hipError_t launch_finalize(const void* x, int U, bool c128, const uint32_t* status, cdm_info* info,
+                           hipStream_t st) {
+    if (c128)
+        hipLaunchKernelGGL(k_finalize<double>, dim3(1), dim3(1024), 0, st, (const double2*)x, U, status, info);
+    else
+        hipLaunchKernelGGL(k_finalize<float>, dim3(1), dim3(1024), 0, st, (const float2*)x, U, status, info);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_resid(const double* __restrict__ src, cdm_info* __restrict__ info, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) info[i].resid = src[i];
+}
+hipError_t launch_copy_resid(const double* src, cdm_info* info, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_resid, dim3((count + 255) / 256), dim3(256), 0, st, src, info, count);
+    return hipGetLastError();
+}
+
+}  // namespace cdm

@@ -1,0 +1,480 @@
+// k_panel.hip -- cooperative "panel" engine for one large uplink instance.
+//
+// Block form of the cyclic sweep of Algorithm 1.  With r the residual at the start
+// of a panel K of consecutive users, g_K = H_K^H r, b_u = g_u - lambda x_u, and
+// G = H_K^H H_K split as D + L + L^H (D = diag(||h_u||^2 + lambda) after adding
+// lambda), the U_K sequential coordinate updates of Algorithm 1 satisfy
+//     delta_u = (b_u - sum_{v<u, v in K} G_uv delta_v) / (||h_u||^2 + lambda),
+// i.e. (D + L) delta_K = b_K: exactly the same numbers, in exact arithmetic, as
+// running the u-loop of Algorithm 1 one coordinate at a time.  Here
+// M_K = (D + L)^-1 is formed once per solve (k_gram_partial + k_gram_invert, a
+// small dense contraction per panel), and every sweep applies
+//     delta_K = M_K b_K,   x_K += delta_K,   r -= H_K delta_K.
+//
+// k_cd_panel runs all sweeps in one cooperative launch.  Workgroup w owns rows
+// [64*RPL*w, 64*RPL*(w+1)) and keeps them of r in VGPRs; lane = row, and the
+// NWV waves split each panel's columns.  Per panel:
+//   1. partial g_K over the workgroup's rows (wave transpose-reduce), written to
+//      a partial buffer, arrive on counter A;  the next panel's tile is loaded
+//      into registers behind this;
+//   2. reducer workgroup j (one per panel column) waits for A, sums the P
+//      partials of column j in a fixed order, forms b_j = g_j - lambda x_j,
+//      publishes (b_j, x_j), arrives on counter B; x_j is owned by reducer j;
+//   3. every workgroup waits for B, computes delta_K = M_K b_K itself (identical
+//      bits everywhere), applies r -= H_K delta_K from the tile still in
+//      registers, and accumulates the stop statistics.
+// H is read from HBM exactly once per sweep.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace cdm {
+
+constexpr int PANEL_NT = 512;   // 8 waves per workgroup
+constexpr int PANEL_NWV = PANEL_NT / 64;
+
+template <typename T> struct PanelArgs {
+    const cv<T>* H;
+    int64_t ld;
+    const cv<T>* r0;
+    cv<T>* x;
+    const cv<T>* M;
+    cv<T>* part;
+    cv<T>* gbuf;
+    uint32_t* ctr;
+    cdm_info* info;
+    double lambda;
+    double tol;
+    uint64_t timeout_ticks;
+    int B, U, npanels, T_max;
+};
+
+template <typename T, int KP, int RPL>
+__global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
+    using V = cv<T>;
+    constexpr int NC = KP / PANEL_NWV;          // panel columns per wave
+    static_assert(NC >= 1 && NC <= 64 && (NC & (NC - 1)) == 0, "bad panel split");
+    constexpr int LOG_NC = (NC == 1) ? 0 : (NC == 2) ? 1 : (NC == 4) ? 2 : (NC == 8) ? 3 : (NC == 16) ? 4 : (NC == 32) ? 5 : 6;
+    constexpr int OWN_SHIFT = 6 - LOG_NC;       // lane >> OWN_SHIFT = column slot after the transpose-reduce
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int w = blockIdx.x;
+    const int P = gridDim.x;
+    const int R = P < KP ? P : KP;             // reducer workgroups
+    const T lambda = (T)a.lambda;
+    const int B = a.B, U = a.U;
+
+    __shared__ V bsh[KP];
+    __shared__ V xsh[KP];
+    __shared__ V dsh[KP];
+    __shared__ V axs[PANEL_NWV][RPL][64];
+    __shared__ T red_s[PANEL_NWV][2];
+    __shared__ uint32_t flag_s;
+
+    uint32_t* ctrA = a.ctr + 0;
+    uint32_t* ctrB = a.ctr + 1;
+    uint32_t* abort_flag = a.ctr + 2;
+
+    const int row0 = w * 64 * RPL;
+    V r[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int row = row0 + lane + 64 * q;
+        r[q] = row < B ? a.r0[row] : czero<T>();
+    }
+
+    V tile[NC][RPL];
+    V nxt[NC][RPL];
+    auto load_panel = [&](int K) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int col = K * KP + wid + PANEL_NWV * c;
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const int row = row0 + lane + 64 * q;
+                nxt[c][q] = (col < U && row < B) ? a.H[(int64_t)col * a.ld + row] : czero<T>();
+            }
+        }
+    };
+    load_panel(0);
+
+    uint32_t seq = 0;
+    int sweeps = 0;
+    double S = 0.0, Xn = 0.0;
+    bool ok = true;
+    const bool reducer = w < R;
+
+    for (int t = 1; t <= a.T_max && ok; ++t) {
+        S = 0.0;
+        Xn = 0.0;
+        for (int K = 0; K < a.npanels; ++K) {
+            const int par = seq & 1;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) tile[c][q] = nxt[c][q];
+
+            // 1. partial g_K = H_K^H r over this workgroup's rows
+            T pr[NC], pi[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                pr[c] = T(0);
+                pi[c] = T(0);
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) {
+                    pr[c] += tile[c][q].x * r[q].x + tile[c][q].y * r[q].y;
+                    pi[c] += tile[c][q].x * r[q].y - tile[c][q].y * r[q].x;
+                }
+            }
+            wave_transpose_sum<T, NC>(pr, lane);
+            wave_transpose_sum<T, NC>(pi, lane);
+            if ((lane & ((1 << OWN_SHIFT) - 1)) == 0) {
+                const int j = wid + PANEL_NWV * (lane >> OWN_SHIFT);
+                a.part[((int64_t)par * KP + j) * P + w] = cmake<T>(pr[0], pi[0]);
+            }
+            wg_arrive(ctrA);
+            const int Kn = (K + 1 < a.npanels) ? K + 1 : 0;
+            if (!reducer) load_panel(Kn);
+
+            // 2. reducers: g_j = sum of the P partials (fixed order), b_j = g_j - lambda x_j
+            if (reducer) {
+                ok = wg_wait_geq(ctrA, (uint32_t)P * (seq + 1), abort_flag, a.timeout_ticks, &flag_s);
+                if (ok) {
+                    for (int j = w; j < KP; j += P) {
+                        V acc = czero<T>();
+                        for (int p = tid; p < P; p += PANEL_NT) {
+                            const V v = a.part[((int64_t)par * KP + j) * P + p];
+                            acc.x += v.x;
+                            acc.y += v.y;
+                        }
+                        acc.x = wave_allsum(acc.x);
+                        acc.y = wave_allsum(acc.y);
+                        if (lane == 0) {
+                            red_s[wid][0] = acc.x;
+                            red_s[wid][1] = acc.y;
+                        }
+                        __syncthreads();
+                        if (tid == 0) {
+                            V g = czero<T>();
+#pragma unroll
+                            for (int v = 0; v < PANEL_NWV; ++v) {
+                                g.x += red_s[v][0];
+                                g.y += red_s[v][1];
+                            }
+                            const int u = K * KP + j;
+                            const V xo = (u < U) ? a.x[u] : czero<T>();
+                            V b;
+                            b.x = g.x - lambda * xo.x;
+                            b.y = g.y - lambda * xo.y;
+                            a.gbuf[((int64_t)par * KP + j) * 2 + 0] = b;
+                            a.gbuf[((int64_t)par * KP + j) * 2 + 1] = xo;
+                        }
+                        __syncthreads();
+                    }
+                }
+                wg_arrive(ctrB);
+                load_panel(Kn);
+            }
+            if (!ok) break;
+
+            // 3. everyone: delta_K = M_K b_K, x_K += delta_K, r -= H_K delta_K
+            ok = wg_wait_geq(ctrB, (uint32_t)R * (seq + 1), abort_flag, a.timeout_ticks, &flag_s);
+            if (!ok) break;
+            for (int j = tid; j < KP; j += PANEL_NT) {
+                bsh[j] = a.gbuf[((int64_t)par * KP + j) * 2 + 0];
+                xsh[j] = a.gbuf[((int64_t)par * KP + j) * 2 + 1];
+            }
+            __syncthreads();
+            if (tid < KP) {
+                const V* Mk = a.M + (int64_t)K * KP * KP;
+                V d = czero<T>();
+                for (int v = 0; v <= tid; ++v) cfma(d, Mk[(int64_t)v * KP + tid], bsh[v]);
+                dsh[tid] = d;
+            }
+            __syncthreads();
+            if (reducer && tid == 0) {
+                for (int j = w; j < KP; j += P) {
+                    const int u = K * KP + j;
+                    if (u < U) {
+                        V xn;
+                        xn.x = xsh[j].x + dsh[j].x;
+                        xn.y = xsh[j].y + dsh[j].y;
+                        a.x[u] = xn;
+                    }
+                }
+            }
+            {
+                double s1 = 0.0, s2 = 0.0;
+                for (int j = lane; j < KP; j += 64) {
+                    const V d = dsh[j];
+                    V xn;
+                    xn.x = xsh[j].x + d.x;
+                    xn.y = xsh[j].y + d.y;
+                    s1 += cabs2d(d);
+                    s2 += cabs2d(xn);
+                }
+                S += wave_allsum(s1);
+                Xn += wave_allsum(s2);
+            }
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                V acc = czero<T>();
+#pragma unroll
+                for (int c = 0; c < NC; ++c) cfma(acc, tile[c][q], dsh[wid + PANEL_NWV * c]);
+                axs[wid][q][lane] = acc;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                V s = czero<T>();
+#pragma unroll
+                for (int v = 0; v < PANEL_NWV; ++v) {
+                    s.x += axs[v][q][lane].x;
+                    s.y += axs[v][q][lane].y;
+                }
+                r[q].x -= s.x;
+                r[q].y -= s.y;
+            }
+            ++seq;
+        }
+        if (!ok) break;
+        sweeps = t;
+        if (a.tol > 0.0 && sqrt(S) <= a.tol * sqrt(Xn)) break;
+    }
+    if (w == 0 && tid == 0) {
+        const double rel = (Xn > 0.0) ? sqrt(S / Xn) : (S > 0.0 ? INFINITY : 0.0);
+        int fl = 0;
+        if (a.tol > 0.0 && !(rel <= a.tol)) fl |= CDM_INFO_NOT_CONVERGED;
+        if (!ok) fl |= CDM_INFO_TIMEOUT;
+        cdm_info o;
+        o.sweeps = sweeps;
+        o.flags = fl;
+        o.rel_step = rel;
+        o.resid = -1.0;
+        o.reserved = 0.0;
+        a.info[0] = o;
+    }
+}
+
+template <typename T, int KP, int RPL>
+static hipError_t launch_panel_t(const PanelLaunch& L, hipStream_t st) {
+    PanelArgs<T> a;
+    a.H = (const cv<T>*)L.H;
+    a.ld = L.ld;
+    a.r0 = (const cv<T>*)L.r0;
+    a.x = (cv<T>*)L.x;
+    a.M = (const cv<T>*)L.M;
+    a.part = (cv<T>*)L.part;
+    a.gbuf = (cv<T>*)L.gbuf;
+    a.ctr = L.ctr;
+    a.info = L.info;
+    a.lambda = L.lambda;
+    a.tol = L.tol;
+    a.timeout_ticks = L.timeout_ticks;
+    a.B = L.B;
+    a.U = L.U;
+    a.npanels = L.npanels;
+    a.T_max = L.T_max;
+    void* args[] = {&a};
+    return hipLaunchCooperativeKernel((const void*)k_cd_panel<T, KP, RPL>, dim3(L.P), dim3(PANEL_NT), args, 0,
+                                      st);
+}
+
+template <typename T, int KP, int RPL>
+static int coresident_t() {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cd_panel<T, KP, RPL>, PANEL_NT, 0) != hipSuccess)
+        return 0;
+    return per * ncu;
+}
+
+hipError_t launch_panel(const PanelLaunch& L, hipStream_t st) {
+    if (L.c128) {
+        if (L.kp == 64 && L.rpl == 1) return launch_panel_t<double, 64, 1>(L, st);
+        if (L.kp == 64 && L.rpl == 2) return launch_panel_t<double, 64, 2>(L, st);
+        if (L.kp == 128 && L.rpl == 1) return launch_panel_t<double, 128, 1>(L, st);
+    } else {
+        if (L.kp == 128 && L.rpl == 1) return launch_panel_t<float, 128, 1>(L, st);
+        if (L.kp == 128 && L.rpl == 2) return launch_panel_t<float, 128, 2>(L, st);
+        if (L.kp == 256 && L.rpl == 1) return launch_panel_t<float, 256, 1>(L, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+int panel_max_coresident(bool c128, int kp, int rpl) {
+    if (c128) {
+        if (kp == 64 && rpl == 1) return coresident_t<double, 64, 1>();
+        if (kp == 64 && rpl == 2) return coresident_t<double, 64, 2>();
+        if (kp == 128 && rpl == 1) return coresident_t<double, 128, 1>();
+    } else {
+        if (kp == 128 && rpl == 1) return coresident_t<float, 128, 1>();
+        if (kp == 128 && rpl == 2) return coresident_t<float, 128, 2>();
+        if (kp == 256 && rpl == 1) return coresident_t<float, 256, 1>();
+    }
+    return 0;
+}
+
+// ============================================================================
+// Panel Gram blocks G_K = H_K^H H_K (lower 64x64 sub-blocks) over a row split.
+// grid.x = npanels * nsub, grid.y = nsplit; 256 threads as a 16 x 16 grid, each
+// accumulating a 4 x 4 complex tile; rows stream through LDS 32 at a time.
+// ============================================================================
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_partial(const cv<T>* __restrict__ H, int64_t ld, int B, int U, int kp,
+                                                      int nsub, int rows_per_split, cv<T>* __restrict__ gpart,
+                                                      int npanels) {
+    using V = cv<T>;
+    __shared__ V As[32][64 + 1];
+    __shared__ V Bs[32][64 + 1];
+    const int tid = threadIdx.x;
+    const int K = blockIdx.x / nsub;
+    int sb = blockIdx.x % nsub;
+    // sub-block (bi, bj), bi >= bj, enumerated row by row of the lower triangle
+    int bi = 0;
+    while (sb > bi) {
+        sb -= bi + 1;
+        ++bi;
+    }
+    const int bj = sb;
+    const int split = blockIdx.y;
+    const int r_lo = split * rows_per_split;
+    const int r_hi = min(B, r_lo + rows_per_split);
+    const int ty = tid >> 4, tx = tid & 15;
+    V acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = czero<T>();
+    const int colA0 = K * kp + bi * 64;
+    const int colB0 = K * kp + bj * 64;
+    for (int rb = r_lo; rb < r_hi; rb += 32) {
+        // fill: thread -> (row i = tid & 31, column group tid >> 5, + 8 per step)
+        const int i = tid & 31;
+        const int row = rb + i;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int c = (tid >> 5) + 8 * k;
+            const int ca = colA0 + c, cb = colB0 + c;
+            As[i][c] = (row < r_hi && ca < U) ? H[(int64_t)ca * ld + row] : czero<T>();
+            Bs[i][c] = (row < r_hi && cb < U) ? H[(int64_t)cb * ld + row] : czero<T>();
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int ii = 0; ii < 32; ++ii) {
+            V av[4], bv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                av[k] = As[ii][ty * 4 + k];
+                bv[k] = Bs[ii][tx * 4 + k];
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cfma_conj(acc[p][q], av[p], bv[q]);
+        }
+        __syncthreads();
+    }
+    V* out = gpart + ((int64_t)split * npanels + K) * kp * kp;
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int u = bi * 64 + ty * 4 + p;
+            const int v = bj * 64 + tx * 4 + q;
+            out[(int64_t)u * kp + v] = acc[p][q];
+        }
+}
+
+// Sum the split partials, form D + L (lambda on the diagonal; inactive coordinates
+// with ||h_u||^2 + lambda == 0 decoupled), and invert it row by row:
+//   M_uc = ([u == c] - sum_{c <= v < u} A_uv M_vc) / A_uu.
+// One workgroup of kp threads per panel; thread c owns column c of M.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_invert(cv<T>* __restrict__ gpart, int nsplit, int npanels, int kp, int U,
+                                                     double lambda, cv<T>* __restrict__ Mcm, cv<T>* __restrict__ Mrow,
+                                                     double* __restrict__ e_out, uint32_t* __restrict__ status) {
+    using V = cv<T>;
+    const int K = blockIdx.x;
+    const int c = threadIdx.x;
+    const int64_t pstride = (int64_t)npanels * kp * kp;
+    V* A = gpart + (int64_t)K * kp * kp;          // split 0 slot receives the sum
+    __shared__ V arow[256];
+    __shared__ T dsh[256];
+    __shared__ int act[256];
+    // 1. sum over splits (elements with u >= v), fixed order
+    for (int idx = c; idx < kp * kp; idx += blockDim.x) {
+        const int u = idx / kp, v = idx % kp;
+        if (u < v) continue;
+        V s = A[idx];
+        for (int sp = 1; sp < nsplit; ++sp) {
+            const V p = gpart[sp * pstride + (int64_t)K * kp * kp + idx];
+            s.x += p.x;
+            s.y += p.y;
+        }
+        A[idx] = s;
+    }
+    __syncthreads();
+    // 2. diagonal: energies, activity
+    if (c < kp) {
+        const int u = K * kp + c;
+        const T e = A[(int64_t)c * kp + c].x;
+        const bool valid = u < U;
+        const bool live = valid && ((double)e + lambda > 0.0);
+        act[c] = live ? 1 : 0;
+        dsh[c] = live ? (T)((double)e + lambda) : T(1);
+        if (valid) e_out[u] = (double)e;
+        if (valid && !live) atomicOr(status, (uint32_t)CDM_INFO_ZERO_COLUMN);
+    }
+    __syncthreads();
+    // 3. inverse of (D + L), row by row
+    V* Mr = Mrow + (int64_t)K * kp * kp;
+    V* Mc = Mcm + (int64_t)K * kp * kp;
+    for (int u = 0; u < kp; ++u) {
+        if (c < u) {
+            const bool live = act[u] && act[c];
+            arow[c] = live ? A[(int64_t)u * kp + c] : czero<T>();
+        }
+        __syncthreads();
+        if (c < kp) {
+            V s = (u == c) ? cmake<T>(T(1), T(0)) : czero<T>();
+            if (c < u) {
+                for (int v = c; v < u; ++v) cfms(s, arow[v], Mr[(int64_t)v * kp + c]);
+            }
+            V m = czero<T>();
+            if (c <= u && act[u]) {
+                m.x = s.x / dsh[u];
+                m.y = s.y / dsh[u];
+            }
+            Mr[(int64_t)u * kp + c] = m;
+            Mc[(int64_t)c * kp + u] = m;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T> static hipError_t launch_gram_t(const GramLaunch& L, hipStream_t st) {
+    const int nb = L.kp / 64;
+    const int nsub = nb * (nb + 1) / 2;
+    int rps = (L.B + L.nsplit - 1) / L.nsplit;
+    rps = (rps + 31) / 32 * 32;
+    hipLaunchKernelGGL(k_gram_partial<T>, dim3(L.npanels * nsub, L.nsplit), dim3(256), 0, st, (const cv<T>*)L.H,
+                       L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // M is written twice: column-major (used by the sweep) and row-major (the
+    // recurrence reads its own earlier rows); the row-major copy lives in the
+    // split-1 slot of gpart when nsplit > 1, else right after M.
+    cv<T>* Mrow = (cv<T>*)L.gpart + (int64_t)L.npanels * L.kp * L.kp;
+    hipLaunchKernelGGL(k_gram_invert<T>, dim3(L.npanels), dim3(L.kp), 0, st, (cv<T>*)L.gpart, L.nsplit, L.npanels,
+                       L.kp, L.U, L.lambda, (cv<T>*)L.M, Mrow, L.e, L.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram(const GramLaunch& L, hipStream_t st) {
+    return L.c128 ? launch_gram_t<double>(L, st) : launch_gram_t<float>(L, st);
+}
+
+}  // namespace cdm

@@ -1,0 +1,258 @@
+// k_wg.hip -- "one workgroup per instance" engine for Algorithm 1 (uplink CD).
+//
+// Each workgroup owns one instance (an antenna cluster's local problem, or one
+// entry of an uneven batch) and runs the whole local CD of Algorithm 1 on it:
+// preprocessing (column energies, fused into the first sweep), init, T_max (or
+// tolerance-bounded) cyclic sweeps, output.  The residual r stays in VGPRs for the
+// whole solve (thread t owns rows t, t+NT, ...); each coordinate step is
+//   partial h_u^H r over the thread's rows  ->  wave64 butterfly  ->  cross-wave
+//   sum through LDS (one barrier)  ->  scalar rule, identical in every thread  ->
+//   axpy r -= h_u delta on the thread's rows.
+// Column u+1 is loaded while column u is reduced.  x and the per-column scalars
+// (m_u, n_u) live in LDS.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace cdm {
+
+template <typename T, int NT, int RPT>
+__global__ __launch_bounds__(NT) void k_cd_wg(const WgJob* __restrict__ jobs, int njobs,
+                                              const cv<T>* __restrict__ H, const cv<T>* __restrict__ Y,
+                                              const cv<T>* __restrict__ X0, cv<T>* __restrict__ X,
+                                              cdm_info* __restrict__ info, double lambda_d, int T_max,
+                                              double tol, const int* __restrict__ order,
+                                              uint32_t* __restrict__ queue, double* __restrict__ msum,
+                                              int64_t ld_arg) {
+    using V = cv<T>;
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const T lambda = (T)lambda_d;
+
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ T red_s[2][NW][3];
+    __shared__ int flag_s;
+    __shared__ int job_s;
+
+    for (;;) {
+        // next job from the shared queue; the queue hands out slots in `order`
+        // (largest instances first for uneven batches)
+        if (tid == 0) {
+            job_s = (int)atomicAdd(queue, 1u);
+            flag_s = 0;
+        }
+        __syncthreads();
+        const int jslot = job_s;
+        if (jslot >= njobs) return;
+        const int jid = order ? order[jslot] : jslot;
+        const WgJob jb = jobs[jid];
+        // ---------------------------------------------------------------- one instance
+        const int m = jb.m, n = jb.n;
+        const int64_t ld = jb.ld > 0 ? jb.ld : ld_arg;   // ld <= 0: the solve's leading dimension
+        const V* Hj = H + jb.h_off;
+        V* x_s = reinterpret_cast<V*>(smem_raw);
+        V* cf_s = x_s + n;   // (m_u, n_u) of Algorithm 1
+
+        V r[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = tid + q * NT;
+            r[q] = (i < m) ? Y[jb.y_off + i] : czero<T>();
+        }
+        for (int u = tid; u < n; u += NT) x_s[u] = X0 ? X0[jb.x0_off + u] : czero<T>();
+        __syncthreads();
+        if (X0) {  // warm start: r = y - H x0
+            for (int u = 0; u < n; ++u) {
+                const V xu = x_s[u];
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    const int i = tid + q * NT;
+                    if (i < m) cfms(r[q], Hj[u * ld + i], xu);
+                }
+            }
+        }
+
+        int sweeps = 0;
+        double S = 0.0, Xn = 0.0;
+        for (int t = 1; t <= T_max; ++t) {
+            S = 0.0;
+            Xn = 0.0;
+            V hc[RPT], hn[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = tid + q * NT;
+                hc[q] = (i < m) ? Hj[i] : czero<T>();
+            }
+            for (int u = 0; u < n; ++u) {
+                if (u + 1 < n) {
+#pragma unroll
+                    for (int q = 0; q < RPT; ++q) {
+                        const int i = tid + q * NT;
+                        hn[q] = (i < m) ? Hj[(int64_t)(u + 1) * ld + i] : czero<T>();
+                    }
+                }
+                T gr = 0, gi = 0, ee = 0;
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    gr += hc[q].x * r[q].x + hc[q].y * r[q].y;
+                    gi += hc[q].x * r[q].y - hc[q].y * r[q].x;
+                    if (t == 1) ee += hc[q].x * hc[q].x + hc[q].y * hc[q].y;
+                }
+                gr = wave_allsum(gr);
+                gi = wave_allsum(gi);
+                if (t == 1) ee = wave_allsum(ee);
+                // read x_u and the scalars before the barrier: thread 0 overwrites them after it
+                const V xu = x_s[u];
+                V cf = (t > 1) ? cf_s[u] : czero<T>();
+                const int par = u & 1;
+                if (lane == 0) {
+                    red_s[par][wid][0] = gr;
+                    red_s[par][wid][1] = gi;
+                    red_s[par][wid][2] = ee;
+                }
+                __syncthreads();
+                V g = czero<T>();
+                T e = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    g.x += red_s[par][w][0];
+                    g.y += red_s[par][w][1];
+                    if (t == 1) e += red_s[par][w][2];
+                }
+                if (t == 1) {
+                    // Algorithm 1 preprocessing: m_u = 1/(||h_u||^2 + lambda), n_u = m_u ||h_u||^2.
+                    // A coordinate with ||h_u||^2 + lambda == 0 stays inactive: (m, n) = (0, 1).
+                    if (e + lambda > T(0)) {
+                        cf.x = T(1) / (e + lambda);
+                        cf.y = cf.x * e;
+                    } else {
+                        cf.x = T(0);
+                        cf.y = T(1);
+                        if (tid == 0) flag_s |= CDM_INFO_ZERO_COLUMN;
+                    }
+                }
+                // x_u <- m_u h_u^H r + n_u x_u ; delta = x_u(new) - x_u(old)
+                V xn;
+                xn.x = cf.x * g.x + cf.y * xu.x;
+                xn.y = cf.x * g.y + cf.y * xu.y;
+                V d;
+                d.x = xn.x - xu.x;
+                d.y = xn.y - xu.y;
+                if (tid == 0) {
+                    x_s[u] = xn;
+                    if (t == 1) cf_s[u] = cf;
+                }
+                // r <- r - h_u delta
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) cfms(r[q], hc[q], d);
+                S += cabs2d(d);
+                Xn += cabs2d(xn);
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) hc[q] = hn[q];
+            }
+            __syncthreads();
+            if (t == 1 && msum && tid == 0) {
+                // sum_u m_u of this cluster, in index order (feeds the fusion weights)
+                double ms = 0.0;
+                for (int u = 0; u < n; ++u) ms += (double)cf_s[u].x;
+                msum[jb.info_idx] = ms;
+            }
+            sweeps = t;
+            if (tol > 0.0 && sqrt(S) <= tol * sqrt(Xn)) break;
+        }
+        // ---------------------------------------------------------------- output
+        int nf = 0;
+        for (int u = tid; u < n; u += NT) {
+            const V v = x_s[u];
+            if (!isfinite(v.x) || !isfinite(v.y)) nf = 1;
+            X[jb.x_off + u] = v;
+        }
+        if (nf) atomicOr(&flag_s, CDM_INFO_NONFINITE);
+        __syncthreads();
+        if (tid == 0) {
+            const double rel = (Xn > 0.0) ? sqrt(S / Xn) : (S > 0.0 ? INFINITY : 0.0);
+            int fl = flag_s;
+            if (tol > 0.0 && !(rel <= tol)) fl |= CDM_INFO_NOT_CONVERGED;
+            cdm_info o;
+            o.sweeps = sweeps;
+            o.flags = fl;
+            o.rel_step = rel;
+            o.resid = -1.0;
+            o.reserved = 0.0;
+            info[jb.info_idx] = o;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int NT, int RPT>
+static hipError_t launch_wg_t(const WgLaunch& L, hipStream_t st) {
+    const size_t shm = (size_t)L.n_max * 2 * sizeof(cv<T>);
+    hipLaunchKernelGGL((k_cd_wg<T, NT, RPT>), dim3(L.grid), dim3(NT), shm, st, L.jobs, L.njobs,
+                       (const cv<T>*)L.H, (const cv<T>*)L.Y, (const cv<T>*)L.X0, (cv<T>*)L.X, L.info,
+                       L.lambda, L.T_max, L.tol, L.order, L.queue, L.msum, L.ld);
+    return hipGetLastError();
+}
+
+template <typename T, int NT>
+static hipError_t launch_wg_rpt(const WgLaunch& L, hipStream_t st) {
+    switch (L.rpt) {
+        case 1: return launch_wg_t<T, NT, 1>(L, st);
+        case 2: return launch_wg_t<T, NT, 2>(L, st);
+        case 4: return launch_wg_t<T, NT, 4>(L, st);
+        case 8: return launch_wg_t<T, NT, 8>(L, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_wg(const WgLaunch& L, hipStream_t st) {
+    if (L.nt == 256) return L.c128 ? launch_wg_rpt<double, 256>(L, st) : launch_wg_rpt<float, 256>(L, st);
+    if (L.nt == 1024) return L.c128 ? launch_wg_rpt<double, 1024>(L, st) : launch_wg_rpt<float, 1024>(L, st);
+    return hipErrorInvalidValue;
+}
+
+size_t wg_lds_bytes(int n_max, bool c128) { return (size_t)n_max * 2 * (c128 ? 16 : 8); }
+
+template <typename T, int NT, int RPT> static hipError_t set_lds_t(size_t bytes) {
+    return hipFuncSetAttribute((const void*)k_cd_wg<T, NT, RPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+template <typename T, int NT, int RPT> static int occ_t(size_t bytes) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cd_wg<T, NT, RPT>, NT, bytes) != hipSuccess) return 0;
+    return per;
+}
+#define CDM_WG_DISPATCH(FN, c128, nt, rpt, ...)                                              \
+    do {                                                                                     \
+        if (c128) {                                                                          \
+            if (nt == 256 && rpt == 1) return FN<double, 256, 1>(__VA_ARGS__);               \
+            if (nt == 256 && rpt == 2) return FN<double, 256, 2>(__VA_ARGS__);               \
+            if (nt == 256 && rpt == 4) return FN<double, 256, 4>(__VA_ARGS__);               \
+            if (nt == 256 && rpt == 8) return FN<double, 256, 8>(__VA_ARGS__);               \
+            if (nt == 1024 && rpt == 1) return FN<double, 1024, 1>(__VA_ARGS__);             \
+            if (nt == 1024 && rpt == 2) return FN<double, 1024, 2>(__VA_ARGS__);             \
+            if (nt == 1024 && rpt == 4) return FN<double, 1024, 4>(__VA_ARGS__);             \
+            if (nt == 1024 && rpt == 8) return FN<double, 1024, 8>(__VA_ARGS__);             \
+        } else {                                                                             \
+            if (nt == 256 && rpt == 1) return FN<float, 256, 1>(__VA_ARGS__);                \
+            if (nt == 256 && rpt == 2) return FN<float, 256, 2>(__VA_ARGS__);                \
+            if (nt == 256 && rpt == 4) return FN<float, 256, 4>(__VA_ARGS__);                \
+            if (nt == 256 && rpt == 8) return FN<float, 256, 8>(__VA_ARGS__);                \
+            if (nt == 1024 && rpt == 1) return FN<float, 1024, 1>(__VA_ARGS__);              \
+            if (nt == 1024 && rpt == 2) return FN<float, 1024, 2>(__VA_ARGS__);              \
+            if (nt == 1024 && rpt == 4) return FN<float, 1024, 4>(__VA_ARGS__);              \
+            if (nt == 1024 && rpt == 8) return FN<float, 1024, 8>(__VA_ARGS__);              \
+        }                                                                                    \
+    } while (0)
+
+hipError_t wg_set_lds_limit(bool c128, int nt, int rpt, size_t bytes) {
+    CDM_WG_DISPATCH(set_lds_t, c128, nt, rpt, bytes);
+    return hipErrorInvalidValue;
+}
+int wg_occupancy(bool c128, int nt, int rpt, size_t bytes) {
+    CDM_WG_DISPATCH(occ_t, c128, nt, rpt, bytes);
+    return 0;
+}
+
+}  // namespace cdm

@@ -1,0 +1,133 @@
+// launch.hpp -- host-side launch descriptors shared by the runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cdm.h"
+
+namespace cdm {
+
+// One instance handled by one workgroup (uplink Algorithm 1, one cluster or one
+// entry of an uneven batch).  Offsets are in complex elements.
+struct WgJob {
+    int64_t h_off;    // first element of the instance's H block
+    int64_t ld;       // leading dimension of that block
+    int64_t y_off;    // first element of its y
+    int64_t x0_off;   // first element of its warm start (if any)
+    int64_t x_off;    // first element of its output x
+    int32_t m;        // rows (antennas)
+    int32_t n;        // columns (users)
+    int32_t info_idx; // cdm_info record to write
+    int32_t pad;
+};
+
+struct WgLaunch {
+    bool c128;
+    int nt;           // threads per workgroup (256 or 1024)
+    int rpt;          // rows per thread (1, 2, 4, 8): m <= nt * rpt
+    int grid;         // workgroups (persistent; they pull jobs from `queue`)
+    int n_max;        // largest n of any job (sizes the LDS)
+    const WgJob* jobs;
+    int njobs;
+    const int* order; // queue slot -> job id (device), NULL = identity
+    uint32_t* queue;  // device counter, zero before the launch
+    const void* H;
+    const void* Y;
+    const void* X0;
+    void* X;
+    cdm_info* info;
+    double lambda;
+    int T_max;
+    double tol;
+    double* msum;     // optional: sum_u m_u per job (cluster fusion weights)
+    int64_t ld;       // leading dimension for jobs whose own ld is <= 0
+};
+hipError_t launch_wg(const WgLaunch& L, hipStream_t st);
+size_t wg_lds_bytes(int n_max, bool c128);
+hipError_t wg_set_lds_limit(bool c128, int nt, int rpt, size_t bytes);
+int wg_occupancy(bool c128, int nt, int rpt, size_t bytes);
+
+// Fusion of C local estimates (Sec. III): x = sum_c lambda_c x_c with
+// lambda_c = sigma_c^-2 / sum_c' sigma_c'^-2 and sigma_c^2 = (N0/U) sum_u m_{u,c}.
+hipError_t launch_fuse(bool c128, const void* xloc, const double* msum, int C, int U, double N0, void* x,
+                       hipStream_t st);
+
+// Cooperative panel engine for one large instance.
+struct PanelLaunch {
+    bool c128;
+    int kp;              // panel width (columns per panel)
+    int rpl;             // rows per lane (each workgroup owns 64*rpl rows)
+    int P;               // workgroups (one per row block), all co-resident
+    int B, U, npanels;
+    const void* H;
+    int64_t ld;
+    const void* r0;      // initial residual (B)
+    void* x;             // in: x^(0) (U), out: x^(T)
+    const void* M;       // [npanels][kp][kp] column-major inverses of (D + L) per panel
+    void* part;          // [2][kp][P] partial dot products
+    void* gbuf;          // [2][kp][2] reduced right-hand sides and old x
+    uint32_t* ctr;       // [0] partial arrivals, [1] reducer arrivals, [2] abort, [3] status word
+    cdm_info* info;
+    double lambda;
+    int T_max;
+    double tol;
+    uint64_t timeout_ticks;
+};
+hipError_t launch_panel(const PanelLaunch& L, hipStream_t st);
+int panel_max_coresident(bool c128, int kp, int rpl);
+
+// Panel Gram blocks and the inverses of the Gauss-Seidel splitting matrices.
+struct GramLaunch {
+    bool c128;
+    int kp;
+    int B, U, npanels, nsplit;
+    const void* H;
+    int64_t ld;
+    void* gpart;         // [nsplit][npanels][kp][kp] partial Gram blocks (row-major, lower part)
+    void* M;             // out: [npanels][kp][kp] column-major (D + L)^-1
+    double* e;           // out: column energies ||h_u||^2 (U), FP64
+    uint32_t* status;    // ORed CDM_INFO_ZERO_COLUMN
+    double lambda;
+};
+hipError_t launch_gram(const GramLaunch& L, hipStream_t st);
+
+// r0 = y (cold) or y - H x0 (warm); x = x0 or 0.
+struct InitLaunch {
+    bool c128;
+    int B, U;
+    const void* H;
+    int64_t ld;
+    const void* y;
+    const void* x0;
+    void* r0;
+    void* x;
+    void* rpart;         // [nchunk][B] scratch for the warm-start product
+    int nchunk;
+};
+hipError_t launch_init(const InitLaunch& L, hipStream_t st);
+
+// FP64 normal-equation residual ||H^H (y - H x) - lambda x|| / ||H^H y||.
+struct ResidLaunch {
+    bool c128;
+    int B, U;
+    const void* H;
+    int64_t ld;
+    const void* y;
+    const void* x;
+    double* rpart;       // [nchunk][2B] scratch
+    int nchunk;
+    double* r;           // [2B] scratch
+    double* colpart;     // [2 * ceil(U/4)] scratch
+    double lambda;
+    double* out;         // device scalar
+};
+hipError_t launch_resid(const ResidLaunch& L, hipStream_t st);
+
+// Small helpers.
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t st);
+hipError_t launch_finalize(const void* x, int U, bool c128, const uint32_t* status, cdm_info* info,
+                           hipStream_t st);
+hipError_t launch_copy_resid(const double* src, cdm_info* info, int count, hipStream_t st);
+
+}  // namespace cdm

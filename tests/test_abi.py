@@ -1,0 +1,90 @@
+"""The C ABI: the library loads, exports every entry point that include/cdm.h
+declares, and rejects invalid descriptors before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cdm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(cdm_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1902_08653_amd import cdm
+    if not os.path.exists(cdm.LIB_PATH):
+        from paper_1902_08653_amd import build
+        build.build()
+    return cdm.lib()
+
+
+def test_header_declares_the_boundary():
+    fns = declared_functions()
+    for f in ["cdm_create", "cdm_solve", "cdm_destroy", "cdm_create_batched", "cdm_solve_batched",
+              "cdm_residual", "cdm_status_string"]:
+        assert f in fns
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1902_08653_amd import cdm
+    fns = declared_functions()
+    missing = [f for f in fns if not hasattr(lib, f)]
+    assert not missing, missing
+    assert sorted(cdm.EXPORTS) == fns
+
+
+def test_version_and_status_strings(lib):
+    assert lib.cdm_version() == 1
+    assert lib.cdm_status_string(0) == b"ok"
+    assert b"infeasible" in lib.cdm_status_string(-6)
+    assert lib.cdm_status_string(12345) == b"unknown status"
+
+
+def _desc(**kw):
+    from paper_1902_08653_amd import cdm
+    d = dict(problem=0, precision=0, layout=0, engine=0, B=64, U=16, C=1, T_max=3, tol=0.0, nnz=0,
+             panel=0, flags=0)
+    d.update(kw)
+    return cdm.Desc(**d)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(T_max=0), -1),
+    (dict(tol=-1.0), -1),
+    (dict(tol=float("nan")), -1),
+    (dict(engine=7), -1),
+    (dict(precision=9), -3),
+    (dict(problem=5), -3),
+    (dict(B=0), -2),
+    (dict(U=0), -2),
+    (dict(B=65, C=2), -2),
+    (dict(problem=1, B=32, U=16, C=4), -6),      # downlink cluster with B_c = 8 < U
+])
+def test_create_rejects_invalid_descriptors_on_the_host(lib, kw, status):
+    h = C.c_void_p(1)
+    st = lib.cdm_create(C.byref(_desc(**kw)), C.byref(h))
+    assert st == status
+    assert h.value is None
+
+
+def test_null_arguments(lib):
+    assert lib.cdm_create(None, None) == -1
+    assert lib.cdm_solve(None, None, 0, None, None, None, 0.1, 1.0, 0.0, None, None, None, None) == -1
+    assert lib.cdm_destroy(None) == 0
+    m = np.array([4], np.int32)
+    assert lib.cdm_create_batched(C.byref(_desc()), 0, m.ctypes.data, m.ctypes.data,
+                                  C.byref(C.c_void_p())) == -1
+
+
+def test_info_record_layout():
+    from paper_1902_08653_amd import cdm
+    assert cdm.INFO_DTYPE.itemsize == 32
+    assert C.sizeof(cdm.Desc) == 56
