@@ -71,6 +71,9 @@ typedef enum cdm_engine { CDM_ENGINE_AUTO = 0, CDM_ENGINE_WG = 1, CDM_ENGINE_PAN
 
 /* Option bits for cdm_desc.flags. */
 #define CDM_F_RESIDUAL 1    /* also compute the FP64 normal-equation residual into cdm_info.resid */
+#define CDM_F_TIMING   2    /* record HIP events around each kernel stage of a solve (cdm_plan_timings) */
+#define CDM_F_AUTOTUNE 4    /* cdm_create_batched: time the candidate workgroup shapes on a sample of the
+                               batch's own shapes (synthetic values) and keep the fastest */
 
 typedef struct cdm_desc {
     int32_t problem;     /* cdm_problem */
@@ -180,6 +183,23 @@ int32_t cdm_residual(cdm_plan* plan, const void* H, int64_t ldh, const void* y, 
 /* Human-readable description of the plan's engine, tiles and workspace
  * (NUL-terminated, truncated to len bytes). */
 int32_t cdm_plan_describe(const cdm_plan* plan, char* buf, int32_t len);
+
+/* Stage durations of the most recent solve of a plan created with CDM_F_TIMING, in
+ * milliseconds, measured with HIP events on the solve's stream (call after the
+ * stream has been synchronised).  out_ms: host double[n]; stages, in order:
+ *   [0] preprocessing (column energies; panel Gram blocks and their inverses),
+ *   [1] init (r = y or y - H x0),
+ *   [2] the sweep kernel (all CD sweeps),
+ *   [3] finalisation and the optional FP64 residual.
+ * Returns the number of stages written (<= n) through *count.
+ * Errors: CDM_EINVAL (no timing flag, NULL), CDM_EHIP. */
+int32_t cdm_plan_timings(const cdm_plan* plan, double* out_ms, int32_t n, int32_t* count);
+
+/* Measurement utility (not part of the method): a plain coalesced device-to-device
+ * copy of `bytes` bytes (a multiple of 16) with the library's own kernel, used to
+ * calibrate HBM byte counters against a known traffic volume.
+ * src, dst: device, 16-byte aligned, non-overlapping. */
+int32_t cdm_stream_copy(const void* src, void* dst, int64_t bytes, void* stream);
 
 /* Release the plan and its device workspace. NULL is accepted. */
 int32_t cdm_destroy(cdm_plan* plan);

@@ -22,6 +22,7 @@ C128, C64, MIXED_BF16, MIXED_FP8 = 0, 1, 2, 3
 DENSE, CSR = 0, 1
 ENGINE_AUTO, ENGINE_WG, ENGINE_PANEL = 0, 1, 2
 F_RESIDUAL = 1
+F_TIMING = 2
 
 INFO_ZERO_COLUMN, INFO_NONFINITE, INFO_NOT_CONVERGED, INFO_TIMEOUT = 1, 2, 4, 8
 
@@ -50,7 +51,7 @@ assert INFO_DTYPE.itemsize == 32
 
 EXPORTS = ["cdm_version", "cdm_status_string", "cdm_last_error", "cdm_create", "cdm_solve",
            "cdm_create_batched", "cdm_batched_offsets", "cdm_solve_batched", "cdm_residual",
-           "cdm_plan_describe", "cdm_destroy"]
+           "cdm_plan_describe", "cdm_plan_timings", "cdm_stream_copy", "cdm_destroy"]
 
 _lib = None
 
@@ -82,6 +83,10 @@ def lib():
         L.cdm_residual.restype = i32
         L.cdm_plan_describe.argtypes = [P, C.c_char_p, i32]
         L.cdm_plan_describe.restype = i32
+        L.cdm_plan_timings.argtypes = [P, P, i32, P]
+        L.cdm_plan_timings.restype = i32
+        L.cdm_stream_copy.argtypes = [P, P, i64, P]
+        L.cdm_stream_copy.restype = i32
         L.cdm_destroy.argtypes = [P]
         L.cdm_destroy.restype = i32
         _lib = L
@@ -118,7 +123,7 @@ class Plan:
     """A plan for single solves (``cdm_create`` / ``cdm_solve`` / ``cdm_destroy``)."""
 
     def __init__(self, B, U, C_clusters=1, precision="c128", T_max=200, tol=0.0, engine="auto",
-                 panel=0, residual=False, problem="uplink", layout="dense", nnz=0):
+                 panel=0, residual=False, problem="uplink", layout="dense", nnz=0, timing=False):
         self.B, self.U, self.C = int(B), int(U), int(C_clusters)
         self.precision = precision
         self.problem = problem
@@ -126,7 +131,7 @@ class Plan:
                  precision=_PREC[precision], layout=DENSE if layout == "dense" else CSR,
                  engine=_ENGINE[engine], B=self.B, U=self.U, C=self.C, T_max=int(T_max),
                  tol=float(tol), nnz=int(nnz), panel=int(panel),
-                 flags=F_RESIDUAL if residual else 0)
+                 flags=(F_RESIDUAL if residual else 0) | (F_TIMING if timing else 0))
         self.desc = d
         h = C.c_void_p()
         _check(lib().cdm_create(C.byref(d), C.byref(h)), "cdm_create")
@@ -155,6 +160,15 @@ class Plan:
         _check(st, "cdm_solve")
         return x, info
 
+    STAGES = ("preprocess", "init", "sweeps", "finalize")
+
+    def timings(self):
+        """Stage durations (ms) of the last solve (plan created with timing=True)."""
+        out = np.zeros(4)
+        cnt = C.c_int32(0)
+        _check(lib().cdm_plan_timings(self._h, out.ctypes.data, 4, C.byref(cnt)), "cdm_plan_timings")
+        return dict(zip(self.STAGES, out[:cnt.value].tolist()))
+
     def residual(self, Hc, y, x, N0=0.1, Ex=1.0, out=None, stream=None):
         import torch
         if out is None:
@@ -173,6 +187,13 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def stream_copy(src, dst, stream=None):
+    """Library copy kernel (measurement utility): dst[:] = src[:] (same byte size)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _check(lib().cdm_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)), "cdm_stream_copy")
 
 
 class BatchedPlan:

@@ -82,10 +82,57 @@ __device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
 __device__ __forceinline__ void fence_release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void fence_acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
-// All threads of the workgroup: make this workgroup's prior global writes visible
-// device-wide, then thread 0 bumps *ctr.
+// Streaming (non-temporal) load of one complex value: read once, keep it out of
+// the way of data that is reused from L2.
+typedef double d2v_t __attribute__((ext_vector_type(2)));
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_nt(const double2* p) {
+    const d2v_t v = __builtin_nontemporal_load(reinterpret_cast<const d2v_t*>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld_nt(const float2* p) {
+    const f2v_t v = __builtin_nontemporal_load(reinterpret_cast<const f2v_t*>(p));
+    return make_float2(v.x, v.y);
+}
+
+// Device-coherent (agent-scope) relaxed loads and stores of one complex value.
+// Used for the small cross-workgroup buffers so that neither side needs an L2
+// write-back or invalidate: the stores write through to the device coherence
+// point and the loads read from it.
+__device__ __forceinline__ void st_dev(double2* p, double2 v) {
+    unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+    __hip_atomic_store(q + 0, __double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, __double_as_longlong(v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double2 ld_dev(const double2* p) {
+    const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
+    double2 v;
+    v.x = __longlong_as_double(__hip_atomic_load(q + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    v.y = __longlong_as_double(__hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    return v;
+}
+__device__ __forceinline__ void st_dev(float2* p, float2 v) {
+    unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+    union { float2 f; unsigned long long u; } c;
+    c.f = v;
+    __hip_atomic_store(q, c.u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float2 ld_dev(const float2* p) {
+    const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
+    union { float2 f; unsigned long long u; } c;
+    c.u = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return c.f;
+}
+
+// Wait until every vector memory operation this wave issued has completed (for
+// the device-coherent stores above: until they have reached the coherence point).
+__device__ __forceinline__ void wave_drain_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// All threads of the workgroup: after this workgroup's st_dev stores, bump *ctr.
+// Each wave drains its own stores, the barrier orders them before thread 0's
+// increment.
 __device__ __forceinline__ void wg_arrive(uint32_t* ctr) {
-    fence_release_agent();
+    wave_drain_vmem();
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -93,7 +140,8 @@ __device__ __forceinline__ void wg_arrive(uint32_t* ctr) {
 // All threads of the workgroup: wait until *ctr >= target.  Thread 0 polls with a
 // wall-clock bound; on time-out it raises *abort_flag, and any waiter that sees
 // the flag raised gives up too, so every wave of the grid reaches the kernel end.
-// Returns false when the wait was abandoned.  `flag_s` is one LDS word.
+// Returns false when the wait was abandoned.  Data published before the counter
+// was bumped must be read with ld_dev after this returns.  `flag_s` is one LDS word.
 __device__ __forceinline__ bool wg_wait_geq(const uint32_t* ctr, uint32_t target, uint32_t* abort_flag,
                                             uint64_t timeout_ticks, uint32_t* flag_s) {
     if (threadIdx.x == 0) {
@@ -113,7 +161,6 @@ __device__ __forceinline__ bool wg_wait_geq(const uint32_t* ctr, uint32_t target
         *flag_s = ok;
     }
     __syncthreads();
-    fence_acquire_agent();
     return *flag_s != 0;
 }
 

@@ -258,4 +258,43 @@ hipError_t launch_copy_resid(const double* src, cdm_info* info, int count, hipSt
     return hipGetLastError();
 }
 
+// stand-in values for timing runs: an integer hash of (seed, i) mapped to [-scale/2, scale/2)
+template <typename T>
+__global__ void k_fill_hash(T* __restrict__ p, int64_t n, uint32_t seed, double scale) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint32_t h = (uint32_t)i * 0x9e3779b1u ^ (uint32_t)(i >> 32) * 0x85ebca77u ^ seed;
+        h ^= h >> 16;
+        h *= 0x7feb352du;
+        h ^= h >> 15;
+        h *= 0x846ca68bu;
+        h ^= h >> 16;
+        p[i] = (T)(scale * ((double)h * (1.0 / 4294967296.0) - 0.5));
+    }
+}
+hipError_t launch_fill_hash(void* p, int64_t n, bool c128, uint32_t seed, double scale) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    if (blocks < 1) return hipSuccess;
+    if (c128)
+        hipLaunchKernelGGL(k_fill_hash<double>, dim3((unsigned)blocks), dim3(256), 0, 0, (double*)p, n, seed, scale);
+    else
+        hipLaunchKernelGGL(k_fill_hash<float>, dim3((unsigned)blocks), dim3(256), 0, 0, (float*)p, n, seed, scale);
+    return hipGetLastError();
+}
+
+// plain grid-stride 16-byte copy (counter calibration)
+__global__ void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t st) {
+    const int64_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const uint4*)src, (uint4*)dst, n);
+    return hipGetLastError();
+}
+
 }  // namespace cdm

@@ -65,10 +65,17 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
     const T lambda = (T)a.lambda;
     const int B = a.B, U = a.U;
 
+    constexpr int NE = KP * (KP + 1) / 2;       // packed lower triangle of M_K
+    constexpr int NS = PANEL_NT / KP;           // matvec slices per row
+    __shared__ V Ms[NE];
     __shared__ V bsh[KP];
     __shared__ V xsh[KP];
     __shared__ V dsh[KP];
-    __shared__ V axs[PANEL_NWV][RPL][64];
+    // the matvec partials and the axpy partials are live in disjoint phases
+    constexpr int SCR = (NS * KP > PANEL_NWV * RPL * 64) ? NS * KP : PANEL_NWV * RPL * 64;
+    __shared__ V scr[SCR];
+    V(*dpart)[KP] = reinterpret_cast<V(*)[KP]>(scr);
+    V(*axs)[RPL][64] = reinterpret_cast<V(*)[RPL][64]>(scr);
     __shared__ T red_s[PANEL_NWV][2];
     __shared__ uint32_t flag_s;
 
@@ -93,11 +100,32 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
 #pragma unroll
             for (int q = 0; q < RPL; ++q) {
                 const int row = row0 + lane + 64 * q;
-                nxt[c][q] = (col < U && row < B) ? a.H[(int64_t)col * a.ld + row] : czero<T>();
+                nxt[c][q] = (col < U && row < B) ? ld_nt(&a.H[(int64_t)col * a.ld + row])
+                                                 : czero<T>();
             }
         }
     };
     load_panel(0);
+    // stage the packed (D + L)^-1 of panel K into LDS, staged through registers
+    auto stage_M = [&](int K) {
+        constexpr int PER = (NE + PANEL_NT - 1) / PANEL_NT;
+        constexpr int CH = 9;
+        const V* src = a.M + (int64_t)K * NE;
+#pragma unroll
+        for (int c0 = 0; c0 < PER; c0 += CH) {
+            V buf[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int e = (c0 + k) * PANEL_NT + tid;
+                if (c0 + k < PER && e < NE) buf[k] = src[e];
+            }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int e = (c0 + k) * PANEL_NT + tid;
+                if (c0 + k < PER && e < NE) Ms[e] = buf[k];
+            }
+        }
+    };
 
     uint32_t seq = 0;
     int sweeps = 0;
@@ -131,11 +159,14 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
             wave_transpose_sum<T, NC>(pi, lane);
             if ((lane & ((1 << OWN_SHIFT) - 1)) == 0) {
                 const int j = wid + PANEL_NWV * (lane >> OWN_SHIFT);
-                a.part[((int64_t)par * KP + j) * P + w] = cmake<T>(pr[0], pi[0]);
+                st_dev(&a.part[((int64_t)par * KP + j) * P + w], cmake<T>(pr[0], pi[0]));
             }
             wg_arrive(ctrA);
             const int Kn = (K + 1 < a.npanels) ? K + 1 : 0;
-            if (!reducer) load_panel(Kn);
+            if (!reducer) {
+                load_panel(Kn);
+                stage_M(K);
+            }
 
             // 2. reducers: g_j = sum of the P partials (fixed order), b_j = g_j - lambda x_j
             if (reducer) {
@@ -144,7 +175,7 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
                     for (int j = w; j < KP; j += P) {
                         V acc = czero<T>();
                         for (int p = tid; p < P; p += PANEL_NT) {
-                            const V v = a.part[((int64_t)par * KP + j) * P + p];
+                            const V v = ld_dev(&a.part[((int64_t)par * KP + j) * P + p]);
                             acc.x += v.x;
                             acc.y += v.y;
                         }
@@ -167,14 +198,15 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
                             V b;
                             b.x = g.x - lambda * xo.x;
                             b.y = g.y - lambda * xo.y;
-                            a.gbuf[((int64_t)par * KP + j) * 2 + 0] = b;
-                            a.gbuf[((int64_t)par * KP + j) * 2 + 1] = xo;
+                            st_dev(&a.gbuf[((int64_t)par * KP + j) * 2 + 0], b);
+                            st_dev(&a.gbuf[((int64_t)par * KP + j) * 2 + 1], xo);
                         }
                         __syncthreads();
                     }
                 }
                 wg_arrive(ctrB);
                 load_panel(Kn);
+                stage_M(K);
             }
             if (!ok) break;
 
@@ -182,15 +214,37 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
             ok = wg_wait_geq(ctrB, (uint32_t)R * (seq + 1), abort_flag, a.timeout_ticks, &flag_s);
             if (!ok) break;
             for (int j = tid; j < KP; j += PANEL_NT) {
-                bsh[j] = a.gbuf[((int64_t)par * KP + j) * 2 + 0];
-                xsh[j] = a.gbuf[((int64_t)par * KP + j) * 2 + 1];
+                bsh[j] = ld_dev(&a.gbuf[((int64_t)par * KP + j) * 2 + 0]);
+                xsh[j] = ld_dev(&a.gbuf[((int64_t)par * KP + j) * 2 + 1]);
             }
             __syncthreads();
-            if (tid < KP) {
-                const V* Mk = a.M + (int64_t)K * KP * KP;
+            {
+                // delta_j = sum_{v <= j} M_jv b_v from the packed M_K in LDS (column v holds
+                // rows v..KP-1 at offset v*KP - v(v-1)/2); NS threads per row j, each over a
+                // contiguous slice of v
+                constexpr int SV = KP / NS;                // v per slice
+                const int j = tid % KP;
+                const int sl = tid / KP;
+                const int v0 = sl * SV;
+                const int v1 = min(v0 + SV - 1, j);
                 V d = czero<T>();
-                for (int v = 0; v <= tid; ++v) cfma(d, Mk[(int64_t)v * KP + tid], bsh[v]);
-                dsh[tid] = d;
+                int off = v0 * KP - (v0 * (v0 - 1)) / 2 + (j - v0);
+#pragma unroll 8
+                for (int v = v0; v <= v1; ++v) {
+                    cfma(d, Ms[off], bsh[v]);
+                    off += KP - v - 1;
+                }
+                dpart[sl][j] = d;
+                __syncthreads();
+                if (tid < KP) {
+                    V s = dpart[0][tid];
+#pragma unroll
+                    for (int k = 1; k < NS; ++k) {
+                        s.x += dpart[k][tid].x;
+                        s.y += dpart[k][tid].y;
+                    }
+                    dsh[tid] = s;
+                }
             }
             __syncthreads();
             if (reducer && tid == 0) {
@@ -299,7 +353,6 @@ hipError_t launch_panel(const PanelLaunch& L, hipStream_t st) {
     } else {
         if (L.kp == 128 && L.rpl == 1) return launch_panel_t<float, 128, 1>(L, st);
         if (L.kp == 128 && L.rpl == 2) return launch_panel_t<float, 128, 2>(L, st);
-        if (L.kp == 256 && L.rpl == 1) return launch_panel_t<float, 256, 1>(L, st);
     }
     return hipErrorInvalidValue;
 }
@@ -312,7 +365,6 @@ int panel_max_coresident(bool c128, int kp, int rpl) {
     } else {
         if (kp == 128 && rpl == 1) return coresident_t<float, 128, 1>();
         if (kp == 128 && rpl == 2) return coresident_t<float, 128, 2>();
-        if (kp == 256 && rpl == 1) return coresident_t<float, 256, 1>();
     }
     return 0;
 }
@@ -431,7 +483,7 @@ __global__ __launch_bounds__(256) void k_gram_invert(cv<T>* __restrict__ gpart, 
     __syncthreads();
     // 3. inverse of (D + L), row by row
     V* Mr = Mrow + (int64_t)K * kp * kp;
-    V* Mc = Mcm + (int64_t)K * kp * kp;
+    V* Mp = Mcm + (int64_t)K * (kp * (kp + 1) / 2);
     for (int u = 0; u < kp; ++u) {
         if (c < u) {
             const bool live = act[u] && act[c];
@@ -449,7 +501,7 @@ __global__ __launch_bounds__(256) void k_gram_invert(cv<T>* __restrict__ gpart, 
                 m.y = s.y / dsh[u];
             }
             Mr[(int64_t)u * kp + c] = m;
-            Mc[(int64_t)c * kp + u] = m;
+            if (c <= u) Mp[(int64_t)c * kp - ((int64_t)c * (c - 1)) / 2 + (u - c)] = m;
         }
         __syncthreads();
     }

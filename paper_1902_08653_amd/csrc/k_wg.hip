@@ -15,38 +15,18 @@
 
 namespace cdm {
 
+// One uplink instance, RPT rows per thread (m <= NT * RPT).
 template <typename T, int NT, int RPT>
-__global__ __launch_bounds__(NT) void k_cd_wg(const WgJob* __restrict__ jobs, int njobs,
-                                              const cv<T>* __restrict__ H, const cv<T>* __restrict__ Y,
-                                              const cv<T>* __restrict__ X0, cv<T>* __restrict__ X,
-                                              cdm_info* __restrict__ info, double lambda_d, int T_max,
-                                              double tol, const int* __restrict__ order,
-                                              uint32_t* __restrict__ queue, double* __restrict__ msum,
-                                              int64_t ld_arg) {
+__device__ __forceinline__ void cd_instance(const WgJob& jb, const cv<T>* __restrict__ H, const cv<T>* __restrict__ Y,
+                                            const cv<T>* __restrict__ X0, cv<T>* __restrict__ X,
+                                            cdm_info* __restrict__ info, T lambda, int T_max, double tol,
+                                            double* __restrict__ msum, int64_t ld_arg, unsigned char* smem_raw,
+                                            T (*red_s)[NT / 64][3], int& flag_s) {
     using V = cv<T>;
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
-    const T lambda = (T)lambda_d;
-
-    extern __shared__ unsigned char smem_raw[];
-    __shared__ T red_s[2][NW][3];
-    __shared__ int flag_s;
-    __shared__ int job_s;
-
-    for (;;) {
-        // next job from the shared queue; the queue hands out slots in `order`
-        // (largest instances first for uneven batches)
-        if (tid == 0) {
-            job_s = (int)atomicAdd(queue, 1u);
-            flag_s = 0;
-        }
-        __syncthreads();
-        const int jslot = job_s;
-        if (jslot >= njobs) return;
-        const int jid = order ? order[jslot] : jslot;
-        const WgJob jb = jobs[jid];
         // ---------------------------------------------------------------- one instance
         const int m = jb.m, n = jb.n;
         const int64_t ld = jb.ld > 0 ? jb.ld : ld_arg;   // ld <= 0: the solve's leading dimension
@@ -182,77 +162,272 @@ __global__ __launch_bounds__(NT) void k_cd_wg(const WgJob* __restrict__ jobs, in
             o.reserved = 0.0;
             info[jb.info_idx] = o;
         }
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_cd_wg(const WgJob* __restrict__ jobs, int njobs,
+                                              const cv<T>* __restrict__ H, const cv<T>* __restrict__ Y,
+                                              const cv<T>* __restrict__ X0, cv<T>* __restrict__ X,
+                                              cdm_info* __restrict__ info, double lambda_d, int T_max,
+                                              double tol, const int* __restrict__ order,
+                                              uint32_t* __restrict__ queue, double* __restrict__ msum,
+                                              int64_t ld_arg) {
+    constexpr int NW = NT / 64;
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ T red_s[2][NW][3];
+    __shared__ int flag_s;
+    __shared__ int job_s;
+    const int tid = threadIdx.x;
+    const T lambda = (T)lambda_d;
+    for (;;) {
+        // next job from the shared queue; the queue hands out slots in `order`
+        // (largest instances first for uneven batches)
+        if (tid == 0) {
+            job_s = (int)atomicAdd(queue, 1u);
+            flag_s = 0;
+        }
+        __syncthreads();
+        const int jslot = job_s;
+        if (jslot >= njobs) return;
+        const WgJob jb = jobs[order ? order[jslot] : jslot];
+        // row tile of this job, chosen on the host per size bucket
+        switch (jb.rpt) {
+            case 1: cd_instance<T, NT, 1>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s); break;
+            case 2: cd_instance<T, NT, 2>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s); break;
+            case 4: cd_instance<T, NT, 4>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s); break;
+            default: cd_instance<T, NT, 8>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s); break;
+        }
         __syncthreads();
     }
 }
 
+// ---------------------------------------------------------------------------
+// Algorithm 2 (decentralized ZF precoding by CD, eq. (4)), one workgroup per
+// cluster.  The local precoded vector x_c (B_c entries) stays in VGPRs with the
+// same row ownership as the uplink residual; per user u:
+//   a = h_u^H x (partial, wave butterfly, LDS)      e = p_u a - p_u s_u
+//   x <- x - e p_u h_u
+// with p_u = 1/||h_u|| computed from the same column load in the first sweep
+// (Algorithm 2 preprocessing: hbar_u = p_u h_u, sbar_u = p_u s_u).  After the
+// sweeps: x_c <- rho_c x_c / ||x_c|| with rho_c = rho / sqrt(C) (Sec. IV-B).
 template <typename T, int NT, int RPT>
-static hipError_t launch_wg_t(const WgLaunch& L, hipStream_t st) {
-    const size_t shm = (size_t)L.n_max * 2 * sizeof(cv<T>);
-    hipLaunchKernelGGL((k_cd_wg<T, NT, RPT>), dim3(L.grid), dim3(NT), shm, st, L.jobs, L.njobs,
-                       (const cv<T>*)L.H, (const cv<T>*)L.Y, (const cv<T>*)L.X0, (cv<T>*)L.X, L.info,
-                       L.lambda, L.T_max, L.tol, L.order, L.queue, L.msum, L.ld);
-    return hipGetLastError();
+__device__ __forceinline__ void zf_instance(const WgJob& jb, const cv<T>* __restrict__ H, const cv<T>* __restrict__ S,
+                                            cv<T>* __restrict__ X, cdm_info* __restrict__ info, int T_max,
+                                            double tol, double rho_c, int64_t ld_arg, unsigned char* smem_raw,
+                                            T (*red_s)[NT / 64][3], double* nrm_s, int& flag_s) {
+    using V = cv<T>;
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+        const int m = jb.m, n = jb.n;
+        const int64_t ld = jb.ld > 0 ? jb.ld : ld_arg;
+        const V* Hj = H + jb.h_off;
+        T* p_s = reinterpret_cast<T*>(smem_raw);   // p_u (0 marks an inactive user)
+
+        V x[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) x[q] = czero<T>();
+
+        int sweeps = 0;
+        double Ssum = 0.0, Xn = 0.0;
+        for (int t = 1; t <= T_max; ++t) {
+            Ssum = 0.0;
+            V hc[RPT], hn[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = tid + q * NT;
+                hc[q] = (i < m) ? Hj[i] : czero<T>();
+            }
+            for (int u = 0; u < n; ++u) {
+                if (u + 1 < n) {
+#pragma unroll
+                    for (int q = 0; q < RPT; ++q) {
+                        const int i = tid + q * NT;
+                        hn[q] = (i < m) ? Hj[(int64_t)(u + 1) * ld + i] : czero<T>();
+                    }
+                }
+                T ar = 0, ai = 0, ee = 0;
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    ar += hc[q].x * x[q].x + hc[q].y * x[q].y;
+                    ai += hc[q].x * x[q].y - hc[q].y * x[q].x;
+                    if (t == 1) ee += hc[q].x * hc[q].x + hc[q].y * hc[q].y;
+                }
+                ar = wave_allsum(ar);
+                ai = wave_allsum(ai);
+                if (t == 1) ee = wave_allsum(ee);
+                const T pu_old = (t > 1) ? p_s[u] : T(0);
+                const V su = S[jb.y_off + u];
+                const int par = u & 1;
+                if (lane == 0) {
+                    red_s[par][wid][0] = ar;
+                    red_s[par][wid][1] = ai;
+                    red_s[par][wid][2] = ee;
+                }
+                __syncthreads();
+                V a = czero<T>();
+                T e = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    a.x += red_s[par][w][0];
+                    a.y += red_s[par][w][1];
+                    if (t == 1) e += red_s[par][w][2];
+                }
+                T pu = pu_old;
+                if (t == 1) {
+                    pu = (e > T(0)) ? T(1) / sqrt(e) : T(0);
+                    if (!(e > T(0)) && tid == 0) flag_s |= CDM_INFO_ZERO_COLUMN;
+                    if (tid == 0) p_s[u] = pu;
+                }
+                // err = hbar_u^H x - sbar_u ;  x <- x - err * hbar_u
+                V err;
+                err.x = pu * a.x - pu * su.x;
+                err.y = pu * a.y - pu * su.y;
+                V ep;
+                ep.x = err.x * pu;
+                ep.y = err.y * pu;
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) cfms(x[q], hc[q], ep);
+                if (pu != T(0)) Ssum += cabs2d(err);
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) hc[q] = hn[q];
+            }
+            // ||x||^2 (fixed-order block reduction, identical in every thread)
+            double xs = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) xs += cabs2d(x[q]);
+            xs = wave_allsum(xs);
+            if (lane == 0) nrm_s[wid] = xs;
+            __syncthreads();
+            Xn = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) Xn += nrm_s[w];
+            __syncthreads();
+            sweeps = t;
+            if (tol > 0.0 && sqrt(Ssum) <= tol * sqrt(Xn)) break;
+        }
+        // power scaling x_c <- rho_c x_c / ||x_c|| (rho_c <= 0: none; x_c = 0 stays 0)
+        const double nrm = sqrt(Xn);
+        const double sc = (rho_c > 0.0 && nrm > 0.0) ? rho_c / nrm : 1.0;
+        int nf = 0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = tid + q * NT;
+            if (i < m) {
+                V v;
+                v.x = (T)((double)x[q].x * sc);
+                v.y = (T)((double)x[q].y * sc);
+                if (!isfinite(v.x) || !isfinite(v.y)) nf = 1;
+                X[jb.x_off + i] = v;
+            }
+        }
+        if (nf) atomicOr(&flag_s, CDM_INFO_NONFINITE);
+        __syncthreads();
+        if (tid == 0) {
+            const double rel = (Xn > 0.0) ? sqrt(Ssum / Xn) : (Ssum > 0.0 ? INFINITY : 0.0);
+            int fl = flag_s;
+            if (tol > 0.0 && !(rel <= tol)) fl |= CDM_INFO_NOT_CONVERGED;
+            cdm_info o;
+            o.sweeps = sweeps;
+            o.flags = fl;
+            o.rel_step = rel;
+            o.resid = -1.0;
+            o.reserved = 0.0;
+            info[jb.info_idx] = o;
+        }
 }
 
 template <typename T, int NT>
-static hipError_t launch_wg_rpt(const WgLaunch& L, hipStream_t st) {
-    switch (L.rpt) {
-        case 1: return launch_wg_t<T, NT, 1>(L, st);
-        case 2: return launch_wg_t<T, NT, 2>(L, st);
-        case 4: return launch_wg_t<T, NT, 4>(L, st);
-        case 8: return launch_wg_t<T, NT, 8>(L, st);
-        default: return hipErrorInvalidValue;
+__global__ __launch_bounds__(NT) void k_zf_wg(const WgJob* __restrict__ jobs, int njobs,
+                                              const cv<T>* __restrict__ H, const cv<T>* __restrict__ S,
+                                              cv<T>* __restrict__ X, cdm_info* __restrict__ info, int T_max,
+                                              double tol, double rho_c, uint32_t* __restrict__ queue,
+                                              int64_t ld_arg) {
+    constexpr int NW = NT / 64;
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ T red_s[2][NW][3];
+    __shared__ double nrm_s[NW];
+    __shared__ int flag_s;
+    __shared__ int job_s;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            job_s = (int)atomicAdd(queue, 1u);
+            flag_s = 0;
+        }
+        __syncthreads();
+        const int jslot = job_s;
+        if (jslot >= njobs) return;
+        const WgJob jb = jobs[jslot];
+        switch (jb.rpt) {
+            case 1: zf_instance<T, NT, 1>(jb, H, S, X, info, T_max, tol, rho_c, ld_arg, smem_raw, red_s, nrm_s, flag_s); break;
+            case 2: zf_instance<T, NT, 2>(jb, H, S, X, info, T_max, tol, rho_c, ld_arg, smem_raw, red_s, nrm_s, flag_s); break;
+            case 4: zf_instance<T, NT, 4>(jb, H, S, X, info, T_max, tol, rho_c, ld_arg, smem_raw, red_s, nrm_s, flag_s); break;
+            default: zf_instance<T, NT, 8>(jb, H, S, X, info, T_max, tol, rho_c, ld_arg, smem_raw, red_s, nrm_s, flag_s); break;
+        }
+        __syncthreads();
     }
 }
 
-hipError_t launch_wg(const WgLaunch& L, hipStream_t st) {
-    if (L.nt == 256) return L.c128 ? launch_wg_rpt<double, 256>(L, st) : launch_wg_rpt<float, 256>(L, st);
-    if (L.nt == 1024) return L.c128 ? launch_wg_rpt<double, 1024>(L, st) : launch_wg_rpt<float, 1024>(L, st);
-    return hipErrorInvalidValue;
+template <typename T, int NT> static hipError_t launch_zf_t(const WgLaunch& L, hipStream_t st) {
+    const size_t shm = (size_t)L.n_max * sizeof(T);
+    hipLaunchKernelGGL((k_zf_wg<T, NT>), dim3(L.grid), dim3(NT), shm, st, L.jobs, L.njobs, (const cv<T>*)L.H,
+                       (const cv<T>*)L.Y, (cv<T>*)L.X, L.info, L.T_max, L.tol, L.rho_c, L.queue, L.ld);
+    return hipGetLastError();
 }
 
-size_t wg_lds_bytes(int n_max, bool c128) { return (size_t)n_max * 2 * (c128 ? 16 : 8); }
-
-template <typename T, int NT, int RPT> static hipError_t set_lds_t(size_t bytes) {
-    return hipFuncSetAttribute((const void*)k_cd_wg<T, NT, RPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
+template <typename T, int NT> static hipError_t launch_wg_t(const WgLaunch& L, hipStream_t st) {
+    const size_t shm = (size_t)L.n_max * 2 * sizeof(cv<T>);
+    hipLaunchKernelGGL((k_cd_wg<T, NT>), dim3(L.grid), dim3(NT), shm, st, L.jobs, L.njobs, (const cv<T>*)L.H,
+                       (const cv<T>*)L.Y, (const cv<T>*)L.X0, (cv<T>*)L.X, L.info, L.lambda, L.T_max, L.tol,
+                       L.order, L.queue, L.msum, L.ld);
+    return hipGetLastError();
 }
-template <typename T, int NT, int RPT> static int occ_t(size_t bytes) {
+
+template <typename T, int NT> static hipError_t set_lds_t(size_t bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_cd_wg<T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_zf_wg<T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+template <typename T, int NT> static int occ_t(size_t bytes) {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cd_wg<T, NT, RPT>, NT, bytes) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cd_wg<T, NT>, NT, bytes) != hipSuccess) return 0;
     return per;
 }
-#define CDM_WG_DISPATCH(FN, c128, nt, rpt, ...)                                              \
-    do {                                                                                     \
-        if (c128) {                                                                          \
-            if (nt == 256 && rpt == 1) return FN<double, 256, 1>(__VA_ARGS__);               \
-            if (nt == 256 && rpt == 2) return FN<double, 256, 2>(__VA_ARGS__);               \
-            if (nt == 256 && rpt == 4) return FN<double, 256, 4>(__VA_ARGS__);               \
-            if (nt == 256 && rpt == 8) return FN<double, 256, 8>(__VA_ARGS__);               \
-            if (nt == 1024 && rpt == 1) return FN<double, 1024, 1>(__VA_ARGS__);             \
-            if (nt == 1024 && rpt == 2) return FN<double, 1024, 2>(__VA_ARGS__);             \
-            if (nt == 1024 && rpt == 4) return FN<double, 1024, 4>(__VA_ARGS__);             \
-            if (nt == 1024 && rpt == 8) return FN<double, 1024, 8>(__VA_ARGS__);             \
-        } else {                                                                             \
-            if (nt == 256 && rpt == 1) return FN<float, 256, 1>(__VA_ARGS__);                \
-            if (nt == 256 && rpt == 2) return FN<float, 256, 2>(__VA_ARGS__);                \
-            if (nt == 256 && rpt == 4) return FN<float, 256, 4>(__VA_ARGS__);                \
-            if (nt == 256 && rpt == 8) return FN<float, 256, 8>(__VA_ARGS__);                \
-            if (nt == 1024 && rpt == 1) return FN<float, 1024, 1>(__VA_ARGS__);              \
-            if (nt == 1024 && rpt == 2) return FN<float, 1024, 2>(__VA_ARGS__);              \
-            if (nt == 1024 && rpt == 4) return FN<float, 1024, 4>(__VA_ARGS__);              \
-            if (nt == 1024 && rpt == 8) return FN<float, 1024, 8>(__VA_ARGS__);              \
-        }                                                                                    \
+
+#define CDM_WG_DISPATCH(FN, c128, nt, ...)                                   \
+    do {                                                                     \
+        if (c128) {                                                          \
+            if (nt == 128) return FN<double, 128>(__VA_ARGS__);              \
+            if (nt == 256) return FN<double, 256>(__VA_ARGS__);              \
+            if (nt == 512) return FN<double, 512>(__VA_ARGS__);              \
+            if (nt == 1024) return FN<double, 1024>(__VA_ARGS__);            \
+        } else {                                                             \
+            if (nt == 128) return FN<float, 128>(__VA_ARGS__);               \
+            if (nt == 256) return FN<float, 256>(__VA_ARGS__);               \
+            if (nt == 512) return FN<float, 512>(__VA_ARGS__);               \
+            if (nt == 1024) return FN<float, 1024>(__VA_ARGS__);             \
+        }                                                                    \
     } while (0)
 
-hipError_t wg_set_lds_limit(bool c128, int nt, int rpt, size_t bytes) {
-    CDM_WG_DISPATCH(set_lds_t, c128, nt, rpt, bytes);
+hipError_t launch_wg(const WgLaunch& L, hipStream_t st) {
+    CDM_WG_DISPATCH(launch_wg_t, L.c128, L.nt, L, st);
     return hipErrorInvalidValue;
 }
-int wg_occupancy(bool c128, int nt, int rpt, size_t bytes) {
-    CDM_WG_DISPATCH(occ_t, c128, nt, rpt, bytes);
+hipError_t launch_zf(const WgLaunch& L, hipStream_t st) {
+    CDM_WG_DISPATCH(launch_zf_t, L.c128, L.nt, L, st);
+    return hipErrorInvalidValue;
+}
+hipError_t wg_set_lds_limit(bool c128, int nt, size_t bytes) {
+    CDM_WG_DISPATCH(set_lds_t, c128, nt, bytes);
+    return hipErrorInvalidValue;
+}
+int wg_occupancy(bool c128, int nt, size_t bytes) {
+    CDM_WG_DISPATCH(occ_t, c128, nt, bytes);
     return 0;
 }
+size_t wg_lds_bytes(int n_max, bool c128) { return (size_t)n_max * 2 * (c128 ? 16 : 8); }
 
 }  // namespace cdm

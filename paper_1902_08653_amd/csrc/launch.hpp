@@ -19,13 +19,12 @@ struct WgJob {
     int32_t m;        // rows (antennas)
     int32_t n;        // columns (users)
     int32_t info_idx; // cdm_info record to write
-    int32_t pad;
+    int32_t rpt;      // rows per thread for this job (1, 2, 4, 8): m <= nt * rpt
 };
 
 struct WgLaunch {
     bool c128;
-    int nt;           // threads per workgroup (256 or 1024)
-    int rpt;          // rows per thread (1, 2, 4, 8): m <= nt * rpt
+    int nt;           // threads per workgroup (128, 256, 512, 1024)
     int grid;         // workgroups (persistent; they pull jobs from `queue`)
     int n_max;        // largest n of any job (sizes the LDS)
     const WgJob* jobs;
@@ -42,11 +41,14 @@ struct WgLaunch {
     double tol;
     double* msum;     // optional: sum_u m_u per job (cluster fusion weights)
     int64_t ld;       // leading dimension for jobs whose own ld is <= 0
+    double rho_c;     // downlink: per-cluster power rho/sqrt(C) (<= 0: no scaling)
 };
 hipError_t launch_wg(const WgLaunch& L, hipStream_t st);
+// Algorithm 2 (downlink ZF precoding), same job and tile conventions; Y is s (U).
+hipError_t launch_zf(const WgLaunch& L, hipStream_t st);
 size_t wg_lds_bytes(int n_max, bool c128);
-hipError_t wg_set_lds_limit(bool c128, int nt, int rpt, size_t bytes);
-int wg_occupancy(bool c128, int nt, int rpt, size_t bytes);
+hipError_t wg_set_lds_limit(bool c128, int nt, size_t bytes);
+int wg_occupancy(bool c128, int nt, size_t bytes);
 
 // Fusion of C local estimates (Sec. III): x = sum_c lambda_c x_c with
 // lambda_c = sigma_c^-2 / sum_c' sigma_c'^-2 and sigma_c^2 = (N0/U) sum_u m_{u,c}.
@@ -64,7 +66,7 @@ struct PanelLaunch {
     int64_t ld;
     const void* r0;      // initial residual (B)
     void* x;             // in: x^(0) (U), out: x^(T)
-    const void* M;       // [npanels][kp][kp] column-major inverses of (D + L) per panel
+    const void* M;       // [npanels][kp*(kp+1)/2] packed lower (D + L)^-1 per panel, column by column
     void* part;          // [2][kp][P] partial dot products
     void* gbuf;          // [2][kp][2] reduced right-hand sides and old x
     uint32_t* ctr;       // [0] partial arrivals, [1] reducer arrivals, [2] abort, [3] status word
@@ -85,7 +87,7 @@ struct GramLaunch {
     const void* H;
     int64_t ld;
     void* gpart;         // [nsplit][npanels][kp][kp] partial Gram blocks (row-major, lower part)
-    void* M;             // out: [npanels][kp][kp] column-major (D + L)^-1
+    void* M;             // out: [npanels][kp*(kp+1)/2] packed lower (D + L)^-1, column by column
     double* e;           // out: column energies ||h_u||^2 (U), FP64
     uint32_t* status;    // ORed CDM_INFO_ZERO_COLUMN
     double lambda;
@@ -129,5 +131,9 @@ hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t st);
 hipError_t launch_finalize(const void* x, int U, bool c128, const uint32_t* status, cdm_info* info,
                            hipStream_t st);
 hipError_t launch_copy_resid(const double* src, cdm_info* info, int count, hipStream_t st);
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
+// Fill n reals (double if c128 else float) with scale * (u - 1/2), u a hash of (seed, i) in
+// [0, 1): stand-in values for timing runs.
+hipError_t launch_fill_hash(void* p, int64_t n, bool c128, uint32_t seed, double scale);
 
 }  // namespace cdm

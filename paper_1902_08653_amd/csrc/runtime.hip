@@ -58,7 +58,7 @@ struct cdm_plan {
     size_t esz = 16;          // bytes per complex element
     int engine = CDM_ENGINE_WG;
     // WG engine
-    int wg_nt = 256, wg_rpt = 1, wg_grid = 1, n_max = 1;
+    int wg_nt = 256, wg_rpt = 1, wg_grid = 1, n_max = 1;   // wg_rpt: rows per thread of the largest job
     size_t wg_lds = 0;
     int njobs = 0;
     // PANEL engine
@@ -87,7 +87,22 @@ struct cdm_plan {
     // batched layout
     std::vector<int64_t> H_off, y_off, x_off;
     std::string text;
+    // stage timing (CDM_F_TIMING)
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool timed = false;
 };
+
+static void ev_record(cdm_plan* p, int i, hipStream_t st) {
+    if (p->timed) (void)hipEventRecord(p->ev[i], st);
+}
+
+static int32_t setup_timing(cdm_plan* p) {
+    if (!(p->d.flags & CDM_F_TIMING)) return CDM_OK;
+    for (int i = 0; i < 5; ++i)
+        if (hipEventCreate(&p->ev[i]) != hipSuccess) return CDM_EHIP;
+    p->timed = true;
+    return CDM_OK;
+}
 
 static int32_t validate_common(const cdm_desc* d) {
     if (!d) return CDM_EINVAL;
@@ -127,32 +142,28 @@ static int32_t alloc_ws(cdm_plan* p, size_t bytes) {
     return CDM_OK;
 }
 
-// choose the WG-engine tile for rows m_max
-static bool wg_tile(int m_max, int* nt, int* rpt) {
-    static const int nts[2] = {256, 1024};
-    static const int rpts[4] = {1, 2, 4, 8};
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 4; ++b)
-            if (nts[a] * rpts[b] >= m_max) {
-                // prefer 256 threads up to 2048 rows, then 1024 threads
-                if (nts[a] == 256 || m_max > 2048) {
-                    *nt = nts[a];
-                    *rpt = rpts[b];
-                    return true;
-                }
-            }
-    return false;
+// rows per thread for an instance of m rows on nt threads (0: too large)
+static int rpt_for(int m, int nt) {
+    for (int r = 1; r <= 8; r *= 2)
+        if ((int64_t)nt * r >= m) return r;
+    return 0;
 }
 
-static int32_t setup_wg(cdm_plan* p, int m_max, int n_max, int njobs) {
-    if (!wg_tile(m_max, &p->wg_nt, &p->wg_rpt)) return CDM_ESHAPE;
+// threads per workgroup for single-instance (cluster) plans; the FP64 kernel is kept
+// at <= 512 threads (its 8-rows-per-thread tile does not fit 1024-thread register budgets)
+static int wg_nt_single(int m, bool c128) { return m <= 2048 ? 256 : (c128 ? 512 : 1024); }
+
+static int32_t setup_wg(cdm_plan* p, int m_max, int n_max, int njobs, int nt) {
+    if (rpt_for(m_max, nt) == 0) return CDM_ESHAPE;
+    p->wg_nt = nt;
+    p->wg_rpt = rpt_for(m_max, nt);
     p->n_max = std::max(1, n_max);
     p->wg_lds = wg_lds_bytes(p->n_max, p->c128);
     if (p->wg_lds + 2048 > kLdsMax) return CDM_ESHAPE;
     if (p->wg_lds > 64 * 1024) {
-        if (wg_set_lds_limit(p->c128, p->wg_nt, p->wg_rpt, p->wg_lds) != hipSuccess) return CDM_ESHAPE;
+        if (wg_set_lds_limit(p->c128, nt, p->wg_lds) != hipSuccess) return CDM_ESHAPE;
     }
-    const int occ = std::max(1, wg_occupancy(p->c128, p->wg_nt, p->wg_rpt, p->wg_lds));
+    const int occ = std::max(1, wg_occupancy(p->c128, nt, p->wg_lds));
     p->wg_grid = std::max(1, std::min(njobs, occ * p->ncu));
     p->njobs = njobs;
     return CDM_OK;
@@ -188,8 +199,9 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
     if (d.B < 1 || d.U < 1 || d.C < 1 || d.B % d.C) return CDM_ESHAPE;
     const int Bc = d.B / d.C;
     if (d.problem == CDM_DOWNLINK_ZF && Bc < d.U) return CDM_EINFEASIBLE;
-    if (d.problem != CDM_UPLINK_LMMSE || d.layout != CDM_DENSE ||
-        (d.precision != CDM_C128 && d.precision != CDM_C64))
+    if (d.layout != CDM_DENSE || (d.precision != CDM_C128 && d.precision != CDM_C64)) return CDM_ENOTIMPL;
+    if (d.problem == CDM_DOWNLINK_ZF &&
+        (d.engine == CDM_ENGINE_PANEL || Bc > (d.precision == CDM_C128 ? kWgMaxRows / 2 : kWgMaxRows)))
         return CDM_ENOTIMPL;
 
     cdm_plan* p = new cdm_plan();
@@ -206,8 +218,9 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
     int engine = d.engine;
     const double elems = (double)d.B * d.U;
     if (engine == CDM_ENGINE_AUTO) engine = (d.C == 1 && d.B >= 2048 && elems >= 4.0e6) ? CDM_ENGINE_PANEL : CDM_ENGINE_WG;
+    if (d.problem == CDM_DOWNLINK_ZF) engine = CDM_ENGINE_WG;
     if (engine == CDM_ENGINE_PANEL && d.C != 1) engine = CDM_ENGINE_WG;
-    if (engine == CDM_ENGINE_WG && Bc > kWgMaxRows) engine = CDM_ENGINE_PANEL;
+    if (engine == CDM_ENGINE_WG && Bc > (p->c128 ? kWgMaxRows / 2 : kWgMaxRows)) engine = CDM_ENGINE_PANEL;
     if (engine == CDM_ENGINE_PANEL && d.C != 1) {
         delete p;
         return CDM_ESHAPE;
@@ -220,26 +233,26 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
            o_msum = 0, o_rpart = 0;
     p->nchunk = std::max(1, std::min(64, (d.U + 127) / 128));
     if (engine == CDM_ENGINE_WG) {
-        st = setup_wg(p, Bc, d.U, d.C);
+        st = setup_wg(p, Bc, d.U, d.C, wg_nt_single(Bc, p->c128));
         if (st) {
             delete p;
             return st;
         }
         o_jobs = ar.take(sizeof(WgJob) * d.C);
-        if (d.C > 1) {
+        if (d.C > 1 && d.problem == CDM_UPLINK_LMMSE) {
             o_xloc = ar.take(p->esz * (size_t)d.C * d.U);
             o_msum = ar.take(sizeof(double) * d.C);
         }
     } else {
-        // panel width and rows per lane: keep one 64*rpl-row block per co-resident workgroup
-        const int kps_c128[2] = {128, 64};
-        const int kps_c64[2] = {256, 128};
-        const int* kps = p->c128 ? kps_c128 : kps_c64;
+        // panel width and rows per lane: one 64*rpl-row block per co-resident workgroup
+        // (the packed panel inverse must fit in LDS next to the sweep's own buffers)
+        static const int cand_c128[2][2] = {{128, 1}, {64, 2}};
+        static const int cand_c64[2][2] = {{128, 1}, {128, 2}};
+        const int(*cand)[2] = p->c128 ? cand_c128 : cand_c64;
         bool found = false;
         for (int i = 0; i < 2 && !found; ++i) {
-            const int kp = kps[i];
+            const int kp = cand[i][0], rpl = cand[i][1];
             if (d.panel && d.panel != kp) continue;
-            const int rpl = (i == 0) ? 1 : 2;
             const int P = (d.B + 64 * rpl - 1) / (64 * rpl);
             const int maxc = panel_max_coresident(p->c128, kp, rpl);
             if (P <= maxc) {
@@ -281,7 +294,7 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
     p->ctr = (uint32_t*)(b + o_ctr);
     if (engine == CDM_ENGINE_WG) {
         p->jobs = (WgJob*)(b + o_jobs);
-        if (d.C > 1) {
+        if (d.C > 1 && d.problem == CDM_UPLINK_LMMSE) {
             p->xloc = b + o_xloc;
             p->msum = (double*)(b + o_msum);
         }
@@ -290,13 +303,14 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
             WgJob& j = jobs[c];
             j.h_off = (int64_t)c * Bc;
             j.ld = 0;   // the solve's ldh
-            j.y_off = (int64_t)c * Bc;
+            const bool dl = d.problem == CDM_DOWNLINK_ZF;
+            j.y_off = dl ? 0 : (int64_t)c * Bc;        // downlink: s is broadcast to every cluster
             j.x0_off = 0;
-            j.x_off = (int64_t)c * d.U;
+            j.x_off = dl ? (int64_t)c * Bc : (int64_t)c * d.U;
             j.m = Bc;
             j.n = d.U;
             j.info_idx = c;
-            j.pad = 0;
+            j.rpt = rpt_for(Bc, p->wg_nt);
         }
         if (hipMemcpy(p->jobs, jobs.data(), sizeof(WgJob) * d.C, hipMemcpyHostToDevice) != hipSuccess) {
             (void)hipFree(p->ws);
@@ -329,6 +343,11 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
                  "\"workgroups\": %d, \"npanels\": %d, \"gram_splits\": %d, \"workspace\": %zu}",
                  p->c128 ? "c128" : "c64", d.B, d.U, p->kp, p->rpl, p->P, p->npanels, p->nsplit, p->ws_bytes);
     p->text = buf;
+    st = setup_timing(p);
+    if (st) {
+        cdm_destroy(p);
+        return st;
+    }
     *plan = p;
     return CDM_OK;
 }
@@ -360,21 +379,55 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
     (void)colidx;
     (void)rho;
     if (!p || p->batched || !H || !rhs || !x || !info) return CDM_EINVAL;
-    if (!(Ex > 0.0) || !(N0 >= 0.0) || !std::isfinite(N0) || !std::isfinite(Ex)) return CDM_EINVAL;
     const cdm_desc& d = p->d;
+    if (d.problem == CDM_UPLINK_LMMSE && (!(Ex > 0.0) || !(N0 >= 0.0) || !std::isfinite(N0) || !std::isfinite(Ex)))
+        return CDM_EINVAL;
     if (ldh < d.B) return CDM_ESHAPE;
     const double lambda = N0 / Ex;
     const int Bc = d.B / d.C;
-    if (lambda == 0.0 && Bc < d.U) return CDM_EINFEASIBLE;
     hipStream_t st = (hipStream_t)stream;
     cdm_info* inf = (cdm_info*)info;
-
-    HIP_TRY(launch_zero_u32(p->ctr, 16, st));
-    if (p->engine == CDM_ENGINE_WG) {
+    if (d.problem == CDM_DOWNLINK_ZF) {
+        if (x0) return CDM_EINVAL;
+        ev_record(p, 0, st);
+        HIP_TRY(launch_zero_u32(p->ctr, 16, st));
+        ev_record(p, 1, st);
+        ev_record(p, 2, st);
         WgLaunch L;
         L.c128 = p->c128;
         L.nt = p->wg_nt;
-        L.rpt = p->wg_rpt;
+        L.grid = p->wg_grid;
+        L.n_max = p->n_max;
+        L.jobs = p->jobs;
+        L.njobs = d.C;
+        L.order = nullptr;
+        L.queue = p->ctr + 4;
+        L.H = H;
+        L.Y = rhs;
+        L.X0 = nullptr;
+        L.X = x;
+        L.info = inf;
+        L.lambda = 0.0;
+        L.T_max = d.T_max;
+        L.tol = d.tol;
+        L.msum = nullptr;
+        L.ld = ldh;
+        L.rho_c = rho > 0.0 ? rho / std::sqrt((double)d.C) : 0.0;
+        HIP_TRY(launch_zf(L, st));
+        ev_record(p, 3, st);
+        ev_record(p, 4, st);
+        return CDM_OK;
+    }
+    if (lambda == 0.0 && Bc < d.U) return CDM_EINFEASIBLE;
+
+    ev_record(p, 0, st);
+    HIP_TRY(launch_zero_u32(p->ctr, 16, st));
+    if (p->engine == CDM_ENGINE_WG) {
+        ev_record(p, 1, st);
+        ev_record(p, 2, st);
+        WgLaunch L;
+        L.c128 = p->c128;
+        L.nt = p->wg_nt;
         L.grid = p->wg_grid;
         L.n_max = p->n_max;
         L.jobs = p->jobs;
@@ -391,7 +444,9 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         L.tol = d.tol;
         L.msum = d.C > 1 ? p->msum : nullptr;
         L.ld = ldh;
+        L.rho_c = 0.0;
         HIP_TRY(launch_wg(L, st));
+        ev_record(p, 3, st);
         if (d.C > 1) HIP_TRY(launch_fuse(p->c128, p->xloc, p->msum, d.C, d.U, N0, x, st));
     } else {
         GramLaunch G;
@@ -409,6 +464,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         G.status = p->ctr + 3;
         G.lambda = lambda;
         HIP_TRY(launch_gram(G, st));
+        ev_record(p, 1, st);
         InitLaunch I;
         I.c128 = p->c128;
         I.B = d.B;
@@ -422,6 +478,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         I.rpart = p->rpart;
         I.nchunk = p->nchunk;
         HIP_TRY(launch_init(I, st));
+        ev_record(p, 2, st);
         PanelLaunch L;
         L.c128 = p->c128;
         L.kp = p->kp;
@@ -444,6 +501,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         L.tol = d.tol;
         L.timeout_ticks = p->timeout_ticks;
         HIP_TRY(launch_panel(L, st));
+        ev_record(p, 3, st);
         HIP_TRY(launch_finalize(x, d.U, p->c128, p->ctr + 2, inf, st));
     }
     if (d.flags & CDM_F_RESIDUAL) {
@@ -451,6 +509,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         if (s2) return s2;
         HIP_TRY(launch_copy_resid(p->res_out, inf, 1, st));
     }
+    ev_record(p, 4, st);
     return CDM_OK;
 }
 
@@ -460,6 +519,60 @@ int32_t cdm_residual(cdm_plan* p, const void* H, int64_t ldh, const void* y, dou
     if (!(Ex > 0.0) || !(N0 >= 0.0)) return CDM_EINVAL;
     if (ldh < p->d.B) return CDM_ESHAPE;
     return run_resid(p, H, ldh, y, N0 / Ex, x, out, (hipStream_t)stream);
+}
+
+// Time one persistent launch of the batched engine with nt threads per workgroup
+// on `jobs` (device), 2 fixed sweeps; returns milliseconds (< 0 on failure).
+static double time_batched(cdm_plan* p, int nt, int m_max, int n_max, WgJob* jobs_d, const std::vector<WgJob>& jobs,
+                           int* order_d, void* H, void* Y, void* X, cdm_info* info, uint32_t* ctr) {
+    const int njobs = (int)jobs.size();
+    std::vector<WgJob> jj = jobs;
+    for (auto& j : jj) j.rpt = rpt_for(j.m, nt);
+    if (hipMemcpy(jobs_d, jj.data(), sizeof(WgJob) * njobs, hipMemcpyHostToDevice) != hipSuccess) return -1.0;
+    const size_t lds = wg_lds_bytes(std::max(1, n_max), p->c128);
+    if (lds > 64 * 1024 && wg_set_lds_limit(p->c128, nt, lds) != hipSuccess) return -1.0;
+    const int occ = std::max(1, wg_occupancy(p->c128, nt, lds));
+    WgLaunch L;
+    L.c128 = p->c128;
+    L.nt = nt;
+    L.grid = std::max(1, std::min(njobs, occ * p->ncu));
+    L.n_max = std::max(1, n_max);
+    L.jobs = jobs_d;
+    L.njobs = njobs;
+    L.order = order_d;
+    L.queue = ctr + 4;
+    L.H = H;
+    L.Y = Y;
+    L.X0 = nullptr;
+    L.X = X;
+    L.info = info;
+    L.lambda = 0.1;
+    L.T_max = 2;
+    L.tol = 0.0;
+    L.msum = nullptr;
+    L.ld = 1;
+    L.rho_c = 0.0;
+    (void)m_max;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.0;
+    }
+    double best = -1.0;
+    for (int rep = 0; rep < 3; ++rep) {
+        if (launch_zero_u32(ctr, 16, nullptr) != hipSuccess) break;
+        (void)hipEventRecord(e0, nullptr);
+        if (launch_wg(L, nullptr) != hipSuccess) break;
+        (void)hipEventRecord(e1, nullptr);
+        if (hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0 && (best < 0 || ms < best)) best = ms;   // first run warms up
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
 }
 
 int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m, const int32_t* n,
@@ -490,11 +603,6 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
         return st;
     }
     p->engine = CDM_ENGINE_WG;
-    st = setup_wg(p, m_max, n_max, batch);
-    if (st) {
-        delete p;
-        return st;
-    }
     p->H_off.resize(batch);
     p->y_off.resize(batch);
     p->x_off.resize(batch);
@@ -513,7 +621,7 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
         j.m = m[i];
         j.n = n[i];
         j.info_idx = i;
-        j.pad = 0;
+        j.rpt = 0;
         ho += (int64_t)m[i] * n[i];
         yo += m[i];
         xo += n[i];
@@ -536,18 +644,87 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
     p->ctr = (uint32_t*)(p->ws + o_ctr);
     p->jobs = (WgJob*)(p->ws + o_jobs);
     p->order = (int*)(p->ws + o_order);
+
+    // ---- tile choice: threads per workgroup for the whole launch; rows per
+    // thread then follow per job.  With CDM_F_AUTOTUNE each candidate is timed
+    // on a spread sample of this batch's shapes (synthetic values).
+    static const int cands[3] = {128, 256, 512};
+    int nt = 0;
+    std::string tune = "null";
+    if (d.flags & CDM_F_AUTOTUNE) {
+        const int S = std::min(batch, 1024);
+        std::vector<WgJob> sj(S);
+        std::vector<int> sorder(S);
+        int64_t sh = 0, sy = 0, sx = 0;
+        int sm_max = 0, sn_max = 0;
+        for (int k = 0; k < S; ++k) {
+            const int i = order[(int64_t)k * batch / S];   // spread over the LPT order
+            WgJob j = jobs[i];
+            j.h_off = sh;
+            j.ld = j.m;
+            j.y_off = sy;
+            j.x0_off = sx;
+            j.x_off = sx;
+            j.info_idx = k;
+            sj[k] = j;
+            sorder[k] = k;
+            sh += (int64_t)j.m * j.n;
+            sy += j.m;
+            sx += j.n;
+            sm_max = std::max(sm_max, j.m);
+            sn_max = std::max(sn_max, j.n);
+        }
+        void *Hs = nullptr, *Ys = nullptr, *Xs = nullptr, *aux = nullptr;
+        bool ok = hipMalloc(&Hs, p->esz * (size_t)sh) == hipSuccess && hipMalloc(&Ys, p->esz * (size_t)sy) == hipSuccess &&
+                  hipMalloc(&Xs, p->esz * (size_t)sx) == hipSuccess &&
+                  hipMalloc(&aux, 64 + sizeof(cdm_info) * S + sizeof(WgJob) * S + sizeof(int) * S) == hipSuccess;
+        if (ok) {
+            uint32_t* tctr = (uint32_t*)aux;
+            cdm_info* tinfo = (cdm_info*)((char*)aux + 64);
+            WgJob* tjobs = (WgJob*)((char*)tinfo + sizeof(cdm_info) * S);
+            int* tord = (int*)((char*)tjobs + sizeof(WgJob) * S);
+            ok = hipMemcpy(tord, sorder.data(), sizeof(int) * S, hipMemcpyHostToDevice) == hipSuccess &&
+                 launch_fill_hash(Hs, (int64_t)sh * 2, p->c128, 0x9e3779b9u, 1.0 / std::sqrt((double)sm_max)) == hipSuccess &&
+                 launch_fill_hash(Ys, (int64_t)sy * 2, p->c128, 0x7f4a7c15u, 1.0) == hipSuccess;
+            double best = -1.0;
+            char tb[256];
+            int tl = snprintf(tb, sizeof(tb), "{");
+            for (int c = 0; ok && c < 3; ++c) {
+                if (rpt_for(m_max, cands[c]) == 0) continue;
+                const double ms = time_batched(p, cands[c], sm_max, sn_max, tjobs, sj, tord, Hs, Ys, Xs, tinfo, tctr);
+                tl += snprintf(tb + tl, sizeof(tb) - tl, "%s\"%d\": %.3f", tl > 1 ? ", " : "", cands[c], ms);
+                if (ms > 0 && (best < 0 || ms < best)) {
+                    best = ms;
+                    nt = cands[c];
+                }
+            }
+            snprintf(tb + tl, sizeof(tb) - tl, "}");
+            tune = tb;
+        }
+        if (Hs) (void)hipFree(Hs);
+        if (Ys) (void)hipFree(Ys);
+        if (Xs) (void)hipFree(Xs);
+        if (aux) (void)hipFree(aux);
+        (void)hipGetLastError();
+    }
+    if (nt == 0) nt = rpt_for(m_max, 256) ? 256 : (rpt_for(m_max, 512) ? 512 : 1024);
+    st = setup_wg(p, m_max, n_max, batch, nt);
+    if (st) {
+        cdm_destroy(p);
+        return st;
+    }
+    for (auto& j : jobs) j.rpt = rpt_for(j.m, nt);
     if (hipMemcpy(p->jobs, jobs.data(), sizeof(WgJob) * batch, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->order, order.data(), sizeof(int) * batch, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(p->ws);
-        delete p;
+        cdm_destroy(p);
         return CDM_EHIP;
     }
-    char buf[512];
+    char buf[768];
     snprintf(buf, sizeof(buf),
              "{\"engine\": \"wg-batched\", \"precision\": \"%s\", \"batch\": %d, \"m_max\": %d, \"n_max\": %d, "
-             "\"nt\": %d, \"rpt\": %d, \"grid\": %d, \"lds\": %zu, \"workspace\": %zu}",
-             p->c128 ? "c128" : "c64", batch, m_max, n_max, p->wg_nt, p->wg_rpt, p->wg_grid, p->wg_lds,
-             p->ws_bytes);
+             "\"nt\": %d, \"grid\": %d, \"lds\": %zu, \"workspace\": %zu, \"autotune_ms\": %s}",
+             p->c128 ? "c128" : "c64", batch, m_max, n_max, p->wg_nt, p->wg_grid, p->wg_lds, p->ws_bytes,
+             tune.c_str());
     p->text = buf;
     *plan = p;
     return CDM_OK;
@@ -571,7 +748,6 @@ int32_t cdm_solve_batched(cdm_plan* p, const void* H, const void* y, double N0, 
     WgLaunch L;
     L.c128 = p->c128;
     L.nt = p->wg_nt;
-    L.rpt = p->wg_rpt;
     L.grid = p->wg_grid;
     L.n_max = p->n_max;
     L.jobs = p->jobs;
@@ -588,6 +764,7 @@ int32_t cdm_solve_batched(cdm_plan* p, const void* H, const void* y, double N0, 
     L.tol = p->d.tol;
     L.msum = nullptr;
     L.ld = 1;
+    L.rho_c = 0.0;
     HIP_TRY(launch_wg(L, st));
     return CDM_OK;
 }
@@ -598,8 +775,28 @@ int32_t cdm_plan_describe(const cdm_plan* p, char* buf, int32_t len) {
     return CDM_OK;
 }
 
+int32_t cdm_plan_timings(const cdm_plan* p, double* out_ms, int32_t n, int32_t* count) {
+    if (!p || !out_ms || !count || !p->timed) return CDM_EINVAL;
+    int k = 0;
+    for (int i = 0; i < 4 && k < n; ++i, ++k) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]));
+        out_ms[k] = ms;
+    }
+    *count = k;
+    return CDM_OK;
+}
+
+int32_t cdm_stream_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+    if (!src || !dst || bytes < 0 || (bytes & 15)) return CDM_EINVAL;
+    HIP_TRY(launch_stream_copy(src, dst, bytes, (hipStream_t)stream));
+    return CDM_OK;
+}
+
 int32_t cdm_destroy(cdm_plan* p) {
     if (!p) return CDM_OK;
+    for (int i = 0; i < 5; ++i)
+        if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
     if (p->ws) (void)hipFree(p->ws);
     delete p;
     return CDM_OK;

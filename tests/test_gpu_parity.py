@@ -194,3 +194,47 @@ def test_batched_uneven(dev, orc, prec):
         ref = orc.local_cd(Ho, yo_, 0.1, T_max=4)
         assert rec["sweeps"][k] == 4
         assert relerr(x[xo[k]:xo[k] + n[k]], ref["x"]) <= TOL[prec], k
+
+
+# ----------------------------------------------------------------------------- Algorithm 2
+
+def run_dl(dev, H, s, prec="c128", T=3, tol=0.0, rho=1.0, C=1):
+    from paper_1902_08653_amd import cdm
+    B, U = H.shape
+    plan = cdm.Plan(B, U, C_clusters=C, precision=prec, T_max=T, tol=tol, problem="downlink")
+    Hd, sd = to_dev(H, s, prec, dev)
+    x, info = plan.solve(Hd, sd, rho=rho)
+    torch.cuda.synchronize()
+    out = x.cpu().numpy().astype(np.complex128), cdm.parse_info(info)
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("B,U,C,T", [(128, 8, 4, 3), (256, 8, 8, 2), (32, 8, 1, 4), (1000, 300, 2, 3),
+                                     (4096, 1000, 1, 2)])
+def test_downlink_zf_precoding(dev, orc, prec, B, U, C, T):
+    rng = np.random.default_rng(B + U + C)
+    H = (rng.standard_normal((B, U)) + 1j * rng.standard_normal((B, U))) / np.sqrt(2)
+    s = inputs.qam16_symbols(rng.integers(0, 2, size=(U, 4)))
+    x, info = run_dl(dev, H, s, prec, T=T, rho=1.5, C=C)
+    Ho, so = oracle_inputs(H, s, prec)
+    ref = orc.downlink_cd(Ho, so, 1.5, T_max=T, C_clusters=C)
+    assert np.all(info["sweeps"] == T) and np.all(info["flags"] == 0)
+    assert relerr(x, ref["x"]) <= TOL[prec], relerr(x, ref["x"])
+    Bc = B // C
+    for c in range(C):
+        assert abs(np.linalg.norm(x[c * Bc:(c + 1) * Bc]) - 1.5 / np.sqrt(C)) <= 10 * TOL[prec]
+
+
+def test_downlink_converges_to_zf(dev, orc):
+    rng = np.random.default_rng(3)
+    B, U = 64, 8
+    H = (rng.standard_normal((B, U)) + 1j * rng.standard_normal((B, U))) / np.sqrt(2)
+    s = (rng.standard_normal(U) + 1j * rng.standard_normal(U)) / np.sqrt(2)
+    x, info = run_dl(dev, H, s, "c128", T=500, tol=1e-13, rho=0.0)
+    ref = H @ np.linalg.solve(H.conj().T @ H, s)
+    assert info["rel_step"][0] <= 1e-13
+    assert relerr(x, ref) <= 1e-11
+    ro = orc.local_zf_cd(H, s, T_max=500, tol=1e-13)
+    assert abs(int(info["sweeps"][0]) - ro["sweeps"]) <= 1
