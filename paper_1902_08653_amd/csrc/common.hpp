@@ -164,4 +164,48 @@ __device__ __forceinline__ bool wg_wait_geq(const uint32_t* ctr, uint32_t target
     return *flag_s != 0;
 }
 
+// Per-workgroup arrival flags: workgroup w publishes `value` in flags[w] with one
+// device-coherent store (no read-modify-write, so arrivals never serialise on one
+// address).  Call from all threads after this workgroup's st_dev stores.
+__device__ __forceinline__ void wg_publish(uint32_t* flags, int w, uint32_t value) {
+    wave_drain_vmem();
+    __syncthreads();
+    if (threadIdx.x == 0) st_relaxed(&flags[w], value);
+}
+
+// All threads: wait until flags[0..count) are all >= target.  Wave 0 polls every
+// flag with one vector pass per round and a wave vote; time-out and abort as in
+// wg_wait_geq.  `flag_s` is one LDS word.
+__device__ __forceinline__ bool wg_wait_flags(const uint32_t* flags, int count, uint32_t target,
+                                              uint32_t* abort_flag, uint64_t timeout_ticks, uint32_t* flag_s) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        uint32_t ok = 1;
+        uint64_t t0 = 0;
+        bool started = false;
+        for (;;) {
+            bool mine = true;
+            for (int i = lane; i < count; i += 64) mine = mine && (ld_relaxed(&flags[i]) >= target);
+            if (__all(mine)) break;
+            if (!started) {
+                t0 = wall_clock64();
+                started = true;
+            }
+            if (ld_relaxed(abort_flag)) {
+                ok = 0;
+                break;
+            }
+            if (wall_clock64() - t0 > timeout_ticks) {
+                if (lane == 0) st_relaxed(abort_flag, 1u);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (lane == 0) *flag_s = ok;
+    }
+    __syncthreads();
+    return *flag_s != 0;
+}
+
 }  // namespace cdm

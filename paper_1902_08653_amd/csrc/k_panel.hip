@@ -29,7 +29,7 @@
 
 namespace cdm {
 
-constexpr int PANEL_NT = 512;   // 8 waves per workgroup
+constexpr int PANEL_NT = 512;   // 8 waves per workgroup, one workgroup per CU
 constexpr int PANEL_NWV = PANEL_NT / 64;
 
 template <typename T> struct PanelArgs {
@@ -53,8 +53,6 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
     using V = cv<T>;
     constexpr int NC = KP / PANEL_NWV;          // panel columns per wave
     static_assert(NC >= 1 && NC <= 64 && (NC & (NC - 1)) == 0, "bad panel split");
-    constexpr int LOG_NC = (NC == 1) ? 0 : (NC == 2) ? 1 : (NC == 4) ? 2 : (NC == 8) ? 3 : (NC == 16) ? 4 : (NC == 32) ? 5 : 6;
-    constexpr int OWN_SHIFT = 6 - LOG_NC;       // lane >> OWN_SHIFT = column slot after the transpose-reduce
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -79,9 +77,11 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
     __shared__ T red_s[PANEL_NWV][2];
     __shared__ uint32_t flag_s;
 
-    uint32_t* ctrA = a.ctr + 0;
-    uint32_t* ctrB = a.ctr + 1;
+    // ctr layout: [2] abort, [3] status, [16, 16+P) partial-arrival flags,
+    // [16+P, 16+P+KP) reducer flags; flag value = panel sequence number + 1
     uint32_t* abort_flag = a.ctr + 2;
+    uint32_t* flagsA = a.ctr + 16;
+    uint32_t* flagsB = a.ctr + 16 + P;
 
     const int row0 = w * 64 * RPL;
     V r[RPL];
@@ -94,22 +94,27 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
     V tile[NC][RPL];
     V nxt[NC][RPL];
     auto load_panel = [&](int K) {
+        // running per-lane pointer: column K*KP + wid + NWV*c, row row0 + lane + 64q
+        const int col0 = K * KP + wid;
+        const V* hp = a.H + (int64_t)col0 * a.ld + row0 + lane;
+        const int64_t cstep = (int64_t)PANEL_NWV * a.ld;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const int col = K * KP + wid + PANEL_NWV * c;
+            const bool cok = col0 + PANEL_NWV * c < U;
 #pragma unroll
             for (int q = 0; q < RPL; ++q) {
-                const int row = row0 + lane + 64 * q;
-                nxt[c][q] = (col < U && row < B) ? ld_nt(&a.H[(int64_t)col * a.ld + row])
-                                                 : czero<T>();
+                const bool rok = row0 + lane + 64 * q < B;
+                nxt[c][q] = (cok && rok) ? ld_nt(hp + 64 * q) : czero<T>();
             }
+            hp += cstep;
         }
     };
     load_panel(0);
     // stage the packed (D + L)^-1 of panel K into LDS, staged through registers
     auto stage_M = [&](int K) {
         constexpr int PER = (NE + PANEL_NT - 1) / PANEL_NT;
-        constexpr int CH = 9;
+        // staged while the prefetch tile is not yet loaded, so its registers are free
+        constexpr int CH = (sizeof(T) == 8) ? 8 : 16;
         const V* src = a.M + (int64_t)K * NE;
 #pragma unroll
         for (int c0 = 0; c0 < PER; c0 += CH) {
@@ -143,34 +148,45 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
 #pragma unroll
                 for (int q = 0; q < RPL; ++q) tile[c][q] = nxt[c][q];
 
-            // 1. partial g_K = H_K^H r over this workgroup's rows
-            T pr[NC], pi[NC];
+            // 1. partial g_K = H_K^H r over this workgroup's rows, in column halves to
+            //    keep the per-lane partials small
+            {
+                constexpr int NH = (NC >= 2) ? NC / 2 : 1;
+                constexpr int LOG_NH = (NH == 1) ? 0 : (NH == 2) ? 1 : (NH == 4) ? 2 : (NH == 8) ? 3 : (NH == 16) ? 4 : 5;
+                constexpr int HSHIFT = 6 - LOG_NH;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                pr[c] = T(0);
-                pi[c] = T(0);
+                for (int h0 = 0; h0 < NC; h0 += NH) {
+                    T pr[NH], pi[NH];
 #pragma unroll
-                for (int q = 0; q < RPL; ++q) {
-                    pr[c] += tile[c][q].x * r[q].x + tile[c][q].y * r[q].y;
-                    pi[c] += tile[c][q].x * r[q].y - tile[c][q].y * r[q].x;
+                    for (int c = 0; c < NH; ++c) {
+                        pr[c] = T(0);
+                        pi[c] = T(0);
+#pragma unroll
+                        for (int q = 0; q < RPL; ++q) {
+                            pr[c] += tile[h0 + c][q].x * r[q].x + tile[h0 + c][q].y * r[q].y;
+                            pi[c] += tile[h0 + c][q].x * r[q].y - tile[h0 + c][q].y * r[q].x;
+                        }
+                    }
+                    wave_transpose_sum<T, NH>(pr, lane);
+                    wave_transpose_sum<T, NH>(pi, lane);
+                    if ((lane & ((1 << HSHIFT) - 1)) == 0) {
+                        const int j = wid + PANEL_NWV * (h0 + (lane >> HSHIFT));
+                        st_dev(&a.part[((int64_t)par * KP + j) * P + w], cmake<T>(pr[0], pi[0]));
+                    }
                 }
             }
-            wave_transpose_sum<T, NC>(pr, lane);
-            wave_transpose_sum<T, NC>(pi, lane);
-            if ((lane & ((1 << OWN_SHIFT) - 1)) == 0) {
-                const int j = wid + PANEL_NWV * (lane >> OWN_SHIFT);
-                st_dev(&a.part[((int64_t)par * KP + j) * P + w], cmake<T>(pr[0], pi[0]));
-            }
-            wg_arrive(ctrA);
+            wg_publish(flagsA, w, seq + 1);
             const int Kn = (K + 1 < a.npanels) ? K + 1 : 0;
             if (!reducer) {
-                load_panel(Kn);
+                // M_K first: waiting for its loads must not wait for the tile stream
+                // (vector loads complete in issue order)
                 stage_M(K);
+                load_panel(Kn);
             }
 
             // 2. reducers: g_j = sum of the P partials (fixed order), b_j = g_j - lambda x_j
             if (reducer) {
-                ok = wg_wait_geq(ctrA, (uint32_t)P * (seq + 1), abort_flag, a.timeout_ticks, &flag_s);
+                ok = wg_wait_flags(flagsA, P, seq + 1, abort_flag, a.timeout_ticks, &flag_s);
                 if (ok) {
                     for (int j = w; j < KP; j += P) {
                         V acc = czero<T>();
@@ -204,14 +220,14 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
                         __syncthreads();
                     }
                 }
-                wg_arrive(ctrB);
-                load_panel(Kn);
+                wg_publish(flagsB, w, seq + 1);
                 stage_M(K);
+                load_panel(Kn);
             }
             if (!ok) break;
 
             // 3. everyone: delta_K = M_K b_K, x_K += delta_K, r -= H_K delta_K
-            ok = wg_wait_geq(ctrB, (uint32_t)R * (seq + 1), abort_flag, a.timeout_ticks, &flag_s);
+            ok = wg_wait_flags(flagsB, R, seq + 1, abort_flag, a.timeout_ticks, &flag_s);
             if (!ok) break;
             for (int j = tid; j < KP; j += PANEL_NT) {
                 bsh[j] = ld_dev(&a.gbuf[((int64_t)par * KP + j) * 2 + 0]);
@@ -227,13 +243,19 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
                 const int sl = tid / KP;
                 const int v0 = sl * SV;
                 const int v1 = min(v0 + SV - 1, j);
-                V d = czero<T>();
+                V d0 = czero<T>(), d1 = czero<T>();
                 int off = v0 * KP - (v0 * (v0 - 1)) / 2 + (j - v0);
-#pragma unroll 8
-                for (int v = v0; v <= v1; ++v) {
-                    cfma(d, Ms[off], bsh[v]);
+                int v = v0;
+                for (; v + 1 <= v1; v += 2) {
+                    cfma(d0, Ms[off], bsh[v]);
                     off += KP - v - 1;
+                    cfma(d1, Ms[off], bsh[v + 1]);
+                    off += KP - v - 2;
                 }
+                if (v <= v1) cfma(d0, Ms[off], bsh[v]);
+                V d;
+                d.x = d0.x + d1.x;
+                d.y = d0.y + d1.y;
                 dpart[sl][j] = d;
                 __syncthreads();
                 if (tid < KP) {

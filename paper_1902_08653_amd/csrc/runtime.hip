@@ -34,6 +34,7 @@ void set_err(const char* where, hipError_t e) {
     } while (0)
 
 constexpr int kWgMaxRows = 8192;      // 1024 threads x 8 rows
+constexpr int kCtrWords = 2048;       // control words: counters, abort/status, arrival flags
 constexpr size_t kLdsMax = 160 * 1024;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -228,7 +229,7 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
     p->engine = engine;
 
     Arena ar;
-    const size_t o_ctr = ar.take(64);
+    const size_t o_ctr = ar.take(kCtrWords * 4);
     size_t o_jobs = 0, o_r0 = 0, o_M = 0, o_gpart = 0, o_part = 0, o_gbuf = 0, o_e = 0, o_xloc = 0,
            o_msum = 0, o_rpart = 0;
     p->nchunk = std::max(1, std::min(64, (d.U + 127) / 128));
@@ -255,7 +256,7 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
             if (d.panel && d.panel != kp) continue;
             const int P = (d.B + 64 * rpl - 1) / (64 * rpl);
             const int maxc = panel_max_coresident(p->c128, kp, rpl);
-            if (P <= maxc) {
+            if (P <= maxc && 16 + P + kp <= kCtrWords) {
                 p->kp = kp;
                 p->rpl = rpl;
                 p->P = P;
@@ -421,7 +422,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
     if (lambda == 0.0 && Bc < d.U) return CDM_EINFEASIBLE;
 
     ev_record(p, 0, st);
-    HIP_TRY(launch_zero_u32(p->ctr, 16, st));
+    HIP_TRY(launch_zero_u32(p->ctr, p->engine == CDM_ENGINE_PANEL ? kCtrWords : 16, st));
     if (p->engine == CDM_ENGINE_WG) {
         ev_record(p, 1, st);
         ev_record(p, 2, st);
