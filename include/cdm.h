@@ -70,7 +70,9 @@ typedef enum cdm_layout { CDM_DENSE = 0, CDM_CSR = 1 } cdm_layout;
 typedef enum cdm_engine { CDM_ENGINE_AUTO = 0, CDM_ENGINE_WG = 1, CDM_ENGINE_PANEL = 2 } cdm_engine;
 
 /* Option bits for cdm_desc.flags. */
-#define CDM_F_RESIDUAL 1    /* also compute the FP64 normal-equation residual into cdm_info.resid */
+#define CDM_F_RESIDUAL 1    /* also compute the FP64 normal-equation residual into cdm_info.resid
+                               (single solves: after the sweeps; batched: per instance, in the
+                               same persistent launch) */
 #define CDM_F_TIMING   2    /* record HIP events around each kernel stage of a solve (cdm_plan_timings) */
 #define CDM_F_AUTOTUNE 4    /* cdm_create_batched: time the candidate workgroup shapes on a sample of the
                                batch's own shapes (synthetic values) and keep the fastest */
@@ -87,7 +89,7 @@ typedef struct cdm_desc {
     int32_t T_max;       /* sweep cap T_max of Algorithms 1 and 2, 1..100000 */
     double tol;          /* 0: run exactly T_max sweeps (the paper's mode); > 0: stop after
                             sweep t once sqrt(sum_u |delta_u|^2) <= tol * ||x^(t)||_2 */
-    int64_t nnz;         /* CDM_CSR: number of stored entries of H (capacity), else 0 */
+    int64_t nnz;         /* CDM_CSR: number of stored entries of H (exactly rowptr[B]), else 0 */
     int32_t panel;       /* CDM_ENGINE_PANEL panel width (64 or 128); 0 = choose */
     int32_t flags;       /* CDM_F_* */
 } cdm_desc;
@@ -173,6 +175,15 @@ int32_t cdm_batched_offsets(const cdm_plan* plan, int64_t* H_off, int64_t* y_off
  * captured into a HIP graph. */
 int32_t cdm_solve_batched(cdm_plan* plan, const void* H, const void* y, double N0, double Ex,
                           const void* x0, void* x, void* info, void* stream);
+
+/* Sparse plans (CDM_CSR): the column-compressed form the solve walks, so that it
+ * can be checked.  Transposes the CSR input (val, rowptr, colidx as in cdm_solve)
+ * and copies the result to the caller's device buffers (any may be NULL):
+ * colptr_out int32[U+1], rowidx_out int32[nnz], cval_out complex[nnz].  Within a
+ * column, entries are ordered by increasing row (the form is unique).
+ * Errors: CDM_EINVAL (not a CSR plan, NULL input), CDM_EHIP. */
+int32_t cdm_csr_transpose(cdm_plan* plan, const void* val, const int32_t* rowptr, const int32_t* colidx,
+                          int32_t* colptr_out, int32_t* rowidx_out, void* cval_out, void* stream);
 
 /* FP64 stationarity check of eq. (1) for a dense uplink plan:
  * *out (device double) = ||H^H (y - H x) - lambda x|| / ||H^H y||, lambda = N0/Ex.

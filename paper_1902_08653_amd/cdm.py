@@ -23,6 +23,7 @@ DENSE, CSR = 0, 1
 ENGINE_AUTO, ENGINE_WG, ENGINE_PANEL = 0, 1, 2
 F_RESIDUAL = 1
 F_TIMING = 2
+F_AUTOTUNE = 4
 
 INFO_ZERO_COLUMN, INFO_NONFINITE, INFO_NOT_CONVERGED, INFO_TIMEOUT = 1, 2, 4, 8
 
@@ -51,7 +52,7 @@ assert INFO_DTYPE.itemsize == 32
 
 EXPORTS = ["cdm_version", "cdm_status_string", "cdm_last_error", "cdm_create", "cdm_solve",
            "cdm_create_batched", "cdm_batched_offsets", "cdm_solve_batched", "cdm_residual",
-           "cdm_plan_describe", "cdm_plan_timings", "cdm_stream_copy", "cdm_destroy"]
+           "cdm_plan_describe", "cdm_plan_timings", "cdm_stream_copy", "cdm_csr_transpose", "cdm_destroy"]
 
 _lib = None
 
@@ -87,6 +88,8 @@ def lib():
         L.cdm_plan_timings.restype = i32
         L.cdm_stream_copy.argtypes = [P, P, i64, P]
         L.cdm_stream_copy.restype = i32
+        L.cdm_csr_transpose.argtypes = [P, P, P, P, P, P, P, P]
+        L.cdm_csr_transpose.restype = i32
         L.cdm_destroy.argtypes = [P]
         L.cdm_destroy.restype = i32
         _lib = L
@@ -169,6 +172,17 @@ class Plan:
         _check(lib().cdm_plan_timings(self._h, out.ctypes.data, 4, C.byref(cnt)), "cdm_plan_timings")
         return dict(zip(self.STAGES, out[:cnt.value].tolist()))
 
+    def csr_transpose(self, val, rowptr, colidx, stream=None):
+        """Column-compressed copy of a CSR channel (sparse plans): (colptr, rowidx, cval)."""
+        import torch
+        nnz = int(self.desc.nnz)
+        colptr = torch.empty(self.U + 1, dtype=torch.int32, device=val.device)
+        rowidx = torch.empty(max(nnz, 1), dtype=torch.int32, device=val.device)
+        cval = torch.empty(max(nnz, 1), dtype=val.dtype, device=val.device)
+        _check(lib().cdm_csr_transpose(self._h, _ptr(val), _ptr(rowptr), _ptr(colidx), _ptr(colptr),
+                                       _ptr(rowidx), _ptr(cval), _stream(stream)), "cdm_csr_transpose")
+        return colptr, rowidx[:nnz], cval[:nnz]
+
     def residual(self, Hc, y, x, N0=0.1, Ex=1.0, out=None, stream=None):
         import torch
         if out is None:
@@ -199,7 +213,7 @@ def stream_copy(src, dst, stream=None):
 class BatchedPlan:
     """A plan for many independent uplink instances of uneven size."""
 
-    def __init__(self, m, n, precision="c64", T_max=200, tol=0.0):
+    def __init__(self, m, n, precision="c64", T_max=200, tol=0.0, residual=False, autotune=False):
         m = np.ascontiguousarray(m, dtype=np.int32)
         n = np.ascontiguousarray(n, dtype=np.int32)
         self.batch = int(m.shape[0])
@@ -207,7 +221,7 @@ class BatchedPlan:
         self.precision = precision
         d = Desc(problem=UPLINK_LMMSE, precision=_PREC[precision], layout=DENSE, engine=ENGINE_WG,
                  B=int(m.max()), U=int(n.max()), C=1, T_max=int(T_max), tol=float(tol), nnz=0,
-                 panel=0, flags=0)
+                 panel=0, flags=(F_RESIDUAL if residual else 0) | (F_AUTOTUNE if autotune else 0))
         h = C.c_void_p()
         _check(lib().cdm_create_batched(C.byref(d), self.batch, m.ctypes.data, n.ctypes.data,
                                         C.byref(h)), "cdm_create_batched")

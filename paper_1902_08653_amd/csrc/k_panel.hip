@@ -547,6 +547,20 @@ template <typename T> static hipError_t launch_gram_t(const GramLaunch& L, hipSt
     return hipGetLastError();
 }
 
+hipError_t launch_gram_invert(bool c128, void* gpart, int nsplit, int npanels, int kp, int U, double lambda, void* M,
+                              double* e, uint32_t* status, hipStream_t st) {
+    if (c128) {
+        using V = cv<double>;
+        hipLaunchKernelGGL(k_gram_invert<double>, dim3(npanels), dim3(kp), 0, st, (V*)gpart, nsplit, npanels, kp, U,
+                           lambda, (V*)M, (V*)gpart + (int64_t)npanels * kp * kp, e, status);
+    } else {
+        using V = cv<float>;
+        hipLaunchKernelGGL(k_gram_invert<float>, dim3(npanels), dim3(kp), 0, st, (V*)gpart, nsplit, npanels, kp, U,
+                           lambda, (V*)M, (V*)gpart + (int64_t)npanels * kp * kp, e, status);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_gram(const GramLaunch& L, hipStream_t st) {
     return L.c128 ? launch_gram_t<double>(L, st) : launch_gram_t<float>(L, st);
 }

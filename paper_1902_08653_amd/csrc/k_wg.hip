@@ -21,7 +21,8 @@ __device__ __forceinline__ void cd_instance(const WgJob& jb, const cv<T>* __rest
                                             const cv<T>* __restrict__ X0, cv<T>* __restrict__ X,
                                             cdm_info* __restrict__ info, T lambda, int T_max, double tol,
                                             double* __restrict__ msum, int64_t ld_arg, unsigned char* smem_raw,
-                                            T (*red_s)[NT / 64][3], int& flag_s) {
+                                            T (*red_s)[NT / 64][3], int& flag_s, int resid,
+                                            double (*red64)[NT / 64][4], double lambda_d) {
     using V = cv<T>;
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
@@ -150,6 +151,76 @@ __device__ __forceinline__ void cd_instance(const WgJob& jb, const cv<T>* __rest
         }
         if (nf) atomicOr(&flag_s, CDM_INFO_NONFINITE);
         __syncthreads();
+        // optional FP64 check of the stationarity of eq. (1):
+        //   ||H^H (y - H x) - lambda x|| / ||H^H y||, with r = y - H x formed in FP64
+        double res = -1.0;
+        if (resid) {
+            const double lam64 = lambda_d;   // the caller's lambda, not its rounding to T
+            double2 r64[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int i = tid + q * NT;
+                const V yv = (i < m) ? Y[jb.y_off + i] : czero<T>();
+                r64[q] = make_double2((double)yv.x, (double)yv.y);
+            }
+            for (int u = 0; u < n; ++u) {
+                const V xv = x_s[u];
+                const double xr = xv.x, xi = xv.y;
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    const int i = tid + q * NT;
+                    if (i < m) {
+                        const V h = Hj[(int64_t)u * ld + i];
+                        r64[q].x -= (double)h.x * xr - (double)h.y * xi;
+                        r64[q].y -= (double)h.x * xi + (double)h.y * xr;
+                    }
+                }
+            }
+            double A2 = 0.0, B2 = 0.0;
+            for (int u = 0; u < n; ++u) {
+                double ar = 0, ai = 0, br = 0, bi = 0;
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    const int i = tid + q * NT;
+                    if (i < m) {
+                        const V h = Hj[(int64_t)u * ld + i];
+                        const V yv = Y[jb.y_off + i];
+                        const double hr = h.x, hi = h.y;
+                        ar += hr * r64[q].x + hi * r64[q].y;
+                        ai += hr * r64[q].y - hi * r64[q].x;
+                        br += hr * (double)yv.x + hi * (double)yv.y;
+                        bi += hr * (double)yv.y - hi * (double)yv.x;
+                    }
+                }
+                ar = wave_allsum(ar);
+                ai = wave_allsum(ai);
+                br = wave_allsum(br);
+                bi = wave_allsum(bi);
+                const int par = u & 1;
+                if (lane == 0) {
+                    red64[par][wid][0] = ar;
+                    red64[par][wid][1] = ai;
+                    red64[par][wid][2] = br;
+                    red64[par][wid][3] = bi;
+                }
+                __syncthreads();
+                double sa = 0, sb = 0, sc = 0, sd = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    sa += red64[par][w][0];
+                    sb += red64[par][w][1];
+                    sc += red64[par][w][2];
+                    sd += red64[par][w][3];
+                }
+                const V xv = x_s[u];
+                sa -= lam64 * (double)xv.x;
+                sb -= lam64 * (double)xv.y;
+                A2 += sa * sa + sb * sb;
+                B2 += sc * sc + sd * sd;
+            }
+            res = B2 > 0.0 ? sqrt(A2 / B2) : sqrt(A2);
+            __syncthreads();
+        }
         if (tid == 0) {
             const double rel = (Xn > 0.0) ? sqrt(S / Xn) : (S > 0.0 ? INFINITY : 0.0);
             int fl = flag_s;
@@ -158,7 +229,7 @@ __device__ __forceinline__ void cd_instance(const WgJob& jb, const cv<T>* __rest
             o.sweeps = sweeps;
             o.flags = fl;
             o.rel_step = rel;
-            o.resid = -1.0;
+            o.resid = res;
             o.reserved = 0.0;
             info[jb.info_idx] = o;
         }
@@ -171,10 +242,11 @@ __global__ __launch_bounds__(NT) void k_cd_wg(const WgJob* __restrict__ jobs, in
                                               cdm_info* __restrict__ info, double lambda_d, int T_max,
                                               double tol, const int* __restrict__ order,
                                               uint32_t* __restrict__ queue, double* __restrict__ msum,
-                                              int64_t ld_arg) {
+                                              int64_t ld_arg, int resid) {
     constexpr int NW = NT / 64;
     extern __shared__ unsigned char smem_raw[];
     __shared__ T red_s[2][NW][3];
+    __shared__ double red64[2][NW][4];
     __shared__ int flag_s;
     __shared__ int job_s;
     const int tid = threadIdx.x;
@@ -192,10 +264,10 @@ __global__ __launch_bounds__(NT) void k_cd_wg(const WgJob* __restrict__ jobs, in
         const WgJob jb = jobs[order ? order[jslot] : jslot];
         // row tile of this job, chosen on the host per size bucket
         switch (jb.rpt) {
-            case 1: cd_instance<T, NT, 1>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s); break;
-            case 2: cd_instance<T, NT, 2>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s); break;
-            case 4: cd_instance<T, NT, 4>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s); break;
-            default: cd_instance<T, NT, 8>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s); break;
+            case 1: cd_instance<T, NT, 1>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s, resid, red64, lambda_d); break;
+            case 2: cd_instance<T, NT, 2>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s, resid, red64, lambda_d); break;
+            case 4: cd_instance<T, NT, 4>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s, resid, red64, lambda_d); break;
+            default: cd_instance<T, NT, 8>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s, resid, red64, lambda_d); break;
         }
         __syncthreads();
     }
@@ -381,7 +453,7 @@ template <typename T, int NT> static hipError_t launch_wg_t(const WgLaunch& L, h
     const size_t shm = (size_t)L.n_max * 2 * sizeof(cv<T>);
     hipLaunchKernelGGL((k_cd_wg<T, NT>), dim3(L.grid), dim3(NT), shm, st, L.jobs, L.njobs, (const cv<T>*)L.H,
                        (const cv<T>*)L.Y, (const cv<T>*)L.X0, (cv<T>*)L.X, L.info, L.lambda, L.T_max, L.tol,
-                       L.order, L.queue, L.msum, L.ld);
+                       L.order, L.queue, L.msum, L.ld, L.resid);
     return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ struct WgLaunch {
     double* msum;     // optional: sum_u m_u per job (cluster fusion weights)
     int64_t ld;       // leading dimension for jobs whose own ld is <= 0
     double rho_c;     // downlink: per-cluster power rho/sqrt(C) (<= 0: no scaling)
+    int resid;        // uplink: also write the FP64 normal-equation residual per job
 };
 hipError_t launch_wg(const WgLaunch& L, hipStream_t st);
 // Algorithm 2 (downlink ZF precoding), same job and tile conventions; Y is s (U).
@@ -93,6 +94,39 @@ struct GramLaunch {
     double lambda;
 };
 hipError_t launch_gram(const GramLaunch& L, hipStream_t st);
+
+// (D + L)^-1 from summed Gram blocks already in gpart (row-major, lower part).
+hipError_t launch_gram_invert(bool c128, void* gpart, int nsplit, int npanels, int kp, int U, double lambda, void* M,
+                              double* e, uint32_t* status, hipStream_t st);
+
+// Sparse (CSR input) single-instance path.
+struct SparseLaunch {
+    bool c128;
+    int B, U, npanels;
+    int64_t nnz;
+    const int32_t* rowptr;   // CSR input (device)
+    const int32_t* colidx;
+    const void* val;
+    int32_t* colptr;         // workspace: column-compressed copy
+    int32_t* fill;
+    int32_t* rowidx;
+    void* cval;
+    void* gpart;             // [2][npanels][64][64]
+    void* M;                 // [npanels][64*65/2]
+    double* e;
+    uint32_t* status;
+    const void* y;
+    const void* x0;
+    void* r;
+    void* x;
+    cdm_info* info;
+    double lambda;
+    int T_max;
+    double tol;
+    bool transpose_only;
+    hipEvent_t ev_sweep0, ev_sweep1;   // optional events around the sweep kernel
+};
+hipError_t launch_sparse(const SparseLaunch& L, hipStream_t st);
 
 // r0 = y (cold) or y - H x0 (warm); x = x0 or 0.
 struct InitLaunch {

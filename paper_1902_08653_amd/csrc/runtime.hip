@@ -85,6 +85,12 @@ struct cdm_plan {
     double* res_r = nullptr;
     double* res_col = nullptr;
     double* res_out = nullptr;
+    // sparse (CSR input)
+    int32_t* sp_colptr = nullptr;
+    int32_t* sp_fill = nullptr;
+    int32_t* sp_rowidx = nullptr;
+    void* sp_cval = nullptr;
+    void* sp_r = nullptr;
     // batched layout
     std::vector<int64_t> H_off, y_off, x_off;
     std::string text;
@@ -170,6 +176,96 @@ static int32_t setup_wg(cdm_plan* p, int m_max, int n_max, int njobs, int nt) {
     return CDM_OK;
 }
 
+extern "C" int32_t cdm_destroy(cdm_plan* p);
+
+static constexpr int kSpKp = 64;
+
+// Sparse plans: column-compressed copy, panel inverses and residual, all in one
+// workspace sized from desc->nnz.
+static int32_t create_sparse(cdm_plan* p, cdm_plan** plan) {
+    const cdm_desc& d = p->d;
+    p->engine = 3;
+    p->kp = kSpKp;
+    p->npanels = (d.U + kSpKp - 1) / kSpKp;
+    const size_t nnz = (size_t)std::max<int64_t>(d.nnz, 1);
+    const size_t ne = (size_t)kSpKp * (kSpKp + 1) / 2;
+    Arena ar;
+    const size_t o_ctr = ar.take(64);
+    const size_t o_colptr = ar.take(4 * ((size_t)d.U + 1));
+    const size_t o_fill = ar.take(4 * (size_t)d.U);
+    const size_t o_rowidx = ar.take(4 * nnz);
+    const size_t o_cval = ar.take(p->esz * nnz);
+    const size_t o_r = ar.take(p->esz * (size_t)d.B);
+    const size_t o_M = ar.take(p->esz * ne * p->npanels);
+    const size_t o_gpart = ar.take(p->esz * 2 * (size_t)kSpKp * kSpKp * p->npanels);
+    const size_t o_e = ar.take(8 * (size_t)d.U);
+    int32_t st = alloc_ws(p, ar.off);
+    if (st) {
+        delete p;
+        return st;
+    }
+    char* b = p->ws;
+    p->ctr = (uint32_t*)(b + o_ctr);
+    p->sp_colptr = (int32_t*)(b + o_colptr);
+    p->sp_fill = (int32_t*)(b + o_fill);
+    p->sp_rowidx = (int32_t*)(b + o_rowidx);
+    p->sp_cval = b + o_cval;
+    p->sp_r = b + o_r;
+    p->M = b + o_M;
+    p->gpart = b + o_gpart;
+    p->e = (double*)(b + o_e);
+    char buf[512];
+    snprintf(buf, sizeof(buf),
+             "{\"engine\": \"sparse\", \"precision\": \"%s\", \"B\": %d, \"U\": %d, \"nnz\": %lld, \"panel\": %d, "
+             "\"npanels\": %d, \"workgroups\": 1, \"workspace\": %zu}",
+             p->c128 ? "c128" : "c64", d.B, d.U, (long long)d.nnz, kSpKp, p->npanels, p->ws_bytes);
+    p->text = buf;
+    st = setup_timing(p);
+    if (st) {
+        cdm_destroy(p);
+        return st;
+    }
+    *plan = p;
+    return CDM_OK;
+}
+
+static int32_t run_sparse(cdm_plan* p, const void* val, const int32_t* rowptr, const int32_t* colidx, const void* y,
+                          double lambda, const void* x0, void* x, cdm_info* info, bool transpose_only,
+                          hipStream_t st) {
+    const cdm_desc& d = p->d;
+    SparseLaunch L;
+    L.c128 = p->c128;
+    L.B = d.B;
+    L.U = d.U;
+    L.npanels = p->npanels;
+    L.nnz = d.nnz;
+    L.rowptr = rowptr;
+    L.colidx = colidx;
+    L.val = val;
+    L.colptr = p->sp_colptr;
+    L.fill = p->sp_fill;
+    L.rowidx = p->sp_rowidx;
+    L.cval = p->sp_cval;
+    L.gpart = p->gpart;
+    L.M = p->M;
+    L.e = p->e;
+    L.status = p->ctr + 3;
+    L.y = y;
+    L.x0 = x0;
+    L.r = p->sp_r;
+    L.x = x;
+    L.info = info;
+    L.lambda = lambda;
+    L.T_max = d.T_max;
+    L.tol = d.tol;
+    L.transpose_only = transpose_only;
+    L.ev_sweep0 = p->timed ? p->ev[2] : nullptr;
+    L.ev_sweep1 = p->timed ? p->ev[3] : nullptr;
+    HIP_TRY(launch_zero_u32(p->ctr, 16, st));
+    HIP_TRY(launch_sparse(L, st));
+    return CDM_OK;
+}
+
 extern "C" {
 
 int32_t cdm_version(void) { return CDM_ABI_VERSION; }
@@ -200,7 +296,9 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
     if (d.B < 1 || d.U < 1 || d.C < 1 || d.B % d.C) return CDM_ESHAPE;
     const int Bc = d.B / d.C;
     if (d.problem == CDM_DOWNLINK_ZF && Bc < d.U) return CDM_EINFEASIBLE;
-    if (d.layout != CDM_DENSE || (d.precision != CDM_C128 && d.precision != CDM_C64)) return CDM_ENOTIMPL;
+    if (d.precision != CDM_C128 && d.precision != CDM_C64) return CDM_ENOTIMPL;
+    if (d.layout == CDM_CSR && (d.problem != CDM_UPLINK_LMMSE || d.C != 1)) return CDM_ENOTIMPL;
+    if (d.layout == CDM_CSR && (d.nnz < 0 || d.nnz > 0x7fffffffLL)) return CDM_ESHAPE;
     if (d.problem == CDM_DOWNLINK_ZF &&
         (d.engine == CDM_ENGINE_PANEL || Bc > (d.precision == CDM_C128 ? kWgMaxRows / 2 : kWgMaxRows)))
         return CDM_ENOTIMPL;
@@ -214,6 +312,8 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         delete p;
         return st;
     }
+
+    if (d.layout == CDM_CSR) return create_sparse(p, plan);
 
     // engine choice: one cooperative launch for a single large instance, else WG
     int engine = d.engine;
@@ -383,7 +483,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
     const cdm_desc& d = p->d;
     if (d.problem == CDM_UPLINK_LMMSE && (!(Ex > 0.0) || !(N0 >= 0.0) || !std::isfinite(N0) || !std::isfinite(Ex)))
         return CDM_EINVAL;
-    if (ldh < d.B) return CDM_ESHAPE;
+    if (d.layout == CDM_DENSE && ldh < d.B) return CDM_ESHAPE;
     const double lambda = N0 / Ex;
     const int Bc = d.B / d.C;
     hipStream_t st = (hipStream_t)stream;
@@ -414,12 +514,23 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         L.msum = nullptr;
         L.ld = ldh;
         L.rho_c = rho > 0.0 ? rho / std::sqrt((double)d.C) : 0.0;
+        L.resid = 0;
         HIP_TRY(launch_zf(L, st));
         ev_record(p, 3, st);
         ev_record(p, 4, st);
         return CDM_OK;
     }
     if (lambda == 0.0 && Bc < d.U) return CDM_EINFEASIBLE;
+    if (d.layout == CDM_CSR) {
+        if (!rowptr || !colidx) return CDM_EINVAL;
+        ev_record(p, 0, st);
+        ev_record(p, 1, st);
+        int32_t s2 = run_sparse(p, H, rowptr, colidx, rhs, lambda, x0, x, inf, false, st);
+        if (s2) return s2;
+        HIP_TRY(launch_finalize(x, d.U, p->c128, p->ctr + 2, inf, st));
+        ev_record(p, 4, st);
+        return CDM_OK;
+    }
 
     ev_record(p, 0, st);
     HIP_TRY(launch_zero_u32(p->ctr, p->engine == CDM_ENGINE_PANEL ? kCtrWords : 16, st));
@@ -446,6 +557,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         L.msum = d.C > 1 ? p->msum : nullptr;
         L.ld = ldh;
         L.rho_c = 0.0;
+        L.resid = 0;
         HIP_TRY(launch_wg(L, st));
         ev_record(p, 3, st);
         if (d.C > 1) HIP_TRY(launch_fuse(p->c128, p->xloc, p->msum, d.C, d.U, N0, x, st));
@@ -514,6 +626,20 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
     return CDM_OK;
 }
 
+int32_t cdm_csr_transpose(cdm_plan* p, const void* val, const int32_t* rowptr, const int32_t* colidx,
+                          int32_t* colptr_out, int32_t* rowidx_out, void* cval_out, void* stream) {
+    if (!p || p->d.layout != CDM_CSR || !val || !rowptr || !colidx) return CDM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    int32_t s2 = run_sparse(p, val, rowptr, colidx, nullptr, 0.0, nullptr, nullptr, nullptr, true, st);
+    if (s2) return s2;
+    const size_t nnz = (size_t)p->d.nnz;
+    if (colptr_out)
+        HIP_TRY(hipMemcpyAsync(colptr_out, p->sp_colptr, 4 * ((size_t)p->d.U + 1), hipMemcpyDeviceToDevice, st));
+    if (rowidx_out && nnz) HIP_TRY(hipMemcpyAsync(rowidx_out, p->sp_rowidx, 4 * nnz, hipMemcpyDeviceToDevice, st));
+    if (cval_out && nnz) HIP_TRY(hipMemcpyAsync(cval_out, p->sp_cval, p->esz * nnz, hipMemcpyDeviceToDevice, st));
+    return CDM_OK;
+}
+
 int32_t cdm_residual(cdm_plan* p, const void* H, int64_t ldh, const void* y, double N0, double Ex, const void* x,
                      double* out, void* stream) {
     if (!p || p->batched || !H || !y || !x || !out) return CDM_EINVAL;
@@ -553,6 +679,7 @@ static double time_batched(cdm_plan* p, int nt, int m_max, int n_max, WgJob* job
     L.msum = nullptr;
     L.ld = 1;
     L.rho_c = 0.0;
+    L.resid = 0;
     (void)m_max;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return -1.0;
@@ -766,6 +893,7 @@ int32_t cdm_solve_batched(cdm_plan* p, const void* H, const void* y, double N0, 
     L.msum = nullptr;
     L.ld = 1;
     L.rho_c = 0.0;
+    L.resid = (p->d.flags & CDM_F_RESIDUAL) ? 1 : 0;
     HIP_TRY(launch_wg(L, st));
     return CDM_OK;
 }

@@ -34,20 +34,6 @@ class DenseInstance:
         return self.H.shape[1]
 
 
-def _cn(rng, shape, var, dtype):
-    sd = np.sqrt(var / 2.0)
-    re = rng.standard_normal(shape)
-    im = rng.standard_normal(shape)
-    out = np.empty(shape, dtype=np.complex128 if dtype == np.complex128 else np.complex64)
-    if dtype == np.complex128:
-        out.real = re * sd
-        out.imag = im * sd
-    else:
-        out.real = (re * sd).astype(np.float32)
-        out.imag = (im * sd).astype(np.float32)
-    return out
-
-
 def dense_uplink(B: int, U: int, seed: int, var_h: float | None = None,
                  dtype=np.complex128) -> DenseInstance:
     """H ~ CN(0, var_h) (default 1/B), y ~ CN(0, 1).  Draw order Re(H), Im(H), Re(y), Im(y)."""
@@ -165,6 +151,28 @@ def pack_batch(instances, dtype=np.complex128):
         Hf[H_off[k]:H_off[k] + hsz[k]] = ins.H.T.reshape(-1)
         yf[y_off[k]:y_off[k] + m[k]] = ins.y
     return Hf, yf, m, n, H_off, y_off, x_off
+
+
+def batch_uneven_device(count: int, seed0: int = 0, m_lo: int = 64, m_hi: int = 2048, dtype=None,
+                        device="cuda:0"):
+    """The uneven batch drawn directly in device memory (for sizes too large to draw
+    on the host): instance sizes m_i, n_i = m_i // 2 exactly as batch_sizes(); the
+    packed H (instance by instance, column-major, ld = m_i) and y come from torch's
+    device generator seeded with seed0: H_i ~ CN(0, 1/m_i), y ~ CN(0, 1).
+    Returns (H, y, m, n) with H and y device tensors."""
+    import torch
+    dtype = torch.complex64 if dtype is None else dtype
+    m, n = batch_sizes(count, seed0, m_lo, m_hi)
+    hsz = m.astype(np.int64) * n.astype(np.int64)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed0) + 7919)
+    H = torch.randn(int(hsz.sum()), dtype=dtype, device=device, generator=g)
+    y = torch.randn(int(m.astype(np.int64).sum()), dtype=dtype, device=device, generator=g)
+    off = 0
+    for i in range(count):
+        H[off:off + int(hsz[i])].mul_(float(1.0 / np.sqrt(m[i])))
+        off += int(hsz[i])
+    return H, y, m, n
 
 
 # 16-QAM with unit average energy (Gray mapping on each axis): the paper's

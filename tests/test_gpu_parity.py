@@ -238,3 +238,48 @@ def test_downlink_converges_to_zf(dev, orc):
     assert relerr(x, ref) <= 1e-11
     ro = orc.local_zf_cd(H, s, T_max=500, tol=1e-13)
     assert abs(int(info["sweeps"][0]) - ro["sweeps"]) <= 1
+
+
+def test_batched_hipgraph_replays_match_eager(dev, orc):
+    """The batched solve enqueues kernels only, so it can be captured into a HIP graph;
+    every replay must reproduce the eager result bit for bit (with eager work and
+    synchronisations between replays)."""
+    from paper_1902_08653_amd import cdm
+    ins = [inputs.batch_instance(i, m_lo=64, m_hi=900) for i in range(40)]
+    Hf, yf, m, n, ho, yo, xo = inputs.pack_batch(ins, dtype=np.complex64)
+    plan = cdm.BatchedPlan(m, n, precision="c64", T_max=200, tol=1e-6, residual=True, autotune=True)
+    H = torch.from_numpy(Hf).to(dev)
+    y = torch.from_numpy(yf).to(dev)
+    x_e, info_e = plan.solve(H, y, N0=0.1)
+    torch.cuda.synchronize()
+    ref_x = x_e.cpu().numpy()
+    ref_info = cdm.parse_info(info_e)
+    x = torch.zeros_like(x_e)
+    info = torch.zeros_like(info_e)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.solve(H, y, N0=0.1, x=x, info=info)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.solve(H, y, N0=0.1, x=x, info=info)
+    for rep in range(3):
+        x.zero_()
+        info.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), ref_x), rep
+        got = cdm.parse_info(info)
+        assert np.array_equal(got["sweeps"], ref_info["sweeps"]) and np.array_equal(got["flags"], ref_info["flags"])
+        _ = (H[:10] * 2).sum().item()      # eager work between replays
+    assert '"autotune_ms": {' in plan.describe()
+    # the in-kernel FP64 residual agrees with the oracle's definition
+    for k in [0, 17, 39]:
+        want = orc.normal_residual(ins[k].H.astype(np.complex64).astype(complex),
+                                   ins[k].y.astype(np.complex64).astype(complex), 0.1,
+                                   ref_x[xo[k]:xo[k] + n[k]].astype(complex))
+        assert abs(ref_info["resid"][k] - want) <= 1e-6 * want + 1e-14
+        assert ref_info["resid"][k] < 1e-4

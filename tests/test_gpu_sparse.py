@@ -1,0 +1,98 @@
+"""Sparse channel (CSR input): the bit-exact CSR -> column-compressed transpose and the
+sparse sweep against the oracle's sparse CD (which itself is pinned bit-exactly to the
+dense oracle on the densified matrix)."""
+import numpy as np
+import pytest
+
+from paper_1902_08653_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DT = {"c128": np.complex128, "c64": np.complex64}
+TOL = {"c128": 1e-10, "c64": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def to_dev(ins, prec, dev):
+    return (torch.from_numpy(ins.val.astype(DT[prec])).to(dev), torch.from_numpy(ins.rowptr).to(dev),
+            torch.from_numpy(ins.colidx).to(dev), torch.from_numpy(ins.y.astype(DT[prec])).to(dev))
+
+
+@pytest.mark.parametrize("B,U,dens", [(50, 20, 0.2), (300, 140, 0.05), (2000, 700, 0.02), (3000, 130, 0.001)])
+def test_csr_transpose_bit_exact(dev, orc, B, U, dens):
+    from paper_1902_08653_amd import cdm
+    ins = inputs.sparse_uplink(B, U, dens, seed=B + U)
+    nnz = int(ins.rowptr[-1])
+    plan = cdm.Plan(B, U, layout="csr", nnz=nnz, T_max=1)
+    val, rp, ci, y = to_dev(ins, "c128", dev)
+    colptr, rowidx, cval = plan.csr_transpose(val, rp, ci)
+    torch.cuda.synchronize()
+    ref = orc.csr_to_csc(B, U, ins.rowptr, ins.colidx, ins.val)
+    assert np.array_equal(colptr.cpu().numpy(), ref[0])
+    assert np.array_equal(rowidx.cpu().numpy(), ref[1])
+    assert np.array_equal(cval.cpu().numpy(), ref[2])
+
+
+def run_sparse(dev, ins, prec, T, tol=0.0, lam=0.1, x0=None):
+    from paper_1902_08653_amd import cdm
+    nnz = int(ins.rowptr[-1])
+    plan = cdm.Plan(ins.B, ins.U, layout="csr", nnz=nnz, precision=prec, T_max=T, tol=tol)
+    val, rp, ci, y = to_dev(ins, prec, dev)
+    x0d = None if x0 is None else torch.from_numpy(x0.astype(DT[prec])).to(dev)
+    x, info = plan.solve(val, y, N0=lam, rowptr=rp, colidx=ci, x0=x0d)
+    torch.cuda.synchronize()
+    out = x.cpu().numpy().astype(np.complex128), cdm.parse_info(info)[0], plan.describe()
+    plan.close()
+    return out
+
+
+def oracle_sparse(orc, ins, prec, T, tol=0.0, lam=0.1, x0=None):
+    val = ins.val.astype(DT[prec]).astype(np.complex128)
+    y = ins.y.astype(DT[prec]).astype(np.complex128)
+    colptr, rowidx, cval = orc.csr_to_csc(ins.B, ins.U, ins.rowptr, ins.colidx, val)
+    return orc.local_cd_csc(ins.B, ins.U, colptr, rowidx, cval, y, lam, T_max=T, tol=tol, x0=x0)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("B,U,dens,T", [(300, 140, 0.05, 3), (2000, 700, 0.02, 4), (1000, 1000, 0.01, 2)])
+def test_sparse_sweeps_match_oracle(dev, orc, prec, B, U, dens, T):
+    ins = inputs.sparse_uplink(B, U, dens, seed=7 * B + U)
+    x, info, desc = run_sparse(dev, ins, prec, T)
+    ref = oracle_sparse(orc, ins, prec, T)
+    err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+    print(prec, B, U, desc, err)
+    assert '"engine": "sparse"' in desc
+    assert info["sweeps"] == T
+    assert err <= TOL[prec], err
+
+
+def test_sparse_tolerance_mode_and_warm_start(dev, orc):
+    ins = inputs.sparse_uplink(1500, 600, 0.02, seed=11)
+    x, info, _ = run_sparse(dev, ins, "c128", 200, tol=1e-11)
+    ref = oracle_sparse(orc, ins, "c128", 200, tol=1e-11)
+    assert abs(int(info["sweeps"]) - ref["sweeps"]) <= 1
+    at = oracle_sparse(orc, ins, "c128", int(info["sweeps"]))
+    assert np.linalg.norm(x - at["x"]) <= 1e-10 * np.linalg.norm(at["x"])
+    rng = np.random.default_rng(2)
+    x0 = rng.standard_normal(600) + 1j * rng.standard_normal(600)
+    xw, iw, _ = run_sparse(dev, ins, "c128", 2, x0=x0)
+    rw = oracle_sparse(orc, ins, "c128", 2, x0=x0)
+    assert np.linalg.norm(xw - rw["x"]) <= 1e-10 * np.linalg.norm(rw["x"])
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_sparse_fullsize_two_sweeps(dev, orc, prec):
+    """16384 x 8192 at 1 % density (the sparse variant of the large single instance)."""
+    ins = inputs.sparse_uplink(16384, 8192, 0.01, seed=1)
+    x, info, desc = run_sparse(dev, ins, prec, 2)
+    ref = oracle_sparse(orc, ins, prec, 2)
+    err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+    print(prec, desc, err)
+    assert info["sweeps"] == 2 and err <= TOL[prec]
