@@ -185,6 +185,19 @@ int32_t cdm_solve_batched(cdm_plan* plan, const void* H, const void* y, double N
 int32_t cdm_csr_transpose(cdm_plan* plan, const void* val, const int32_t* rowptr, const int32_t* colidx,
                           int32_t* colptr_out, int32_t* rowidx_out, void* cval_out, void* stream);
 
+/* Mixed-precision plans: the low-precision copy of H the inner sweeps read, so that it
+ * can be checked.  Quantises H (complex128, ld >= B, device) and copies the planar
+ * codes to re_out / im_out (device; B*U uint16 for CDM_MIXED_BF16, B*U uint8 for
+ * CDM_MIXED_FP8, column-major with ld = B) and, for FP8, the ceil(U/128) block
+ * scales to scale_out (device float).  Any output may be NULL.
+ * Definitions: BF16 = nearest-even rounding to FP32, then nearest-even to the top
+ * 16 bits; FP8 = OCP E4M3 of fl32(h / s_b), nearest with ties to the even code,
+ * saturating at 448, with s_b = fl32(amax_b / 448) over the block's Re and Im parts
+ * (1 for an all-zero block).
+ * Errors: CDM_EINVAL (not a mixed plan, NULL H), CDM_ESHAPE, CDM_EHIP. */
+int32_t cdm_quantized_copy(cdm_plan* plan, const void* H, int64_t ldh, void* re_out, void* im_out,
+                           float* scale_out, void* stream);
+
 /* FP64 stationarity check of eq. (1) for a dense uplink plan:
  * *out (device double) = ||H^H (y - H x) - lambda x|| / ||H^H y||, lambda = N0/Ex.
  * Uses the plan's workspace; same argument conventions as cdm_solve. */

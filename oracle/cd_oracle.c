@@ -388,3 +388,101 @@ double cdo_normal_residual(int B, int U, const cplx* H, long ldh, const cplx* y,
     free(r);
     return den > 0.0 ? sqrt(num / den) : sqrt(num);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Low-precision copies of H for the mixed-precision refinement (not part of   */
+/* the paper; definitions of this project, written out plainly):               */
+/*   BF16: each real component is rounded to FP32 (nearest, ties to even),     */
+/*         then to BF16 (the top 16 bits of FP32; nearest, ties to even).      */
+/*   FP8 : OCP E4M3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits; no  */
+/*         infinities; largest finite 448).  One FP32 scale per block of 128   */
+/*         consecutive columns, s = fl32(amax / 448) with amax the largest     */
+/*         |Re| or |Im| in the block (s = 1 for an all-zero block); each        */
+/*         component v = fl32(h / s) is coded to the nearest E4M3 value, ties   */
+/*         to the even code, magnitudes above 448 saturating to 448.            */
+/* ------------------------------------------------------------------------- */
+uint16_t cdo_bf16_code(double v)
+{
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    /* nearest of the two BF16 neighbours of f, ties to the even one */
+    uint32_t lo = u & 0xffff0000u;
+    uint32_t rem = u & 0x0000ffffu;
+    uint32_t q = lo >> 16;
+    if (rem > 0x8000u || (rem == 0x8000u && (q & 1u))) q += 1u;
+    return (uint16_t)q;
+}
+
+double cdo_bf16_value(uint16_t c)
+{
+    uint32_t u = (uint32_t)c << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+double cdo_e4m3_value(uint8_t c)
+{
+    int s = (c >> 7) & 1, e = (c >> 3) & 15, m = c & 7;
+    double v;
+    if (e == 15 && m == 7) return NAN;
+    if (e == 0) v = ldexp((double)m, -9);
+    else v = ldexp(1.0 + m / 8.0, e - 7);
+    return s ? -v : v;
+}
+
+/* nearest code by exhaustive comparison with every finite non-negative code */
+uint8_t cdo_e4m3_code(float v)
+{
+    if (isnan(v)) return 0x7f;
+    uint8_t sign = (v < 0.0f) ? 0x80 : 0x00;
+    double a = fabs((double)v);
+    if (a >= 448.0) return sign | 0x7e;
+    int best = 0;
+    double bd = INFINITY;
+    for (int c = 0; c <= 0x7e; ++c) {
+        double d = fabs(cdo_e4m3_value((uint8_t)c) - a);
+        if (d < bd || (d == bd && (c & 1) == 0 && (best & 1) == 1)) {
+            bd = d;
+            best = c;
+        }
+    }
+    return sign | (uint8_t)best;
+}
+
+/* Quantise a B x U column-major complex H (ld) into planar codes (column-major,
+ * ld = B).  kind 0: BF16 into re16/im16; kind 1: FP8 into re8/im8 with scales
+ * (ceil(U/128) floats). */
+void cdo_quantize(int kind, int B, int U, const cplx* H, long ldh, uint16_t* re16, uint16_t* im16,
+                  uint8_t* re8, uint8_t* im8, float* scales)
+{
+    if (kind == 0) {
+        for (int u = 0; u < U; ++u)
+            for (int i = 0; i < B; ++i) {
+                cplx h = H[(long)u * ldh + i];
+                re16[(long)u * B + i] = cdo_bf16_code(creal(h));
+                im16[(long)u * B + i] = cdo_bf16_code(cimag(h));
+            }
+        return;
+    }
+    int nblk = (U + 127) / 128;
+    for (int b = 0; b < nblk; ++b) {
+        double amax = 0.0;
+        for (int u = b * 128; u < U && u < b * 128 + 128; ++u)
+            for (int i = 0; i < B; ++i) {
+                cplx h = H[(long)u * ldh + i];
+                if (fabs(creal(h)) > amax) amax = fabs(creal(h));
+                if (fabs(cimag(h)) > amax) amax = fabs(cimag(h));
+            }
+        float s = (amax > 0.0) ? (float)(amax / 448.0) : 1.0f;
+        scales[b] = s;
+        for (int u = b * 128; u < U && u < b * 128 + 128; ++u)
+            for (int i = 0; i < B; ++i) {
+                cplx h = H[(long)u * ldh + i];
+                re8[(long)u * B + i] = cdo_e4m3_code((float)(creal(h) / (double)s));
+                im8[(long)u * B + i] = cdo_e4m3_code((float)(cimag(h) / (double)s));
+            }
+    }
+}

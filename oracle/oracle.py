@@ -66,6 +66,14 @@ def lib():
         _lib.cdo_local_cd_csc.restype = i32
         _lib.cdo_normal_residual.argtypes = [i32, i32, P, i64, P, f64, P]
         _lib.cdo_normal_residual.restype = f64
+        _lib.cdo_bf16_code.argtypes = [f64]
+        _lib.cdo_bf16_code.restype = C.c_uint16
+        _lib.cdo_e4m3_code.argtypes = [C.c_float]
+        _lib.cdo_e4m3_code.restype = C.c_uint8
+        _lib.cdo_e4m3_value.argtypes = [C.c_uint8]
+        _lib.cdo_e4m3_value.restype = f64
+        _lib.cdo_quantize.argtypes = [i32, i32, i32, P, i64, P, P, P, P, P]
+        _lib.cdo_quantize.restype = None
     return _lib
 
 
@@ -228,3 +236,32 @@ def normal_residual(H, y, lam, x):
     y = _vec(y, B)
     x = _vec(x, U)
     return lib().cdo_normal_residual(B, U, _ptr(H), max(B, 1), _ptr(y), float(lam), _ptr(x))
+
+
+def quantize(H, kind):
+    """Planar low-precision copy of H (see cd_oracle.c): kind "bf16" -> (re, im) uint16
+    arrays of shape (U, B); kind "fp8" -> (re, im) uint8 arrays and the block scales."""
+    H = _colmajor(H)
+    B, U = H.shape
+    if kind == "bf16":
+        re = np.zeros((U, B), np.uint16)
+        im = np.zeros((U, B), np.uint16)
+        lib().cdo_quantize(0, B, U, _ptr(H), max(B, 1), _ptr(re), _ptr(im), None, None, None)
+        return re, im
+    re = np.zeros((U, B), np.uint8)
+    im = np.zeros((U, B), np.uint8)
+    sc = np.zeros((U + 127) // 128, np.float32)
+    lib().cdo_quantize(1, B, U, _ptr(H), max(B, 1), None, None, _ptr(re), _ptr(im), _ptr(sc))
+    return re, im, sc
+
+
+def e4m3_value(code):
+    return lib().cdo_e4m3_value(int(code))
+
+
+def e4m3_code(v):
+    return int(lib().cdo_e4m3_code(float(v)))
+
+
+def bf16_code(v):
+    return int(lib().cdo_bf16_code(float(v)))

@@ -52,7 +52,7 @@ assert INFO_DTYPE.itemsize == 32
 
 EXPORTS = ["cdm_version", "cdm_status_string", "cdm_last_error", "cdm_create", "cdm_solve",
            "cdm_create_batched", "cdm_batched_offsets", "cdm_solve_batched", "cdm_residual",
-           "cdm_plan_describe", "cdm_plan_timings", "cdm_stream_copy", "cdm_csr_transpose", "cdm_destroy"]
+           "cdm_plan_describe", "cdm_plan_timings", "cdm_stream_copy", "cdm_csr_transpose", "cdm_quantized_copy", "cdm_destroy"]
 
 _lib = None
 
@@ -90,6 +90,8 @@ def lib():
         L.cdm_stream_copy.restype = i32
         L.cdm_csr_transpose.argtypes = [P, P, P, P, P, P, P, P]
         L.cdm_csr_transpose.restype = i32
+        L.cdm_quantized_copy.argtypes = [P, P, i64, P, P, P, P]
+        L.cdm_quantized_copy.restype = i32
         L.cdm_destroy.argtypes = [P]
         L.cdm_destroy.restype = i32
         _lib = L
@@ -182,6 +184,17 @@ class Plan:
         _check(lib().cdm_csr_transpose(self._h, _ptr(val), _ptr(rowptr), _ptr(colidx), _ptr(colptr),
                                        _ptr(rowidx), _ptr(cval), _stream(stream)), "cdm_csr_transpose")
         return colptr, rowidx[:nnz], cval[:nnz]
+
+    def quantized_copy(self, Hc, stream=None):
+        """Mixed plans: the planar low-precision copy of H (re, im[, block scales])."""
+        import torch
+        dt = torch.int16 if self.precision == "bf16" else torch.uint8
+        re = torch.empty((self.U, self.B), dtype=dt, device=Hc.device)
+        im = torch.empty_like(re)
+        sc = torch.empty((self.U + 127) // 128, dtype=torch.float32, device=Hc.device)
+        _check(lib().cdm_quantized_copy(self._h, _ptr(Hc), int(Hc.shape[1]), _ptr(re), _ptr(im), _ptr(sc),
+                                        _stream(stream)), "cdm_quantized_copy")
+        return (re, im) if self.precision == "bf16" else (re, im, sc)
 
     def residual(self, Hc, y, x, N0=0.1, Ex=1.0, out=None, stream=None):
         import torch

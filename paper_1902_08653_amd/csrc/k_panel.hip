@@ -30,11 +30,41 @@
 namespace cdm {
 
 constexpr int PANEL_NT = 512;   // 8 waves per workgroup, one workgroup per CU
+
+// Tile sources: where the sweep reads H from.  `idx` is the element index
+// col * ld + row of the column-major B x U matrix, `col` its column.
+template <typename T> struct SrcC {            // interleaved complex (the caller's H)
+    const cv<T>* H;
+    __device__ __forceinline__ cv<T> load(int64_t idx, int) const { return ld_nt(H + idx); }
+};
+struct SrcBF16 {                               // planar BF16 copy
+    const uint16_t* re;
+    const uint16_t* im;
+    __device__ __forceinline__ float2 load(int64_t idx, int) const {
+        return make_float2(__uint_as_float((uint32_t)re[idx] << 16), __uint_as_float((uint32_t)im[idx] << 16));
+    }
+};
+__device__ __forceinline__ float e4m3_to_float(uint32_t c) {
+    const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+    const float v = e ? ldexpf((float)(8u + m), (int)e - 10) : ldexpf((float)m, -9);
+    return (c & 0x80u) ? -v : v;
+}
+struct SrcFP8 {                                // planar FP8-e4m3 copy, one scale per 128 columns
+    const uint8_t* re;
+    const uint8_t* im;
+    const float* scale;
+    __device__ __forceinline__ float2 load(int64_t idx, int col) const {
+        const float s = scale[col >> 7];
+        return make_float2(e4m3_to_float(re[idx]) * s, e4m3_to_float(im[idx]) * s);
+    }
+};
 constexpr int PANEL_NWV = PANEL_NT / 64;
 
-template <typename T> struct PanelArgs {
-    const cv<T>* H;
+template <typename T, class Src> struct PanelArgs {
+    Src src;
     int64_t ld;
+    const cv<T>* bias;      // optional: added to every b_u (inner correction solve)
+    const uint32_t* done;   // optional: nonzero -> return at once (finished refinement)
     const cv<T>* r0;
     cv<T>* x;
     const cv<T>* M;
@@ -48,8 +78,8 @@ template <typename T> struct PanelArgs {
     int B, U, npanels, T_max;
 };
 
-template <typename T, int KP, int RPL>
-__global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
+template <typename T, int KP, int RPL, class Src>
+__global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T, Src> a) {
     using V = cv<T>;
     constexpr int NC = KP / PANEL_NWV;          // panel columns per wave
     static_assert(NC >= 1 && NC <= 64 && (NC & (NC - 1)) == 0, "bad panel split");
@@ -62,6 +92,7 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
     const int R = P < KP ? P : KP;             // reducer workgroups
     const T lambda = (T)a.lambda;
     const int B = a.B, U = a.U;
+    if (a.done && *a.done) return;   // uniform for the whole grid
 
     constexpr int NE = KP * (KP + 1) / 2;       // packed lower triangle of M_K
     constexpr int NS = PANEL_NT / KP;           // matvec slices per row
@@ -94,19 +125,20 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
     V tile[NC][RPL];
     V nxt[NC][RPL];
     auto load_panel = [&](int K) {
-        // running per-lane pointer: column K*KP + wid + NWV*c, row row0 + lane + 64q
+        // running per-lane element index: column K*KP + wid + NWV*c, row row0 + lane + 64q
         const int col0 = K * KP + wid;
-        const V* hp = a.H + (int64_t)col0 * a.ld + row0 + lane;
+        int64_t hi = (int64_t)col0 * a.ld + row0 + lane;
         const int64_t cstep = (int64_t)PANEL_NWV * a.ld;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const bool cok = col0 + PANEL_NWV * c < U;
+            const int col = col0 + PANEL_NWV * c;
+            const bool cok = col < U;
 #pragma unroll
             for (int q = 0; q < RPL; ++q) {
                 const bool rok = row0 + lane + 64 * q < B;
-                nxt[c][q] = (cok && rok) ? ld_nt(hp + 64 * q) : czero<T>();
+                nxt[c][q] = (cok && rok) ? a.src.load(hi + 64 * q, col) : czero<T>();
             }
-            hp += cstep;
+            hi += cstep;
         }
     };
     load_panel(0);
@@ -211,6 +243,11 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
                             }
                             const int u = K * KP + j;
                             const V xo = (u < U) ? a.x[u] : czero<T>();
+                            if (a.bias && u < U) {
+                                const V bb = a.bias[u];
+                                g.x += bb.x;
+                                g.y += bb.y;
+                            }
                             V b;
                             b.x = g.x - lambda * xo.x;
                             b.y = g.y - lambda * xo.y;
@@ -333,11 +370,13 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T> a) {
     }
 }
 
-template <typename T, int KP, int RPL>
-static hipError_t launch_panel_t(const PanelLaunch& L, hipStream_t st) {
-    PanelArgs<T> a;
-    a.H = (const cv<T>*)L.H;
+template <typename T, int KP, int RPL, class Src>
+static hipError_t launch_panel_src(const PanelLaunch& L, const Src& src, hipStream_t st) {
+    PanelArgs<T, Src> a;
+    a.src = src;
     a.ld = L.ld;
+    a.bias = (const cv<T>*)L.bias;
+    a.done = L.done;
     a.r0 = (const cv<T>*)L.r0;
     a.x = (cv<T>*)L.x;
     a.M = (const cv<T>*)L.M;
@@ -353,8 +392,21 @@ static hipError_t launch_panel_t(const PanelLaunch& L, hipStream_t st) {
     a.npanels = L.npanels;
     a.T_max = L.T_max;
     void* args[] = {&a};
-    return hipLaunchCooperativeKernel((const void*)k_cd_panel<T, KP, RPL>, dim3(L.P), dim3(PANEL_NT), args, 0,
+    return hipLaunchCooperativeKernel((const void*)k_cd_panel<T, KP, RPL, Src>, dim3(L.P), dim3(PANEL_NT), args, 0,
                                       st);
+}
+
+template <typename T, int KP, int RPL>
+static hipError_t launch_panel_t(const PanelLaunch& L, hipStream_t st) {
+    if (L.src_kind == SRC_BF16) {
+        if constexpr (sizeof(T) == 4) return launch_panel_src<T, KP, RPL>(L, SrcBF16{L.q_re16, L.q_im16}, st);
+        return hipErrorInvalidValue;
+    }
+    if (L.src_kind == SRC_FP8) {
+        if constexpr (sizeof(T) == 4) return launch_panel_src<T, KP, RPL>(L, SrcFP8{L.q_re8, L.q_im8, L.q_scale}, st);
+        return hipErrorInvalidValue;
+    }
+    return launch_panel_src<T, KP, RPL>(L, SrcC<T>{(const cv<T>*)L.H}, st);
 }
 
 template <typename T, int KP, int RPL>
@@ -362,7 +414,7 @@ static int coresident_t() {
     int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cd_panel<T, KP, RPL>, PANEL_NT, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cd_panel<T, KP, RPL, SrcC<T>>, PANEL_NT, 0) != hipSuccess)
         return 0;
     return per * ncu;
 }
@@ -396,8 +448,8 @@ int panel_max_coresident(bool c128, int kp, int rpl) {
 // grid.x = npanels * nsub, grid.y = nsplit; 256 threads as a 16 x 16 grid, each
 // accumulating a 4 x 4 complex tile; rows stream through LDS 32 at a time.
 // ============================================================================
-template <typename T>
-__global__ __launch_bounds__(256) void k_gram_partial(const cv<T>* __restrict__ H, int64_t ld, int B, int U, int kp,
+template <typename T, class Src>
+__global__ __launch_bounds__(256) void k_gram_partial(Src src, int64_t ld, int B, int U, int kp,
                                                       int nsub, int rows_per_split, cv<T>* __restrict__ gpart,
                                                       int npanels) {
     using V = cv<T>;
@@ -432,8 +484,8 @@ __global__ __launch_bounds__(256) void k_gram_partial(const cv<T>* __restrict__ 
         for (int k = 0; k < 8; ++k) {
             const int c = (tid >> 5) + 8 * k;
             const int ca = colA0 + c, cb = colB0 + c;
-            As[i][c] = (row < r_hi && ca < U) ? H[(int64_t)ca * ld + row] : czero<T>();
-            Bs[i][c] = (row < r_hi && cb < U) ? H[(int64_t)cb * ld + row] : czero<T>();
+            As[i][c] = (row < r_hi && ca < U) ? src.load((int64_t)ca * ld + row, ca) : czero<T>();
+            Bs[i][c] = (row < r_hi && cb < U) ? src.load((int64_t)cb * ld + row, cb) : czero<T>();
         }
         __syncthreads();
 #pragma unroll 4
@@ -534,8 +586,20 @@ template <typename T> static hipError_t launch_gram_t(const GramLaunch& L, hipSt
     const int nsub = nb * (nb + 1) / 2;
     int rps = (L.B + L.nsplit - 1) / L.nsplit;
     rps = (rps + 31) / 32 * 32;
-    hipLaunchKernelGGL(k_gram_partial<T>, dim3(L.npanels * nsub, L.nsplit), dim3(256), 0, st, (const cv<T>*)L.H,
-                       L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels);
+    if (L.src_kind == SRC_BF16) {
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_gram_partial<T, SrcBF16>), dim3(L.npanels * nsub, L.nsplit), dim3(256), 0, st,
+                               SrcBF16{L.q_re16, L.q_im16}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart,
+                               L.npanels);
+    } else if (L.src_kind == SRC_FP8) {
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_gram_partial<T, SrcFP8>), dim3(L.npanels * nsub, L.nsplit), dim3(256), 0, st,
+                               SrcFP8{L.q_re8, L.q_im8, L.q_scale}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart,
+                               L.npanels);
+    } else {
+        hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>>), dim3(L.npanels * nsub, L.nsplit), dim3(256), 0, st,
+                           SrcC<T>{(const cv<T>*)L.H}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // M is written twice: column-major (used by the sweep) and row-major (the

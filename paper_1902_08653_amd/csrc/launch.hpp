@@ -56,9 +56,20 @@ int wg_occupancy(bool c128, int nt, size_t bytes);
 hipError_t launch_fuse(bool c128, const void* xloc, const double* msum, int C, int U, double N0, void* x,
                        hipStream_t st);
 
+// Where the panel engine reads H from.
+enum SrcKind { SRC_COMPLEX = 0, SRC_BF16 = 1, SRC_FP8 = 2 };
+
 // Cooperative panel engine for one large instance.
 struct PanelLaunch {
     bool c128;
+    int src_kind = SRC_COMPLEX;      // SRC_BF16 / SRC_FP8 (FP32 arithmetic only): q_* below
+    const uint16_t* q_re16 = nullptr;
+    const uint16_t* q_im16 = nullptr;
+    const uint8_t* q_re8 = nullptr;
+    const uint8_t* q_im8 = nullptr;
+    const float* q_scale = nullptr;
+    const void* bias = nullptr;      // optional per-column addend of b_u (inner correction solve)
+    const uint32_t* done = nullptr;  // optional device flag: nonzero -> the launch does nothing
     int kp;              // panel width (columns per panel)
     int rpl;             // rows per lane (each workgroup owns 64*rpl rows)
     int P;               // workgroups (one per row block), all co-resident
@@ -83,6 +94,12 @@ int panel_max_coresident(bool c128, int kp, int rpl);
 // Panel Gram blocks and the inverses of the Gauss-Seidel splitting matrices.
 struct GramLaunch {
     bool c128;
+    int src_kind = SRC_COMPLEX;
+    const uint16_t* q_re16 = nullptr;
+    const uint16_t* q_im16 = nullptr;
+    const uint8_t* q_re8 = nullptr;
+    const uint8_t* q_im8 = nullptr;
+    const float* q_scale = nullptr;
     int kp;
     int B, U, npanels, nsplit;
     const void* H;
@@ -127,6 +144,41 @@ struct SparseLaunch {
     hipEvent_t ev_sweep0, ev_sweep1;   // optional events around the sweep kernel
 };
 hipError_t launch_sparse(const SparseLaunch& L, hipStream_t st);
+
+// Mixed-precision refinement (outer FP64 steps around the FP32 panel engine).
+struct MixedLaunch {
+    int src_kind;            // SRC_BF16 or SRC_FP8
+    int B, U;
+    const void* H;           // complex128 caller data
+    int64_t ld;
+    const void* y;
+    const void* x0;
+    void* x;                 // complex128 iterate / output
+    uint16_t* q_re16;
+    uint16_t* q_im16;
+    uint8_t* q_re8;
+    uint8_t* q_im8;
+    float* q_scale;
+    double* colamax;         // [U]
+    void* rpart;             // [nchunk][B] double2
+    int nchunk;
+    void* r64;               // [B] double2
+    void* g32;               // [U] float2 (inner bias)
+    void* d32;               // [U] float2 (inner iterate)
+    void* r32;               // [B] float2 (inner residual, starts at 0)
+    uint32_t* ctr;           // panel engine control words to reset per outer step
+    int nctr;
+    uint32_t* done;          // device flag
+    cdm_info* info;
+    double lambda;
+    double tol;
+    int inner_sweeps;
+};
+hipError_t launch_quantize(const MixedLaunch& L, hipStream_t st);
+hipError_t launch_mixed_start(const MixedLaunch& L, hipStream_t st);
+hipError_t launch_mixed_outer_head(const MixedLaunch& L, hipStream_t st);
+hipError_t launch_mixed_outer_tail(const MixedLaunch& L, hipStream_t st);
+hipError_t launch_mixed_finish(const MixedLaunch& L, hipStream_t st);
 
 // r0 = y (cold) or y - H x0 (warm); x = x0 or 0.
 struct InitLaunch {

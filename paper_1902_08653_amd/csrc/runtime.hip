@@ -85,6 +85,20 @@ struct cdm_plan {
     double* res_r = nullptr;
     double* res_col = nullptr;
     double* res_out = nullptr;
+    // mixed precision
+    bool mixed = false;
+    int src_kind = SRC_COMPLEX;
+    uint16_t* q_re16 = nullptr;
+    uint16_t* q_im16 = nullptr;
+    uint8_t* q_re8 = nullptr;
+    uint8_t* q_im8 = nullptr;
+    float* q_scale = nullptr;
+    double* colamax = nullptr;
+    void* mx_r64 = nullptr;
+    void* mx_g32 = nullptr;
+    void* mx_d32 = nullptr;
+    void* mx_r32 = nullptr;
+    uint32_t* mx_done = nullptr;
     // sparse (CSR input)
     int32_t* sp_colptr = nullptr;
     int32_t* sp_fill = nullptr;
@@ -266,6 +280,114 @@ static int32_t run_sparse(cdm_plan* p, const void* val, const int32_t* rowptr, c
     return CDM_OK;
 }
 
+static constexpr int kInnerSweeps = 8;   // low-precision CD sweeps per outer refinement step
+
+static int32_t run_resid(cdm_plan* p, const void* H, int64_t ldh, const void* y, double lambda, const void* x,
+                         double* out, hipStream_t st);
+
+// Mixed precision: quantise H, Gram blocks of the quantised copy, then T_max outer
+// FP64 steps (each a no-op once converged) around the FP32 panel engine.
+static int32_t solve_mixed(cdm_plan* p, const void* H, int64_t ldh, const void* y, double lambda, const void* x0,
+                           void* x, cdm_info* inf, hipStream_t st) {
+    const cdm_desc& d = p->d;
+    MixedLaunch M;
+    M.src_kind = p->src_kind;
+    M.B = d.B;
+    M.U = d.U;
+    M.H = H;
+    M.ld = ldh;
+    M.y = y;
+    M.x0 = x0;
+    M.x = x;
+    M.q_re16 = p->q_re16;
+    M.q_im16 = p->q_im16;
+    M.q_re8 = p->q_re8;
+    M.q_im8 = p->q_im8;
+    M.q_scale = p->q_scale;
+    M.colamax = p->colamax;
+    M.rpart = p->rpart;
+    M.nchunk = p->nchunk;
+    M.r64 = p->mx_r64;
+    M.g32 = p->mx_g32;
+    M.d32 = p->mx_d32;
+    M.r32 = p->mx_r32;
+    M.ctr = p->ctr;
+    M.nctr = kCtrWords;
+    M.done = p->mx_done;
+    M.info = inf;
+    M.lambda = lambda;
+    M.tol = d.tol;
+    M.inner_sweeps = kInnerSweeps;
+    ev_record(p, 0, st);
+    HIP_TRY(launch_zero_u32(p->ctr, kCtrWords, st));
+    HIP_TRY(launch_quantize(M, st));
+    GramLaunch G;
+    G.c128 = false;
+    G.src_kind = p->src_kind;
+    G.q_re16 = p->q_re16;
+    G.q_im16 = p->q_im16;
+    G.q_re8 = p->q_re8;
+    G.q_im8 = p->q_im8;
+    G.q_scale = p->q_scale;
+    G.kp = p->kp;
+    G.B = d.B;
+    G.U = d.U;
+    G.npanels = p->npanels;
+    G.nsplit = p->nsplit;
+    G.H = nullptr;
+    G.ld = d.B;
+    G.gpart = p->gpart;
+    G.M = p->M;
+    G.e = p->e;
+    G.status = p->ctr + 3;
+    G.lambda = lambda;
+    HIP_TRY(launch_gram(G, st));
+    HIP_TRY(launch_mixed_start(M, st));
+    ev_record(p, 1, st);
+    ev_record(p, 2, st);
+    PanelLaunch L;
+    L.c128 = false;
+    L.src_kind = p->src_kind;
+    L.q_re16 = p->q_re16;
+    L.q_im16 = p->q_im16;
+    L.q_re8 = p->q_re8;
+    L.q_im8 = p->q_im8;
+    L.q_scale = p->q_scale;
+    L.bias = p->mx_g32;
+    L.done = p->mx_done;
+    L.kp = p->kp;
+    L.rpl = p->rpl;
+    L.P = p->P;
+    L.B = d.B;
+    L.U = d.U;
+    L.npanels = p->npanels;
+    L.H = nullptr;
+    L.ld = d.B;
+    L.r0 = p->mx_r32;
+    L.x = p->mx_d32;
+    L.M = p->M;
+    L.part = p->part;
+    L.gbuf = p->gbuf;
+    L.ctr = p->ctr;
+    L.lambda = lambda;
+    L.T_max = kInnerSweeps;
+    L.tol = 0.0;
+    L.timeout_ticks = p->timeout_ticks;
+    L.info = (cdm_info*)((char*)p->mx_done + 32);   // the inner launches' own record (unused)
+    for (int k = 0; k < d.T_max; ++k) {
+        HIP_TRY(launch_mixed_outer_head(M, st));
+        HIP_TRY(launch_panel(L, st));
+        HIP_TRY(launch_mixed_outer_tail(M, st));
+    }
+    HIP_TRY(launch_mixed_finish(M, st));
+    ev_record(p, 3, st);
+    int32_t s2 = run_resid(p, H, ldh, y, lambda, x, p->res_out, st);
+    if (s2) return s2;
+    HIP_TRY(launch_copy_resid(p->res_out, inf, 1, st));
+    ev_record(p, 4, st);
+    return CDM_OK;
+}
+
 extern "C" {
 
 int32_t cdm_version(void) { return CDM_ABI_VERSION; }
@@ -296,7 +418,9 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
     if (d.B < 1 || d.U < 1 || d.C < 1 || d.B % d.C) return CDM_ESHAPE;
     const int Bc = d.B / d.C;
     if (d.problem == CDM_DOWNLINK_ZF && Bc < d.U) return CDM_EINFEASIBLE;
-    if (d.precision != CDM_C128 && d.precision != CDM_C64) return CDM_ENOTIMPL;
+    const bool mixed = d.precision == CDM_MIXED_BF16 || d.precision == CDM_MIXED_FP8;
+    if (mixed && (d.problem != CDM_UPLINK_LMMSE || d.layout != CDM_DENSE || d.C != 1)) return CDM_ENOTIMPL;
+    if (mixed && !(d.tol > 0.0)) return CDM_EINVAL;
     if (d.layout == CDM_CSR && (d.problem != CDM_UPLINK_LMMSE || d.C != 1)) return CDM_ENOTIMPL;
     if (d.layout == CDM_CSR && (d.nnz < 0 || d.nnz > 0x7fffffffLL)) return CDM_ESHAPE;
     if (d.problem == CDM_DOWNLINK_ZF &&
@@ -305,7 +429,9 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
 
     cdm_plan* p = new cdm_plan();
     p->d = d;
-    p->c128 = d.precision == CDM_C128;
+    p->mixed = mixed;
+    p->src_kind = d.precision == CDM_MIXED_BF16 ? SRC_BF16 : (d.precision == CDM_MIXED_FP8 ? SRC_FP8 : SRC_COMPLEX);
+    p->c128 = d.precision == CDM_C128;      // mixed: the inner engine runs in FP32
     p->esz = p->c128 ? 16 : 8;
     st = device_setup(p);
     if (st) {
@@ -314,11 +440,16 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
     }
 
     if (d.layout == CDM_CSR) return create_sparse(p, plan);
+    if (mixed && d.engine == CDM_ENGINE_WG) {
+        delete p;
+        return CDM_ENOTIMPL;
+    }
 
     // engine choice: one cooperative launch for a single large instance, else WG
     int engine = d.engine;
     const double elems = (double)d.B * d.U;
     if (engine == CDM_ENGINE_AUTO) engine = (d.C == 1 && d.B >= 2048 && elems >= 4.0e6) ? CDM_ENGINE_PANEL : CDM_ENGINE_WG;
+    if (mixed) engine = CDM_ENGINE_PANEL;
     if (d.problem == CDM_DOWNLINK_ZF) engine = CDM_ENGINE_WG;
     if (engine == CDM_ENGINE_PANEL && d.C != 1) engine = CDM_ENGINE_WG;
     if (engine == CDM_ENGINE_WG && Bc > (p->c128 ? kWgMaxRows / 2 : kWgMaxRows)) engine = CDM_ENGINE_PANEL;
@@ -379,7 +510,21 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         o_part = ar.take(p->esz * 2 * (size_t)p->kp * p->P);
         o_gbuf = ar.take(p->esz * 2 * (size_t)p->kp * 2);
         o_e = ar.take(sizeof(double) * d.U);
-        o_rpart = ar.take(p->esz * (size_t)p->nchunk * d.B);
+        o_rpart = ar.take(16 * (size_t)p->nchunk * d.B);
+    }
+    size_t o_q1 = 0, o_q2 = 0, o_qs = 0, o_ca = 0, o_r64 = 0, o_g32 = 0, o_d32 = 0, o_r32 = 0, o_done = 0;
+    if (mixed) {
+        const size_t bu = (size_t)d.B * d.U;
+        const size_t qb = p->src_kind == SRC_BF16 ? 2 : 1;
+        o_q1 = ar.take(qb * bu);
+        o_q2 = ar.take(qb * bu);
+        o_qs = ar.take(4 * (size_t)((d.U + 127) / 128));
+        o_ca = ar.take(8 * (size_t)d.U);
+        o_r64 = ar.take(16 * (size_t)d.B);
+        o_g32 = ar.take(8 * (size_t)d.U);
+        o_d32 = ar.take(8 * (size_t)d.U);
+        o_r32 = ar.take(8 * (size_t)d.B);
+        o_done = ar.take(64);
     }
     const size_t o_res_rpart = ar.take(16 * (size_t)p->nchunk * d.B);
     const size_t o_res_r = ar.take(16 * (size_t)d.B);
@@ -427,6 +572,22 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         p->e = (double*)(b + o_e);
         p->rpart = b + o_rpart;
     }
+    if (mixed) {
+        if (p->src_kind == SRC_BF16) {
+            p->q_re16 = (uint16_t*)(b + o_q1);
+            p->q_im16 = (uint16_t*)(b + o_q2);
+        } else {
+            p->q_re8 = (uint8_t*)(b + o_q1);
+            p->q_im8 = (uint8_t*)(b + o_q2);
+        }
+        p->q_scale = (float*)(b + o_qs);
+        p->colamax = (double*)(b + o_ca);
+        p->mx_r64 = b + o_r64;
+        p->mx_g32 = b + o_g32;
+        p->mx_d32 = b + o_d32;
+        p->mx_r32 = b + o_r32;
+        p->mx_done = (uint32_t*)(b + o_done);
+    }
     p->res_rpart = (double*)(b + o_res_rpart);
     p->res_r = (double*)(b + o_res_r);
     p->res_col = (double*)(b + o_res_col);
@@ -442,7 +603,8 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         snprintf(buf, sizeof(buf),
                  "{\"engine\": \"panel\", \"precision\": \"%s\", \"B\": %d, \"U\": %d, \"panel\": %d, \"rpl\": %d, "
                  "\"workgroups\": %d, \"npanels\": %d, \"gram_splits\": %d, \"workspace\": %zu}",
-                 p->c128 ? "c128" : "c64", d.B, d.U, p->kp, p->rpl, p->P, p->npanels, p->nsplit, p->ws_bytes);
+                 mixed ? (p->src_kind == SRC_BF16 ? "mixed-bf16" : "mixed-fp8") : (p->c128 ? "c128" : "c64"), d.B, d.U,
+                 p->kp, p->rpl, p->P, p->npanels, p->nsplit, p->ws_bytes);
     p->text = buf;
     st = setup_timing(p);
     if (st) {
@@ -456,7 +618,7 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
 static int32_t run_resid(cdm_plan* p, const void* H, int64_t ldh, const void* y, double lambda, const void* x,
                          double* out, hipStream_t st) {
     ResidLaunch R;
-    R.c128 = p->c128;
+    R.c128 = p->c128 || p->mixed;   // mixed plans take complex128 H, y, x
     R.B = p->d.B;
     R.U = p->d.U;
     R.H = H;
@@ -532,6 +694,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         return CDM_OK;
     }
 
+    if (p->mixed) return solve_mixed(p, H, ldh, rhs, lambda, x0, x, inf, st);
     ev_record(p, 0, st);
     HIP_TRY(launch_zero_u32(p->ctr, p->engine == CDM_ENGINE_PANEL ? kCtrWords : 16, st));
     if (p->engine == CDM_ENGINE_WG) {
@@ -637,6 +800,34 @@ int32_t cdm_csr_transpose(cdm_plan* p, const void* val, const int32_t* rowptr, c
         HIP_TRY(hipMemcpyAsync(colptr_out, p->sp_colptr, 4 * ((size_t)p->d.U + 1), hipMemcpyDeviceToDevice, st));
     if (rowidx_out && nnz) HIP_TRY(hipMemcpyAsync(rowidx_out, p->sp_rowidx, 4 * nnz, hipMemcpyDeviceToDevice, st));
     if (cval_out && nnz) HIP_TRY(hipMemcpyAsync(cval_out, p->sp_cval, p->esz * nnz, hipMemcpyDeviceToDevice, st));
+    return CDM_OK;
+}
+
+int32_t cdm_quantized_copy(cdm_plan* p, const void* H, int64_t ldh, void* re_out, void* im_out, float* scale_out,
+                           void* stream) {
+    if (!p || !p->mixed || !H) return CDM_EINVAL;
+    if (ldh < p->d.B) return CDM_ESHAPE;
+    hipStream_t st = (hipStream_t)stream;
+    MixedLaunch M{};
+    M.src_kind = p->src_kind;
+    M.B = p->d.B;
+    M.U = p->d.U;
+    M.H = H;
+    M.ld = ldh;
+    M.q_re16 = p->q_re16;
+    M.q_im16 = p->q_im16;
+    M.q_re8 = p->q_re8;
+    M.q_im8 = p->q_im8;
+    M.q_scale = p->q_scale;
+    M.colamax = p->colamax;
+    HIP_TRY(launch_quantize(M, st));
+    const size_t n = (size_t)p->d.B * p->d.U * (p->src_kind == SRC_BF16 ? 2 : 1);
+    const void* qr = p->src_kind == SRC_BF16 ? (const void*)p->q_re16 : (const void*)p->q_re8;
+    const void* qi = p->src_kind == SRC_BF16 ? (const void*)p->q_im16 : (const void*)p->q_im8;
+    if (re_out) HIP_TRY(hipMemcpyAsync(re_out, qr, n, hipMemcpyDeviceToDevice, st));
+    if (im_out) HIP_TRY(hipMemcpyAsync(im_out, qi, n, hipMemcpyDeviceToDevice, st));
+    if (scale_out && p->src_kind == SRC_FP8)
+        HIP_TRY(hipMemcpyAsync(scale_out, p->q_scale, 4 * (size_t)((p->d.U + 127) / 128), hipMemcpyDeviceToDevice, st));
     return CDM_OK;
 }
 

@@ -283,3 +283,52 @@ def test_batched_hipgraph_replays_match_eager(dev, orc):
                                    ref_x[xo[k]:xo[k] + n[k]].astype(complex))
         assert abs(ref_info["resid"][k] - want) <= 1e-6 * want + 1e-14
         assert ref_info["resid"][k] < 1e-4
+
+
+# ----------------------------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+def test_mixed_refinement_reaches_fp64_oracle(dev, orc, kind):
+    """Low-precision inner sweeps with FP64 outer residuals reach the FP64 oracle's
+    converged solution to 1e-10, and the quantised copy is bit-exact with the oracle's
+    quantiser (checked through the converged result's dependence being nil and via
+    the residual)."""
+    from paper_1902_08653_amd import cdm
+    B, U = 2048, 1000
+    inst = inputs.dense_uplink(B, U, seed=21)
+    plan = cdm.Plan(B, U, precision=kind, T_max=40, tol=1e-12)
+    Hd, yd = to_dev(inst.H, inst.y, "c128", dev)
+    x, info = plan.solve(Hd, yd, N0=0.1)
+    torch.cuda.synchronize()
+    rec = cdm.parse_info(info)[0]
+    ref = orc.local_cd(inst.H, inst.y, 0.1, T_max=2000, tol=1e-14)
+    err = relerr(x.cpu().numpy(), ref["x"])
+    print(kind, plan.describe(), rec, err)
+    assert rec["flags"] == 0 and rec["rel_step"] <= 1e-12
+    assert err <= 1e-10
+    assert rec["resid"] <= 1e-11
+    assert 1 <= rec["sweeps"] <= 40 and rec["reserved"] == 8 * rec["sweeps"]
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+def test_quantized_copy_bit_exact(dev, orc, kind):
+    from paper_1902_08653_amd import cdm
+    B, U = 700, 300
+    inst = inputs.dense_uplink(B, U, seed=22)
+    H = np.array(inst.H)
+    H[:, 5] = 0                       # zero column; also an all-zero FP8 block below
+    H[3, 7] = 1e9 if kind == "bf16" else H[3, 7]
+    if kind == "fp8":
+        H[:, 256:] = 0
+    plan = cdm.Plan(B, U, precision=kind, T_max=2, tol=1e-6)
+    Hd, _ = to_dev(H, inst.y, "c128", dev)
+    out = plan.quantized_copy(Hd)
+    torch.cuda.synchronize()
+    ref = orc.quantize(H, kind)
+    if kind == "bf16":
+        assert np.array_equal(out[0].cpu().numpy().view(np.uint16), ref[0])
+        assert np.array_equal(out[1].cpu().numpy().view(np.uint16), ref[1])
+    else:
+        assert np.array_equal(out[0].cpu().numpy(), ref[0])
+        assert np.array_equal(out[1].cpu().numpy(), ref[1])
+        assert np.array_equal(out[2].cpu().numpy(), ref[2])

@@ -339,3 +339,53 @@ def test_column_scalars(orc):
     assert np.allclose(e, np.linalg.norm(inst.H, axis=0) ** 2, rtol=1e-14)
     assert np.allclose(m * (e + 0.2), 1.0, rtol=1e-15)
     assert np.allclose(n, e / (e + 0.2), rtol=1e-15)
+
+
+# ----------------------------------------------------------------------------- quantizers
+
+def test_bf16_codes_match_torch_rounding(orc):
+    import torch
+    rng = np.random.default_rng(0)
+    v = np.concatenate([rng.standard_normal(5000) * 10.0 ** rng.integers(-6, 6, 5000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3.0e38, -2.5e-40]])
+    f32 = torch.from_numpy(v.astype(np.float32))
+    want = f32.to(torch.bfloat16).view(torch.int16).numpy().astype(np.uint16)
+    got = np.array([orc.bf16_code(x) for x in v.astype(np.float32).astype(np.float64)], np.uint16)
+    assert np.array_equal(got, want)
+
+
+def test_e4m3_table_and_rounding(orc):
+    vals = np.array([orc.e4m3_value(c) for c in range(0x7f)])
+    assert vals[0] == 0 and vals[1] == 2.0 ** -9 and vals[8] == 2.0 ** -6 and vals[0x7e] == 448.0
+    assert np.all(np.diff(vals) > 0)               # monotone code -> value
+    rng = np.random.default_rng(1)
+    xs = np.concatenate([rng.uniform(-500, 500, 3000), rng.uniform(-0.02, 0.02, 3000),
+                         (vals[:-1] + vals[1:]) / 2, -(vals[:-1] + vals[1:]) / 2])
+    for x in xs.astype(np.float32):
+        c = orc.e4m3_code(x)
+        a = abs(float(x))
+        if a >= 448:
+            assert c & 0x7f == 0x7e
+            continue
+        d = np.abs(vals - a)
+        best = np.flatnonzero(d == d.min())
+        assert (c & 0x7f) in best
+        if len(best) == 2:                         # tie: the even code
+            assert (c & 0x7f) % 2 == 0
+        if a > 0:
+            assert (c >> 7) == (x < 0)
+
+
+def test_quantized_copy_error_levels(orc):
+    inst = inputs.dense_uplink(512, 256, seed=3)
+    re, im = orc.quantize(inst.H, "bf16")
+    deq = (re.astype(np.uint32) << 16).view(np.float32) + 1j * (im.astype(np.uint32) << 16).view(np.float32)
+    err = np.linalg.norm(deq.T - inst.H) / np.linalg.norm(inst.H)
+    assert 5e-4 < err < 4e-3
+    r8, i8, sc = orc.quantize(inst.H, "fp8")
+    vals = np.array([orc.e4m3_value(c) for c in range(256)])
+    blk = np.repeat(sc, 128)[:256]
+    deq8 = (vals[r8] + 1j * vals[i8]) * blk[:, None]
+    err8 = np.linalg.norm(deq8.T - inst.H) / np.linalg.norm(inst.H)
+    assert 5e-3 < err8 < 6e-2
+    assert np.all(np.abs(vals[r8]) <= 448) and np.max(np.abs(vals[r8])) == 448
