@@ -389,3 +389,62 @@ def test_quantized_copy_error_levels(orc):
     err8 = np.linalg.norm(deq8.T - inst.H) / np.linalg.norm(inst.H)
     assert 5e-3 < err8 < 6e-2
     assert np.all(np.abs(vals[r8]) <= 448) and np.max(np.abs(vals[r8])) == 448
+
+
+# ----------------------------------------------------------------------------- warm-start network
+
+def test_mlp_oracle_gradients_match_finite_differences():
+    from oracle import mlp_oracle as mo
+    rng = np.random.default_rng(0)
+    shape = (5, 7, 6, 2)
+    n = 5 * 7 + 7 + 7 * 6 + 6 + 6 * 2 + 2
+    flat = rng.standard_normal(n) * 0.5
+    X = rng.standard_normal((11, 5))
+    T = rng.standard_normal((11, 2))
+    g = mo.gradients(flat, shape, X, T)
+    h = 1e-6
+    fd = np.zeros(n)
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = h
+        fd[k] = (mo.loss(flat + e, shape, X, T) - mo.loss(flat - e, shape, X, T)) / (2 * h)
+    assert np.max(np.abs(fd - g)) <= 1e-7 * max(1.0, np.max(np.abs(g)))
+
+
+def test_mlp_oracle_forward_hand_case():
+    """Identity-like weights: Y = relu(relu(X) ) @ [[1, 0], [0, -1]] + b3."""
+    from oracle import mlp_oracle as mo
+    shape = (2, 2, 2, 2)
+    W1 = np.eye(2)
+    W2 = np.eye(2)
+    W3 = np.array([[1.0, 0.0], [0.0, -1.0]])
+    flat = np.concatenate([W1.ravel(), [0, 0], W2.ravel(), [0.5, 0], W3.ravel(), [1.0, 2.0]])
+    X = np.array([[1.0, -3.0], [-2.0, 4.0]])
+    Y = mo.forward(flat, shape, X)["Y"]
+    assert np.allclose(Y, [[2.5, 2.0], [1.5, -2.0]])
+
+
+def test_bf16_round_matches_torch():
+    import torch
+    from oracle import mlp_oracle as mo
+    v = np.random.default_rng(3).standard_normal(1000) * 1e3
+    want = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mo.bf16_round(v), want)
+
+
+def test_mlp_oracle_adam_first_step_is_signed_lr():
+    """With zero moments, the first bias-corrected Adam step is lr * g / (|g| + eps)."""
+    from oracle import mlp_oracle as mo
+    g = np.array([0.5, -2.0, 1e-3])
+    w, _, _ = mo.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, 0.01, eps=0.0)
+    assert np.allclose(w, [-0.01, 0.01, -0.01])
+
+
+def test_mlp_oracle_features_single_user():
+    """One user: z = h^H y / (||h||^2 + lambda); a textbook scalar case."""
+    from oracle import mlp_oracle as mo
+    h = np.array([[1 + 1j], [2 - 1j]])
+    y = np.array([1.0, 1j])
+    F = mo.features([(h, y)], 0.5)
+    # h^H y = (1-1j)*1 + (2+1j)*1j = 1 - 1j + 2j - 1 = 1j ; ||h||^2 = 7
+    assert np.allclose(F[0], [0.0, 1 / 7.5, 1 / 7.5, 7.0, 0.5, 2 / 2048, 0.5, 1.0])
