@@ -204,6 +204,44 @@ int32_t cdm_quantized_copy(cdm_plan* plan, const void* H, int64_t ldh, void* re_
 int32_t cdm_residual(cdm_plan* plan, const void* H, int64_t ldh, const void* y, double N0,
                      double Ex, const void* x, double* out, void* stream);
 
+/* Per-coordinate features of a batched plan's packed instances, for the
+ * learned warm start (one row of 8 floats per user u of instance i, rows in the
+ * packed x order): [Re z, Im z, |z|, ||h_u||^2, lambda, m_i/2048, n_i/m_i, 1] with
+ * z = h_u^H y_i / (||h_u||^2 + lambda), the regularised matched filter of the
+ * instance, accumulated in FP64.  F: device float[sum_i n_i][8].  Errors: CDM_EINVAL. */
+int32_t cdm_batched_features(cdm_plan* plan, const void* H, const void* y, double N0, double Ex, float* F,
+                             void* stream);
+
+/* ---- warm-start network -------------------------------------------------------
+ * A per-coordinate MLP nin -> h1 -> h2 -> nout with ReLU after the first two layers,
+ * trained by the library's own kernels: BF16 operands on MFMA with FP32
+ * accumulation, FP32 master weights, mean-squared-error loss, Adam.  Its output for
+ * a feature row is a warm start (Re, Im) for the coordinate (cdm_solve_batched x0).
+ * Parameters are one flat FP32 array: W1 (nin x h1, row-major), b1 (h1), W2, b2, W3, b3.
+ * All row matrices are row-major; X: rows x nin, T and Y: rows x nout (device FP32).
+ * Calls on one network are ordered by their stream and share its activation buffers.
+ * Errors: CDM_EINVAL (NULL handle or operand, rows outside 1..max_rows, count not
+ * the parameter count), CDM_ESHAPE (a width < 1), CDM_ENOMEM, CDM_EHIP. */
+typedef struct cdm_mlp cdm_mlp;
+int32_t cdm_mlp_create(int32_t nin, int32_t h1, int32_t h2, int32_t nout, int32_t max_rows, cdm_mlp** out);
+int64_t cdm_mlp_param_count(const cdm_mlp* mlp);
+/* host float[count] in / out; set also resets the Adam state */
+int32_t cdm_mlp_set_weights(cdm_mlp* mlp, const float* params, int64_t count);
+int32_t cdm_mlp_get_weights(const cdm_mlp* mlp, float* params, int64_t count);
+/* Y (device, may be NULL) = network(X) */
+int32_t cdm_mlp_forward(cdm_mlp* mlp, const float* X, int32_t rows, float* Y, void* stream);
+/* gradients of mean((Y - T)^2) into grads (device float[count], may be NULL) and the
+ * per-256-element partial sums of (Y - T)^2 into loss_parts (device, may be NULL) */
+int32_t cdm_mlp_gradients(cdm_mlp* mlp, const float* X, const float* T, int32_t rows, float* grads,
+                          float* loss_parts, void* stream);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on a mini-batch */
+int32_t cdm_mlp_train_step(cdm_mlp* mlp, const float* X, const float* T, int32_t rows, float lr, void* stream);
+/* Warm start from feature rows: x0[k] = Y[k][0] + i Y[k][1] for k < rows (any count;
+ * evaluated in chunks of max_rows), written as interleaved complex in `precision`
+ * (CDM_C128 or CDM_C64) into device x0.  Needs nout == 2.  Errors: CDM_EINVAL. */
+int32_t cdm_mlp_predict(cdm_mlp* mlp, const float* X, int64_t rows, void* x0, int32_t precision, void* stream);
+int32_t cdm_mlp_destroy(cdm_mlp* mlp);
+
 /* Human-readable description of the plan's engine, tiles and workspace
  * (NUL-terminated, truncated to len bytes). */
 int32_t cdm_plan_describe(const cdm_plan* plan, char* buf, int32_t len);

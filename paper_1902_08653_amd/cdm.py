@@ -52,7 +52,9 @@ assert INFO_DTYPE.itemsize == 32
 
 EXPORTS = ["cdm_version", "cdm_status_string", "cdm_last_error", "cdm_create", "cdm_solve",
            "cdm_create_batched", "cdm_batched_offsets", "cdm_solve_batched", "cdm_residual",
-           "cdm_plan_describe", "cdm_plan_timings", "cdm_stream_copy", "cdm_csr_transpose", "cdm_quantized_copy", "cdm_destroy"]
+           "cdm_plan_describe", "cdm_plan_timings", "cdm_stream_copy", "cdm_csr_transpose", "cdm_quantized_copy", "cdm_batched_features", "cdm_mlp_create",
+           "cdm_mlp_param_count", "cdm_mlp_set_weights", "cdm_mlp_get_weights", "cdm_mlp_forward",
+           "cdm_mlp_gradients", "cdm_mlp_train_step", "cdm_mlp_predict", "cdm_mlp_destroy", "cdm_destroy"]
 
 _lib = None
 
@@ -92,6 +94,26 @@ def lib():
         L.cdm_csr_transpose.restype = i32
         L.cdm_quantized_copy.argtypes = [P, P, i64, P, P, P, P]
         L.cdm_quantized_copy.restype = i32
+        L.cdm_batched_features.argtypes = [P, P, P, f64, f64, P, P]
+        L.cdm_batched_features.restype = i32
+        L.cdm_mlp_create.argtypes = [i32, i32, i32, i32, i32, C.POINTER(P)]
+        L.cdm_mlp_create.restype = i32
+        L.cdm_mlp_param_count.argtypes = [P]
+        L.cdm_mlp_param_count.restype = i64
+        L.cdm_mlp_set_weights.argtypes = [P, P, i64]
+        L.cdm_mlp_set_weights.restype = i32
+        L.cdm_mlp_get_weights.argtypes = [P, P, i64]
+        L.cdm_mlp_get_weights.restype = i32
+        L.cdm_mlp_forward.argtypes = [P, P, i32, P, P]
+        L.cdm_mlp_forward.restype = i32
+        L.cdm_mlp_gradients.argtypes = [P, P, P, i32, P, P, P]
+        L.cdm_mlp_gradients.restype = i32
+        L.cdm_mlp_train_step.argtypes = [P, P, P, i32, C.c_float, P]
+        L.cdm_mlp_train_step.restype = i32
+        L.cdm_mlp_predict.argtypes = [P, P, i64, P, i32, P]
+        L.cdm_mlp_predict.restype = i32
+        L.cdm_mlp_destroy.argtypes = [P]
+        L.cdm_mlp_destroy.restype = i32
         L.cdm_destroy.argtypes = [P]
         L.cdm_destroy.restype = i32
         _lib = L
@@ -250,6 +272,16 @@ class BatchedPlan:
         _check(lib().cdm_plan_describe(self._h, buf, 1024), "cdm_plan_describe")
         return buf.value.decode()
 
+    def features(self, H, y, N0=0.1, Ex=1.0, out=None, stream=None):
+        """Per-coordinate feature rows (sum n_i x 8 float32) of the packed batch."""
+        import torch
+        F = out
+        if F is None:
+            F = torch.empty((int(self.n.astype(np.int64).sum()), 8), dtype=torch.float32, device=y.device)
+        _check(lib().cdm_batched_features(self._h, _ptr(H), _ptr(y), float(N0), float(Ex), _ptr(F),
+                                          _stream(stream)), "cdm_batched_features")
+        return F
+
     def solve(self, H, y, N0=0.1, Ex=1.0, x0=None, x=None, info=None, stream=None):
         import torch
         if x is None:
@@ -263,6 +295,88 @@ class BatchedPlan:
     def close(self):
         if getattr(self, "_h", None):
             lib().cdm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The warm-start network (cdm_mlp_*): nin -> h1 -> h2 -> nout, ReLU, BF16 MFMA."""
+
+    def __init__(self, nin=8, h1=512, h2=512, nout=2, max_rows=8192):
+        h = C.c_void_p()
+        _check(lib().cdm_mlp_create(int(nin), int(h1), int(h2), int(nout), int(max_rows), C.byref(h)),
+               "cdm_mlp_create")
+        self._h = h
+        self.shape = (nin, h1, h2, nout)
+        self.max_rows = max_rows
+        self.nparam = int(lib().cdm_mlp_param_count(h))
+
+    def split(self, flat):
+        nin, h1, h2, nout = self.shape
+        sizes = [nin * h1, h1, h1 * h2, h2, h2 * nout, nout]
+        shapes = [(nin, h1), (h1,), (h1, h2), (h2,), (h2, nout), (nout,)]
+        out, k = [], 0
+        for sz, sh in zip(sizes, shapes):
+            out.append(np.asarray(flat[k:k + sz]).reshape(sh))
+            k += sz
+        return out
+
+    def init(self, seed=0):
+        """He-style initialisation from a seeded generator (host), uploaded."""
+        rng = np.random.default_rng(seed)
+        nin, h1, h2, nout = self.shape
+        parts = [rng.standard_normal((nin, h1)) * np.sqrt(2.0 / nin), np.zeros(h1),
+                 rng.standard_normal((h1, h2)) * np.sqrt(2.0 / h1), np.zeros(h2),
+                 rng.standard_normal((h2, nout)) * np.sqrt(1.0 / h2), np.zeros(nout)]
+        self.set_weights(np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32))
+
+    def set_weights(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(lib().cdm_mlp_set_weights(self._h, flat.ctypes.data, self.nparam), "cdm_mlp_set_weights")
+
+    def get_weights(self):
+        out = np.zeros(self.nparam, np.float32)
+        _check(lib().cdm_mlp_get_weights(self._h, out.ctypes.data, self.nparam), "cdm_mlp_get_weights")
+        return out
+
+    def forward(self, X, Y=None, stream=None):
+        import torch
+        if Y is None:
+            Y = torch.empty((X.shape[0], self.shape[3]), dtype=torch.float32, device=X.device)
+        _check(lib().cdm_mlp_forward(self._h, _ptr(X), int(X.shape[0]), _ptr(Y), _stream(stream)),
+               "cdm_mlp_forward")
+        return Y
+
+    def gradients(self, X, T, stream=None):
+        import torch
+        g = torch.empty(self.nparam, dtype=torch.float32, device=X.device)
+        parts = torch.empty((X.shape[0] * self.shape[3] + 255) // 256, dtype=torch.float32, device=X.device)
+        _check(lib().cdm_mlp_gradients(self._h, _ptr(X), _ptr(T), int(X.shape[0]), _ptr(g), _ptr(parts),
+                                       _stream(stream)), "cdm_mlp_gradients")
+        return g, parts
+
+    def train_step(self, X, T, lr, stream=None):
+        _check(lib().cdm_mlp_train_step(self._h, _ptr(X), _ptr(T), int(X.shape[0]), float(lr),
+                                        _stream(stream)), "cdm_mlp_train_step")
+
+    def predict(self, X, dtype, out=None, stream=None):
+        """Warm start x0 (complex `dtype`, one entry per feature row) from the network."""
+        import torch
+        if out is None:
+            out = torch.empty(X.shape[0], dtype=dtype, device=X.device)
+        prec = _PREC["c128" if dtype == torch.complex128 else "c64"]
+        _check(lib().cdm_mlp_predict(self._h, _ptr(X), int(X.shape[0]), _ptr(out), prec, _stream(stream)),
+               "cdm_mlp_predict")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cdm_mlp_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -1,0 +1,443 @@
+// k_mlp.hip -- the small per-coordinate MLP of the learned warm start.
+//
+// Three weight layers F -> H1 -> H2 -> 2 with ReLU between them; BF16 operands on
+// MFMA (v_mfma_f32_16x16x16_bf16) with FP32 accumulation; FP32 master weights and
+// Adam state.  The GEMM is generic over strides so that one kernel serves the
+// forward products, the weight gradients (A^T B) and the input gradients (A B^T).
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace cdm {
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (unsigned short)((u >> 16) | 0x40u);
+    uint32_t q = u >> 16;
+    const uint32_t rem = u & 0xffffu;
+    if (rem > 0x8000u || (rem == 0x8000u && (q & 1u))) q += 1u;
+    return (unsigned short)q;
+}
+
+// C[m][n] = sum_k A(m, k) B(k, n) (+ bias[n]); A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn];
+// C row-major with leading dimension ldc.  64 x 64 tile per workgroup of 4 waves,
+// each wave a 32 x 32 block of 2 x 2 MFMA 16 x 16 x 16 tiles.  beta: 0 overwrite, 1 accumulate.
+constexpr int GT = 64;
+constexpr int GK = 16;
+
+__global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, int64_t sam, int64_t sak,
+                                                   const float* __restrict__ Bm, int64_t sbk, int64_t sbn,
+                                                   float* __restrict__ C, int64_t ldc, int M, int N, int K,
+                                                   const float* __restrict__ bias, int beta) {
+    __shared__ unsigned short As[GT][GK + 4];
+    __shared__ unsigned short Bs[GK][GT + 4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+    const int wm = (wid >> 1) * 32, wn = (wid & 1) * 32;
+    f32x4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        // stage A (64 x 16) and B (16 x 64) as BF16: 1024 elements each, 4 per thread
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q;
+            const int am = e / GK, ak = e % GK;
+            const int gm = m0 + am, gk = k0 + ak;
+            As[am][ak] = (gm < M && gk < K) ? f32_to_bf16(A[(int64_t)gm * sam + (int64_t)gk * sak]) : (unsigned short)0;
+            const int bk = e / GT, bn = e % GT;
+            const int hk = k0 + bk, hn = n0 + bn;
+            Bs[bk][bn] = (hk < K && hn < N) ? f32_to_bf16(Bm[(int64_t)hk * sbk + (int64_t)hn * sbn]) : (unsigned short)0;
+        }
+        __syncthreads();
+        bf16x4_t a[2], b[2];
+        const int kk = 4 * (lane >> 4);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int r = wm + 16 * i + (lane & 15);
+            a[i] = bf16x4_t{(short)As[r][kk], (short)As[r][kk + 1], (short)As[r][kk + 2], (short)As[r][kk + 3]};
+            const int c = wn + 16 * i + (lane & 15);
+            b[i] = bf16x4_t{(short)Bs[kk][c], (short)Bs[kk + 1][c], (short)Bs[kk + 2][c], (short)Bs[kk + 3][c]};
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // D layout: lane -> column (lane & 15), rows 4 * (lane >> 4) + r
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                const int gn = n0 + wn + 16 * j + (lane & 15);
+                if (gm < M && gn < N) {
+                    float v = acc[i][j][r];
+                    if (bias) v += bias[gn];
+                    float* cp = &C[(int64_t)gm * ldc + gn];
+                    *cp = beta ? (*cp + v) : v;
+                }
+            }
+}
+
+hipError_t launch_gemm_bf16(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk, int64_t sbn, float* C,
+                            int64_t ldc, int M, int N, int K, const float* bias, int beta, hipStream_t st) {
+    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, beta);
+    return hipGetLastError();
+}
+
+// A = relu(Z)
+__global__ void k_relu(const float* __restrict__ Z, float* __restrict__ A, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) A[i] = Z[i] > 0.f ? Z[i] : 0.f;
+}
+// dZ = dA * [Z > 0]
+__global__ void k_relu_bwd(const float* __restrict__ Z, const float* __restrict__ dA, float* __restrict__ dZ, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dZ[i] = Z[i] > 0.f ? dA[i] : 0.f;
+}
+// dO = 2 (O - T) / (N * nout); per-block partial sums of (O - T)^2
+__global__ void k_mse(const float* __restrict__ O, const float* __restrict__ Tg, float* __restrict__ dO, int64_t n,
+                      float scale, float* __restrict__ part) {
+    __shared__ float s[256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float e = 0.f;
+    if (i < n) {
+        const float d = O[i] - Tg[i];
+        dO[i] = 2.f * d * scale;
+        e = d * d;
+    }
+    s[threadIdx.x] = e;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+// column sums of an M x N row-major matrix (bias gradients), fixed order per column
+__global__ void k_colsum(const float* __restrict__ X, int M, int N, float* __restrict__ out) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.f;
+    for (int m = 0; m < M; ++m) s += X[(int64_t)m * N + n];
+    out[n] = s;
+}
+// Adam (bias-corrected), FP32 master weights
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m1, float* __restrict__ m2,
+                       int64_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float a = b1 * m1[i] + (1.f - b1) * gi;
+    const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+    m1[i] = a;
+    m2[i] = b;
+    w[i] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+}
+
+hipError_t launch_relu(const float* Z, float* A, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_relu, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Z, A, n);
+    return hipGetLastError();
+}
+hipError_t launch_relu_bwd(const float* Z, const float* dA, float* dZ, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_relu_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Z, dA, dZ, n);
+    return hipGetLastError();
+}
+hipError_t launch_mse(const float* O, const float* T, float* dO, int64_t n, float scale, float* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_mse, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, O, T, dO, n, scale, part);
+    return hipGetLastError();
+}
+hipError_t launch_colsum(const float* X, int M, int N, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, st, X, M, N, out);
+    return hipGetLastError();
+}
+hipError_t launch_adam(float* w, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t st) {
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, g, m1, m2, n, lr, b1, b2, eps,
+                       c1, c2);
+    return hipGetLastError();
+}
+
+// ---- per-coordinate features of a packed uneven batch --------------------------
+// One wave per (instance, user): z = h_u^H y / (||h_u||^2 + lambda) (regularised
+// matched filter), e = ||h_u||^2.  Row layout (NF = 8 floats):
+//   [Re z, Im z, |z|, e, lambda, m/2048, n/m, 1]
+template <typename V>
+__global__ __launch_bounds__(256) void k_features(const V* __restrict__ H, const V* __restrict__ Y,
+                                                  const WgJob* __restrict__ jobs, const int64_t* __restrict__ row_off,
+                                                  int njobs, double lambda, float* __restrict__ F) {
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // locate (job, user) by a binary search over the row offsets
+    int lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (row_off[mid] <= gw) lo = mid;
+        else hi = mid;
+    }
+    const WgJob jb = jobs[lo];
+    const int64_t u = gw - row_off[lo];
+    if (lo >= njobs || u >= jb.n || u < 0) return;
+    const V* h = H + jb.h_off + u * jb.ld;
+    const V* y = Y + jb.y_off;
+    double gr = 0.0, gi = 0.0, e = 0.0;
+    for (int i = lane; i < jb.m; i += 64) {
+        const V hv = h[i], yv = y[i];
+        gr += (double)hv.x * yv.x + (double)hv.y * yv.y;
+        gi += (double)hv.x * yv.y - (double)hv.y * yv.x;
+        e += (double)hv.x * hv.x + (double)hv.y * hv.y;
+    }
+    gr = wave_allsum(gr);
+    gi = wave_allsum(gi);
+    e = wave_allsum(e);
+    if (lane == 0) {
+        const double den = e + lambda;
+        const double zr = den > 0.0 ? gr / den : 0.0, zi = den > 0.0 ? gi / den : 0.0;
+        float* f = F + gw * 8;
+        f[0] = (float)zr;
+        f[1] = (float)zi;
+        f[2] = (float)sqrt(zr * zr + zi * zi);
+        f[3] = (float)e;
+        f[4] = (float)lambda;
+        f[5] = (float)jb.m / 2048.f;
+        f[6] = (float)jb.n / (float)jb.m;
+        f[7] = 1.f;
+    }
+}
+
+hipError_t launch_features(bool c128, const void* H, const void* Y, const WgJob* jobs, const int64_t* row_off,
+                           int njobs, int64_t nrows, double lambda, float* F, hipStream_t st) {
+    if (c128)
+        hipLaunchKernelGGL(k_features<double2>, dim3((unsigned)((nrows + 3) / 4)), dim3(256), 0, st,
+                           (const double2*)H, (const double2*)Y, jobs, row_off, njobs, lambda, F);
+    else
+        hipLaunchKernelGGL(k_features<float2>, dim3((unsigned)((nrows + 3) / 4)), dim3(256), 0, st, (const float2*)H,
+                           (const float2*)Y, jobs, row_off, njobs, lambda, F);
+    return hipGetLastError();
+}
+
+// (rows x 2) FP32 network output -> interleaved complex warm start
+template <typename V>
+__global__ void k_out_complex(const float2* __restrict__ O, V* __restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const float2 o = O[i];
+        V v;
+        v.x = o.x;
+        v.y = o.y;
+        x[i] = v;
+    }
+}
+
+hipError_t launch_out_complex(const float* O, void* x, int64_t n, bool c128, hipStream_t st) {
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (c128)
+        hipLaunchKernelGGL(k_out_complex<double2>, grid, dim3(256), 0, st, (const float2*)O, (double2*)x, n);
+    else
+        hipLaunchKernelGGL(k_out_complex<float2>, grid, dim3(256), 0, st, (const float2*)O, (float2*)x, n);
+    return hipGetLastError();
+}
+
+}  // namespace cdm
+
+// ============================================================================
+// C ABI of the warm-start MLP (host side)
+// ============================================================================
+namespace {
+struct Mlp {
+    int nin, h1, h2, nout, max_rows;
+    int64_t nparam;
+    float *w = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;
+    float *Z1, *A1, *Z2, *A2, *O, *dO, *dA2, *dZ2, *dA1, *dZ1, *part;
+    void* ws = nullptr;
+    int64_t step = 0;
+    // parameter block offsets: W1 b1 W2 b2 W3 b3
+    int64_t oW1, ob1, oW2, ob2, oW3, ob3;
+};
+thread_local char g_mlp_err[256] = "";
+}  // namespace
+
+struct cdm_mlp : Mlp {};
+
+using namespace cdm;
+
+#define MLP_TRY(call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            snprintf(g_mlp_err, sizeof(g_mlp_err), "%s: %s", #call, hipGetErrorString(e_)); \
+            return CDM_EHIP;                                                                \
+        }                                                                                   \
+    } while (0)
+
+static hipError_t mlp_forward(cdm_mlp* n, const float* X, int rows, hipStream_t st) {
+    hipError_t e;
+    float* w = n->w;
+    if ((e = launch_gemm_bf16(X, n->nin, 1, w + n->oW1, n->h1, 1, n->Z1, n->h1, rows, n->h1, n->nin, w + n->ob1, 0, st)))
+        return e;
+    if ((e = launch_relu(n->Z1, n->A1, (int64_t)rows * n->h1, st))) return e;
+    if ((e = launch_gemm_bf16(n->A1, n->h1, 1, w + n->oW2, n->h2, 1, n->Z2, n->h2, rows, n->h2, n->h1, w + n->ob2, 0, st)))
+        return e;
+    if ((e = launch_relu(n->Z2, n->A2, (int64_t)rows * n->h2, st))) return e;
+    return launch_gemm_bf16(n->A2, n->h2, 1, w + n->oW3, n->nout, 1, n->O, n->nout, rows, n->nout, n->h2, w + n->ob3,
+                            0, st);
+}
+
+// gradients of the mean squared error (1 / (rows * nout)) sum (O - T)^2 into n->g
+static hipError_t mlp_backward(cdm_mlp* n, const float* X, const float* T, int rows, hipStream_t st) {
+    hipError_t e;
+    float* w = n->w;
+    float* g = n->g;
+    const int64_t no = (int64_t)rows * n->nout;
+    if ((e = launch_mse(n->O, T, n->dO, no, 1.f / (float)no, n->part, st))) return e;
+    // layer 3
+    if ((e = launch_gemm_bf16(n->A2, 1, n->h2, n->dO, n->nout, 1, g + n->oW3, n->nout, n->h2, n->nout, rows, nullptr, 0, st)))
+        return e;
+    if ((e = launch_colsum(n->dO, rows, n->nout, g + n->ob3, st))) return e;
+    if ((e = launch_gemm_bf16(n->dO, n->nout, 1, w + n->oW3, 1, n->nout, n->dA2, n->h2, rows, n->h2, n->nout, nullptr, 0, st)))
+        return e;
+    if ((e = launch_relu_bwd(n->Z2, n->dA2, n->dZ2, (int64_t)rows * n->h2, st))) return e;
+    // layer 2
+    if ((e = launch_gemm_bf16(n->A1, 1, n->h1, n->dZ2, n->h2, 1, g + n->oW2, n->h2, n->h1, n->h2, rows, nullptr, 0, st)))
+        return e;
+    if ((e = launch_colsum(n->dZ2, rows, n->h2, g + n->ob2, st))) return e;
+    if ((e = launch_gemm_bf16(n->dZ2, n->h2, 1, w + n->oW2, 1, n->h2, n->dA1, n->h1, rows, n->h1, n->h2, nullptr, 0, st)))
+        return e;
+    if ((e = launch_relu_bwd(n->Z1, n->dA1, n->dZ1, (int64_t)rows * n->h1, st))) return e;
+    // layer 1
+    if ((e = launch_gemm_bf16(X, 1, n->nin, n->dZ1, n->h1, 1, g + n->oW1, n->h1, n->nin, n->h1, rows, nullptr, 0, st)))
+        return e;
+    return launch_colsum(n->dZ1, rows, n->h1, g + n->ob1, st);
+}
+
+extern "C" {
+
+int32_t cdm_mlp_create(int32_t nin, int32_t h1, int32_t h2, int32_t nout, int32_t max_rows, cdm_mlp** out) {
+    if (!out) return CDM_EINVAL;
+    *out = nullptr;
+    if (nin < 1 || h1 < 1 || h2 < 1 || nout < 1 || max_rows < 1) return CDM_ESHAPE;
+    cdm_mlp* n = new cdm_mlp();
+    n->nin = nin;
+    n->h1 = h1;
+    n->h2 = h2;
+    n->nout = nout;
+    n->max_rows = max_rows;
+    n->oW1 = 0;
+    n->ob1 = n->oW1 + (int64_t)nin * h1;
+    n->oW2 = n->ob1 + h1;
+    n->ob2 = n->oW2 + (int64_t)h1 * h2;
+    n->oW3 = n->ob2 + h2;
+    n->ob3 = n->oW3 + (int64_t)h2 * nout;
+    n->nparam = n->ob3 + nout;
+    const int64_t R = max_rows;
+    const int64_t fl = 4 * n->nparam + R * (4 * (int64_t)h1 + 4 * (int64_t)h2 + 2 * nout) + (R * nout + 255) / 256 + 64;
+    if (hipMalloc(&n->ws, sizeof(float) * fl) != hipSuccess) {
+        delete n;
+        return CDM_ENOMEM;
+    }
+    float* p = (float*)n->ws;
+    n->w = p; p += n->nparam;
+    n->g = p; p += n->nparam;
+    n->m1 = p; p += n->nparam;
+    n->m2 = p; p += n->nparam;
+    n->Z1 = p; p += R * h1;
+    n->A1 = p; p += R * h1;
+    n->dA1 = p; p += R * h1;
+    n->dZ1 = p; p += R * h1;
+    n->Z2 = p; p += R * h2;
+    n->A2 = p; p += R * h2;
+    n->dA2 = p; p += R * h2;
+    n->dZ2 = p; p += R * h2;
+    n->O = p; p += R * nout;
+    n->dO = p; p += R * nout;
+    n->part = p;
+    if (hipMemset(n->m1, 0, sizeof(float) * 2 * n->nparam) != hipSuccess) {
+        (void)hipFree(n->ws);
+        delete n;
+        return CDM_EHIP;
+    }
+    *out = n;
+    return CDM_OK;
+}
+
+int64_t cdm_mlp_param_count(const cdm_mlp* n) { return n ? n->nparam : -1; }
+
+int32_t cdm_mlp_set_weights(cdm_mlp* n, const float* host, int64_t count) {
+    if (!n || !host || count != n->nparam) return CDM_EINVAL;
+    MLP_TRY(hipMemcpy(n->w, host, sizeof(float) * count, hipMemcpyHostToDevice));
+    MLP_TRY(hipMemset(n->m1, 0, sizeof(float) * 2 * n->nparam));
+    n->step = 0;
+    return CDM_OK;
+}
+
+int32_t cdm_mlp_get_weights(const cdm_mlp* n, float* host, int64_t count) {
+    if (!n || !host || count != n->nparam) return CDM_EINVAL;
+    MLP_TRY(hipMemcpy(host, n->w, sizeof(float) * count, hipMemcpyDeviceToHost));
+    return CDM_OK;
+}
+
+int32_t cdm_mlp_forward(cdm_mlp* n, const float* X, int32_t rows, float* Y, void* stream) {
+    if (!n || !X || rows < 1 || rows > n->max_rows) return CDM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    MLP_TRY(mlp_forward(n, X, rows, st));
+    if (Y) MLP_TRY(hipMemcpyAsync(Y, n->O, sizeof(float) * (size_t)rows * n->nout, hipMemcpyDeviceToDevice, st));
+    return CDM_OK;
+}
+
+int32_t cdm_mlp_gradients(cdm_mlp* n, const float* X, const float* T, int32_t rows, float* grads, float* loss_parts,
+                          void* stream) {
+    if (!n || !X || !T || rows < 1 || rows > n->max_rows) return CDM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    MLP_TRY(mlp_forward(n, X, rows, st));
+    MLP_TRY(mlp_backward(n, X, T, rows, st));
+    if (grads) MLP_TRY(hipMemcpyAsync(grads, n->g, sizeof(float) * n->nparam, hipMemcpyDeviceToDevice, st));
+    if (loss_parts)
+        MLP_TRY(hipMemcpyAsync(loss_parts, n->part, sizeof(float) * (((size_t)rows * n->nout + 255) / 256),
+                               hipMemcpyDeviceToDevice, st));
+    return CDM_OK;
+}
+
+int32_t cdm_mlp_train_step(cdm_mlp* n, const float* X, const float* T, int32_t rows, float lr, void* stream) {
+    if (!n || !X || !T || rows < 1 || rows > n->max_rows || !(lr > 0.f)) return CDM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    MLP_TRY(mlp_forward(n, X, rows, st));
+    MLP_TRY(mlp_backward(n, X, T, rows, st));
+    n->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)n->step), c2 = 1.f - powf(b2, (float)n->step);
+    MLP_TRY(launch_adam(n->w, n->g, n->m1, n->m2, n->nparam, lr, b1, b2, 1e-8f, c1, c2, st));
+    return CDM_OK;
+}
+
+int32_t cdm_mlp_predict(cdm_mlp* n, const float* X, int64_t rows, void* x0, int32_t precision, void* stream) {
+    if (!n || !X || !x0 || rows < 1 || n->nout != 2) return CDM_EINVAL;
+    if (precision != CDM_C128 && precision != CDM_C64) return CDM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const bool c128 = precision == CDM_C128;
+    const size_t esz = c128 ? 16 : 8;
+    for (int64_t r0 = 0; r0 < rows; r0 += n->max_rows) {
+        const int cnt = (int)std::min<int64_t>(n->max_rows, rows - r0);
+        MLP_TRY(mlp_forward(n, X + r0 * n->nin, cnt, st));
+        MLP_TRY(launch_out_complex(n->O, (char*)x0 + r0 * esz, cnt, c128, st));
+    }
+    return CDM_OK;
+}
+
+int32_t cdm_mlp_destroy(cdm_mlp* n) {
+    if (!n) return CDM_OK;
+    if (n->ws) (void)hipFree(n->ws);
+    delete n;
+    return CDM_OK;
+}
+
+}  // extern "C"

@@ -180,6 +180,10 @@ hipError_t launch_mixed_outer_head(const MixedLaunch& L, hipStream_t st);
 hipError_t launch_mixed_outer_tail(const MixedLaunch& L, hipStream_t st);
 hipError_t launch_mixed_finish(const MixedLaunch& L, hipStream_t st);
 
+// Warm-start MLP and its features.
+hipError_t launch_features(bool c128, const void* H, const void* Y, const WgJob* jobs, const int64_t* row_off,
+                           int njobs, int64_t nrows, double lambda, float* F, hipStream_t st);
+
 // r0 = y (cold) or y - H x0 (warm); x = x0 or 0.
 struct InitLaunch {
     bool c128;

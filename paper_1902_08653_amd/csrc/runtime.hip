@@ -107,6 +107,8 @@ struct cdm_plan {
     void* sp_r = nullptr;
     // batched layout
     std::vector<int64_t> H_off, y_off, x_off;
+    int64_t* xoff_dev = nullptr;
+    int64_t total_n = 0;
     std::string text;
     // stage timing (CDM_F_TIMING)
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -945,6 +947,7 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
         yo += m[i];
         xo += n[i];
     }
+    p->total_n = xo;
     // largest work first (longest-processing-time order), ties by index
     std::vector<int> order(batch);
     std::iota(order.begin(), order.end(), 0);
@@ -955,6 +958,7 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
     const size_t o_ctr = ar.take(64);
     const size_t o_jobs = ar.take(sizeof(WgJob) * batch);
     const size_t o_order = ar.take(sizeof(int) * batch);
+    const size_t o_xoff = ar.take(sizeof(int64_t) * batch);
     st = alloc_ws(p, ar.off);
     if (st) {
         delete p;
@@ -963,6 +967,11 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
     p->ctr = (uint32_t*)(p->ws + o_ctr);
     p->jobs = (WgJob*)(p->ws + o_jobs);
     p->order = (int*)(p->ws + o_order);
+    p->xoff_dev = (int64_t*)(p->ws + o_xoff);
+    if (hipMemcpy(p->xoff_dev, p->x_off.data(), sizeof(int64_t) * batch, hipMemcpyHostToDevice) != hipSuccess) {
+        cdm_destroy(p);
+        return CDM_EHIP;
+    }
 
     // ---- tile choice: threads per workgroup for the whole launch; rows per
     // thread then follow per job.  With CDM_F_AUTOTUNE each candidate is timed
@@ -1086,6 +1095,14 @@ int32_t cdm_solve_batched(cdm_plan* p, const void* H, const void* y, double N0, 
     L.rho_c = 0.0;
     L.resid = (p->d.flags & CDM_F_RESIDUAL) ? 1 : 0;
     HIP_TRY(launch_wg(L, st));
+    return CDM_OK;
+}
+
+int32_t cdm_batched_features(cdm_plan* p, const void* H, const void* y, double N0, double Ex, float* F, void* stream) {
+    if (!p || !p->batched || !H || !y || !F) return CDM_EINVAL;
+    if (!(Ex > 0.0) || !(N0 >= 0.0)) return CDM_EINVAL;
+    const int64_t rows = p->total_n;
+    HIP_TRY(launch_features(p->c128, H, y, p->jobs, p->xoff_dev, p->njobs, rows, N0 / Ex, F, (hipStream_t)stream));
     return CDM_OK;
 }
 
