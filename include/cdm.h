@@ -76,6 +76,10 @@ typedef enum cdm_engine { CDM_ENGINE_AUTO = 0, CDM_ENGINE_WG = 1, CDM_ENGINE_PAN
 #define CDM_F_TIMING   2    /* record HIP events around each kernel stage of a solve (cdm_plan_timings) */
 #define CDM_F_AUTOTUNE 4    /* cdm_create_batched: time the candidate workgroup shapes on a sample of the
                                batch's own shapes (synthetic values) and keep the fastest */
+#define CDM_F_NO_LOOKAHEAD 8 /* panel engine: use the two-hop schedule (partials -> reducers -> all,
+                               per panel) instead of the look-ahead schedule, whose exchange of panel
+                               K+1's partials overlaps the wait for panel K's update (same deltas in
+                               exact arithmetic; kept for comparison) */
 
 typedef struct cdm_desc {
     int32_t problem;     /* cdm_problem */

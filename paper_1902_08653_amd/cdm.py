@@ -24,6 +24,7 @@ ENGINE_AUTO, ENGINE_WG, ENGINE_PANEL = 0, 1, 2
 F_RESIDUAL = 1
 F_TIMING = 2
 F_AUTOTUNE = 4
+F_NO_LOOKAHEAD = 8
 
 INFO_ZERO_COLUMN, INFO_NONFINITE, INFO_NOT_CONVERGED, INFO_TIMEOUT = 1, 2, 4, 8
 
@@ -150,7 +151,8 @@ class Plan:
     """A plan for single solves (``cdm_create`` / ``cdm_solve`` / ``cdm_destroy``)."""
 
     def __init__(self, B, U, C_clusters=1, precision="c128", T_max=200, tol=0.0, engine="auto",
-                 panel=0, residual=False, problem="uplink", layout="dense", nnz=0, timing=False):
+                 panel=0, residual=False, problem="uplink", layout="dense", nnz=0, timing=False,
+                 lookahead=True):
         self.B, self.U, self.C = int(B), int(U), int(C_clusters)
         self.precision = precision
         self.problem = problem
@@ -158,7 +160,8 @@ class Plan:
                  precision=_PREC[precision], layout=DENSE if layout == "dense" else CSR,
                  engine=_ENGINE[engine], B=self.B, U=self.U, C=self.C, T_max=int(T_max),
                  tol=float(tol), nnz=int(nnz), panel=int(panel),
-                 flags=(F_RESIDUAL if residual else 0) | (F_TIMING if timing else 0))
+                 flags=(F_RESIDUAL if residual else 0) | (F_TIMING if timing else 0)
+                 | (0 if lookahead else F_NO_LOOKAHEAD))
         self.desc = d
         h = C.c_void_p()
         _check(lib().cdm_create(C.byref(d), C.byref(h)), "cdm_create")

@@ -62,8 +62,12 @@ template <typename T, int NV> __device__ __forceinline__ void wave_transpose_sum
         const bool upper = (lane & mask) != 0;
 #pragma unroll
         for (int i = 0; i < half; ++i) {
-            T send = upper ? v[i] : v[i + half];
-            T keep = upper ? v[i + half] : v[i];
+            // both values pinned in registers first: a select between two array
+            // elements would otherwise become a dynamically indexed (scratch) load
+            T lo = v[i], hi = v[i + half];
+            asm("" : "+v"(lo), "+v"(hi));
+            const T send = upper ? lo : hi;
+            const T keep = upper ? hi : lo;
             v[i] = keep + __shfl_xor(send, mask, 64);
         }
         mask >>= 1;
@@ -126,7 +130,12 @@ __device__ __forceinline__ float2 ld_dev(const float2* p) {
 
 // Wait until every vector memory operation this wave issued has completed (for
 // the device-coherent stores above: until they have reached the coherence point).
-__device__ __forceinline__ void wave_drain_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Issued through the builtin (vmcnt = 0, expcnt and lgkmcnt left at their maxima) so
+// that the compiler's own wait tracking knows it happened.
+__device__ __forceinline__ void wave_drain_vmem() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 // All threads of the workgroup: after this workgroup's st_dev stores, bump *ctr.
 // Each wave drains its own stores, the barrier orders them before thread 0's
@@ -184,8 +193,20 @@ __device__ __forceinline__ bool wg_wait_flags(const uint32_t* flags, int count, 
         uint64_t t0 = 0;
         bool started = false;
         for (;;) {
+            // all of a lane's flags are loaded before any is tested, so one polling
+            // round costs one memory round trip, not one per flag
             bool mine = true;
-            for (int i = lane; i < count; i += 64) mine = mine && (ld_relaxed(&flags[i]) >= target);
+            for (int base = 0; base < count; base += 256) {
+                uint32_t v[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    // clamped, not guarded: a branch-free load sequence issues back to back
+                    const int i = min(base + lane + 64 * k, count - 1);
+                    v[k] = ld_relaxed(&flags[i]);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) mine &= (v[k] >= target);
+            }
             if (__all(mine)) break;
             if (!started) {
                 t0 = wall_clock64();

@@ -24,59 +24,9 @@
 //      bits everywhere), applies r -= H_K delta_K from the tile still in
 //      registers, and accumulates the stop statistics.
 // H is read from HBM exactly once per sweep.
-#include "common.hpp"
-#include "launch.hpp"
+#include "panel.hpp"
 
 namespace cdm {
-
-constexpr int PANEL_NT = 512;   // 8 waves per workgroup, one workgroup per CU
-
-// Tile sources: where the sweep reads H from.  `idx` is the element index
-// col * ld + row of the column-major B x U matrix, `col` its column.
-template <typename T> struct SrcC {            // interleaved complex (the caller's H)
-    const cv<T>* H;
-    __device__ __forceinline__ cv<T> load(int64_t idx, int) const { return ld_nt(H + idx); }
-};
-struct SrcBF16 {                               // planar BF16 copy
-    const uint16_t* re;
-    const uint16_t* im;
-    __device__ __forceinline__ float2 load(int64_t idx, int) const {
-        return make_float2(__uint_as_float((uint32_t)re[idx] << 16), __uint_as_float((uint32_t)im[idx] << 16));
-    }
-};
-__device__ __forceinline__ float e4m3_to_float(uint32_t c) {
-    const uint32_t e = (c >> 3) & 15u, m = c & 7u;
-    const float v = e ? ldexpf((float)(8u + m), (int)e - 10) : ldexpf((float)m, -9);
-    return (c & 0x80u) ? -v : v;
-}
-struct SrcFP8 {                                // planar FP8-e4m3 copy, one scale per 128 columns
-    const uint8_t* re;
-    const uint8_t* im;
-    const float* scale;
-    __device__ __forceinline__ float2 load(int64_t idx, int col) const {
-        const float s = scale[col >> 7];
-        return make_float2(e4m3_to_float(re[idx]) * s, e4m3_to_float(im[idx]) * s);
-    }
-};
-constexpr int PANEL_NWV = PANEL_NT / 64;
-
-template <typename T, class Src> struct PanelArgs {
-    Src src;
-    int64_t ld;
-    const cv<T>* bias;      // optional: added to every b_u (inner correction solve)
-    const uint32_t* done;   // optional: nonzero -> return at once (finished refinement)
-    const cv<T>* r0;
-    cv<T>* x;
-    const cv<T>* M;
-    cv<T>* part;
-    cv<T>* gbuf;
-    uint32_t* ctr;
-    cdm_info* info;
-    double lambda;
-    double tol;
-    uint64_t timeout_ticks;
-    int B, U, npanels, T_max;
-};
 
 template <typename T, int KP, int RPL, class Src>
 __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T, Src> a) {
@@ -380,6 +330,7 @@ static hipError_t launch_panel_src(const PanelLaunch& L, const Src& src, hipStre
     a.r0 = (const cv<T>*)L.r0;
     a.x = (cv<T>*)L.x;
     a.M = (const cv<T>*)L.M;
+    a.X = nullptr;
     a.part = (cv<T>*)L.part;
     a.gbuf = (cv<T>*)L.gbuf;
     a.ctr = L.ctr;
@@ -448,7 +399,8 @@ int panel_max_coresident(bool c128, int kp, int rpl) {
 // grid.x = npanels * nsub, grid.y = nsplit; 256 threads as a 16 x 16 grid, each
 // accumulating a 4 x 4 complex tile; rows stream through LDS 32 at a time.
 // ============================================================================
-template <typename T, class Src>
+// CROSS: the full block H_K^H H_{K-1 mod npanels} instead (nsub = (kp/64)^2 sub-blocks).
+template <typename T, class Src, bool CROSS = false>
 __global__ __launch_bounds__(256) void k_gram_partial(Src src, int64_t ld, int B, int U, int kp,
                                                       int nsub, int rows_per_split, cv<T>* __restrict__ gpart,
                                                       int npanels) {
@@ -458,13 +410,18 @@ __global__ __launch_bounds__(256) void k_gram_partial(Src src, int64_t ld, int B
     const int tid = threadIdx.x;
     const int K = blockIdx.x / nsub;
     int sb = blockIdx.x % nsub;
-    // sub-block (bi, bj), bi >= bj, enumerated row by row of the lower triangle
-    int bi = 0;
-    while (sb > bi) {
-        sb -= bi + 1;
-        ++bi;
+    int bi = 0, bj = 0;
+    if (CROSS) {
+        bi = sb / (kp / 64);
+        bj = sb % (kp / 64);
+    } else {
+        // sub-block (bi, bj), bi >= bj, enumerated row by row of the lower triangle
+        while (sb > bi) {
+            sb -= bi + 1;
+            ++bi;
+        }
+        bj = sb;
     }
-    const int bj = sb;
     const int split = blockIdx.y;
     const int r_lo = split * rows_per_split;
     const int r_hi = min(B, r_lo + rows_per_split);
@@ -475,7 +432,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(Src src, int64_t ld, int B
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = czero<T>();
     const int colA0 = K * kp + bi * 64;
-    const int colB0 = K * kp + bj * 64;
+    const int colB0 = (CROSS ? (K + npanels - 1) % npanels : K) * kp + bj * 64;
     for (int rb = r_lo; rb < r_hi; rb += 32) {
         // fill: thread -> (row i = tid & 31, column group tid >> 5, + 8 per step)
         const int i = tid & 31;
@@ -627,6 +584,51 @@ hipError_t launch_gram_invert(bool c128, void* gpart, int nsplit, int npanels, i
 
 hipError_t launch_gram(const GramLaunch& L, hipStream_t st) {
     return L.c128 ? launch_gram_t<double>(L, st) : launch_gram_t<float>(L, st);
+}
+
+// X[i] = sum over splits of part[s][i], fixed order
+template <typename V>
+__global__ void k_sum_splits(const V* __restrict__ part, int nsplit, int64_t n, V* __restrict__ X) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    V s = part[i];
+    for (int k = 1; k < nsplit; ++k) {
+        const V p = part[(int64_t)k * n + i];
+        s.x += p.x;
+        s.y += p.y;
+    }
+    X[i] = s;
+}
+
+template <typename T> static hipError_t launch_gram_cross_t(const GramLaunch& L, void* X, hipStream_t st) {
+    const int nb = L.kp / 64;
+    const int nsub = nb * nb;
+    int rps = (L.B + L.nsplit - 1) / L.nsplit;
+    rps = (rps + 31) / 32 * 32;
+    const dim3 grid(L.npanels * nsub, L.nsplit);
+    if (L.src_kind == SRC_BF16) {
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_gram_partial<T, SrcBF16, true>), grid, dim3(256), 0, st, SrcBF16{L.q_re16, L.q_im16},
+                               L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels);
+    } else if (L.src_kind == SRC_FP8) {
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_gram_partial<T, SrcFP8, true>), grid, dim3(256), 0, st,
+                               SrcFP8{L.q_re8, L.q_im8, L.q_scale}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart,
+                               L.npanels);
+    } else {
+        hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>, true>), grid, dim3(256), 0, st, SrcC<T>{(const cv<T>*)L.H},
+                           L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)L.npanels * L.kp * L.kp;
+    hipLaunchKernelGGL(k_sum_splits<cv<T>>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       (const cv<T>*)L.gpart, L.nsplit, n, (cv<T>*)X);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_cross(const GramLaunch& L, void* X, hipStream_t st) {
+    return L.c128 ? launch_gram_cross_t<double>(L, X, st) : launch_gram_cross_t<float>(L, X, st);
 }
 
 }  // namespace cdm

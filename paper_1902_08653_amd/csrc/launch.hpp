@@ -79,9 +79,10 @@ struct PanelLaunch {
     const void* r0;      // initial residual (B)
     void* x;             // in: x^(0) (U), out: x^(T)
     const void* M;       // [npanels][kp*(kp+1)/2] packed lower (D + L)^-1 per panel, column by column
+    const void* X = nullptr;  // look-ahead: [npanels][kp][kp] X_K = H_K^H H_{K-1 mod npanels}, row-major
     void* part;          // [2][kp][P] partial dot products
     void* gbuf;          // [2][kp][2] reduced right-hand sides and old x
-    uint32_t* ctr;       // [0] partial arrivals, [1] reducer arrivals, [2] abort, [3] status word
+    uint32_t* ctr;       // [2] abort, [3] status word, [16..) arrival flags
     cdm_info* info;
     double lambda;
     int T_max;
@@ -90,6 +91,11 @@ struct PanelLaunch {
 };
 hipError_t launch_panel(const PanelLaunch& L, hipStream_t st);
 int panel_max_coresident(bool c128, int kp, int rpl);
+// Look-ahead schedule (one cross-workgroup hop per panel on the critical path):
+// complex128 with kp = 64, complex64 / FP32 inner solves with kp = 128; rpl = 1 and
+// P >= kp; needs PanelLaunch::X.
+hipError_t launch_panel_la(const PanelLaunch& L, hipStream_t st);
+int panel_la_max_coresident(bool c128, int kp);
 
 // Panel Gram blocks and the inverses of the Gauss-Seidel splitting matrices.
 struct GramLaunch {
@@ -111,6 +117,9 @@ struct GramLaunch {
     double lambda;
 };
 hipError_t launch_gram(const GramLaunch& L, hipStream_t st);
+// Cross blocks X_K = H_K^H H_{K-1 mod npanels} (full kp x kp, row-major) into X,
+// using gpart as split scratch (call after launch_gram: its contents are consumed).
+hipError_t launch_gram_cross(const GramLaunch& L, void* X, hipStream_t st);
 
 // (D + L)^-1 from summed Gram blocks already in gpart (row-major, lower part).
 hipError_t launch_gram_invert(bool c128, void* gpart, int nsplit, int npanels, int kp, int U, double lambda, void* M,

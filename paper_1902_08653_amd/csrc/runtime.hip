@@ -64,6 +64,8 @@ struct cdm_plan {
     int njobs = 0;
     // PANEL engine
     int kp = 128, rpl = 1, P = 1, npanels = 1, nsplit = 1;
+    bool la = false;          // look-ahead schedule (k_cd_panel_la)
+    void* X = nullptr;        // its cross blocks H_K^H H_{K-1}
     uint64_t timeout_ticks = 0;
     // workspace
     char* ws = nullptr;
@@ -344,6 +346,7 @@ static int32_t solve_mixed(cdm_plan* p, const void* H, int64_t ldh, const void* 
     G.status = p->ctr + 3;
     G.lambda = lambda;
     HIP_TRY(launch_gram(G, st));
+    if (p->la) HIP_TRY(launch_gram_cross(G, p->X, st));
     HIP_TRY(launch_mixed_start(M, st));
     ev_record(p, 1, st);
     ev_record(p, 2, st);
@@ -368,6 +371,7 @@ static int32_t solve_mixed(cdm_plan* p, const void* H, int64_t ldh, const void* 
     L.r0 = p->mx_r32;
     L.x = p->mx_d32;
     L.M = p->M;
+    L.X = p->X;
     L.part = p->part;
     L.gbuf = p->gbuf;
     L.ctr = p->ctr;
@@ -378,7 +382,7 @@ static int32_t solve_mixed(cdm_plan* p, const void* H, int64_t ldh, const void* 
     L.info = (cdm_info*)((char*)p->mx_done + 32);   // the inner launches' own record (unused)
     for (int k = 0; k < d.T_max; ++k) {
         HIP_TRY(launch_mixed_outer_head(M, st));
-        HIP_TRY(launch_panel(L, st));
+        HIP_TRY(p->la ? launch_panel_la(L, st) : launch_panel(L, st));
         HIP_TRY(launch_mixed_outer_tail(M, st));
     }
     HIP_TRY(launch_mixed_finish(M, st));
@@ -464,7 +468,7 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
     Arena ar;
     const size_t o_ctr = ar.take(kCtrWords * 4);
     size_t o_jobs = 0, o_r0 = 0, o_M = 0, o_gpart = 0, o_part = 0, o_gbuf = 0, o_e = 0, o_xloc = 0,
-           o_msum = 0, o_rpart = 0;
+           o_msum = 0, o_rpart = 0, o_X = 0;
     p->nchunk = std::max(1, std::min(64, (d.U + 127) / 128));
     if (engine == CDM_ENGINE_WG) {
         st = setup_wg(p, Bc, d.U, d.C, wg_nt_single(Bc, p->c128));
@@ -484,6 +488,19 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         static const int cand_c64[2][2] = {{128, 1}, {128, 2}};
         const int(*cand)[2] = p->c128 ? cand_c128 : cand_c64;
         bool found = false;
+        if (!(d.flags & CDM_F_NO_LOOKAHEAD)) {
+            // look-ahead schedule: 64-row blocks, one reducer workgroup per panel column
+            const int kp = p->c128 ? 64 : 128;
+            const int P = (d.B + 63) / 64;
+            if ((!d.panel || d.panel == kp) && P >= kp && P <= panel_la_max_coresident(p->c128, kp) &&
+                16 + P + kp <= kCtrWords) {
+                p->kp = kp;
+                p->rpl = 1;
+                p->P = P;
+                p->la = true;
+                found = true;
+            }
+        }
         for (int i = 0; i < 2 && !found; ++i) {
             const int kp = cand[i][0], rpl = cand[i][1];
             if (d.panel && d.panel != kp) continue;
@@ -513,6 +530,7 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         o_gbuf = ar.take(p->esz * 2 * (size_t)p->kp * 2);
         o_e = ar.take(sizeof(double) * d.U);
         o_rpart = ar.take(16 * (size_t)p->nchunk * d.B);
+        if (p->la) o_X = ar.take(p->esz * kk);
     }
     size_t o_q1 = 0, o_q2 = 0, o_qs = 0, o_ca = 0, o_r64 = 0, o_g32 = 0, o_d32 = 0, o_r32 = 0, o_done = 0;
     if (mixed) {
@@ -573,6 +591,7 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         p->gbuf = b + o_gbuf;
         p->e = (double*)(b + o_e);
         p->rpart = b + o_rpart;
+        if (p->la) p->X = b + o_X;
     }
     if (mixed) {
         if (p->src_kind == SRC_BF16) {
@@ -603,8 +622,10 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
                  p->c128 ? "c128" : "c64", d.B, d.U, d.C, p->wg_nt, p->wg_rpt, p->wg_grid, p->wg_lds, p->ws_bytes);
     else
         snprintf(buf, sizeof(buf),
-                 "{\"engine\": \"panel\", \"precision\": \"%s\", \"B\": %d, \"U\": %d, \"panel\": %d, \"rpl\": %d, "
-                 "\"workgroups\": %d, \"npanels\": %d, \"gram_splits\": %d, \"workspace\": %zu}",
+                 "{\"engine\": \"panel\", \"schedule\": \"%s\", \"precision\": \"%s\", \"B\": %d, \"U\": %d, "
+                 "\"panel\": %d, \"rpl\": %d, \"workgroups\": %d, \"npanels\": %d, \"gram_splits\": %d, "
+                 "\"workspace\": %zu}",
+                 p->la ? "lookahead" : "two-hop",
                  mixed ? (p->src_kind == SRC_BF16 ? "mixed-bf16" : "mixed-fp8") : (p->c128 ? "c128" : "c64"), d.B, d.U,
                  p->kp, p->rpl, p->P, p->npanels, p->nsplit, p->ws_bytes);
     p->text = buf;
@@ -742,6 +763,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         G.status = p->ctr + 3;
         G.lambda = lambda;
         HIP_TRY(launch_gram(G, st));
+        if (p->la) HIP_TRY(launch_gram_cross(G, p->X, st));
         ev_record(p, 1, st);
         InitLaunch I;
         I.c128 = p->c128;
@@ -770,6 +792,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         L.r0 = p->r0;
         L.x = x;
         L.M = p->M;
+        L.X = p->X;
         L.part = p->part;
         L.gbuf = p->gbuf;
         L.ctr = p->ctr;
@@ -778,7 +801,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         L.T_max = d.T_max;
         L.tol = d.tol;
         L.timeout_ticks = p->timeout_ticks;
-        HIP_TRY(launch_panel(L, st));
+        HIP_TRY(p->la ? launch_panel_la(L, st) : launch_panel(L, st));
         ev_record(p, 3, st);
         HIP_TRY(launch_finalize(x, d.U, p->c128, p->ctr + 2, inf, st));
     }

