@@ -117,6 +117,9 @@ def main():
 
     esz = 16 if prec == "c128" else 8
     h_bytes = float(a.B) * a.U * esz
+    desc = json.loads(plan.describe())
+    sweep_kernel = "k_cd_panel_la" if desc.get("schedule") == "lookahead" else (
+        "k_cd_panel" if desc.get("engine") == "panel" else "k_cd_wg")
     sweep_ms = stage["sweeps"] / a.steps
     mean_sweeps = float(np.mean(sweeps))
     achieved = mean_sweeps * h_bytes / (sweep_ms * 1e-3) / 1e9
@@ -180,7 +183,7 @@ def main():
                    "engine": json.loads(plan.describe())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_cd_panel", "algorithmic_bytes_per_launch": mean_sweeps * h_bytes,
+                     "kernel": sweep_kernel, "algorithmic_bytes_per_launch": mean_sweeps * h_bytes,
                      "avg_launch_ms": sweep_ms},
         "cpu_baseline": cpu,
         "accuracy": {"sweeps": sweeps, "rel_step": float(rec["rel_step"]), "flags": int(rec["flags"]),

@@ -2,22 +2,28 @@
 //
 // Same block form of the cyclic sweep as k_cd_panel (delta_K = M_K b_K with
 // M_K = (D + L)^-1 of the panel Gram, b_K = H_K^H r - lambda x_K), but the partial
-// products of panel K+1 are formed from the residual *before* panel K's update and
-// corrected afterwards:
+// products of a panel are formed from the residual *before* the previous panel's
+// update and corrected afterwards:
 //     H_{K+1}^H (r - H_K delta_K) = H_{K+1}^H r - X_{K+1} delta_K,
 //     X_{K+1} = H_{K+1}^H H_K  (formed once per solve, next to M).
-// The exchange of panel K+1's partials therefore overlaps the wait for panel K's
-// reduced b, and only one cross-workgroup hop per panel sits on the critical path.
-// In exact arithmetic every delta is the same as in the sequential sweep.
+// The exchange of panel K+1's partials thereby overlaps the wait for panel K's
+// reduced b.  In exact arithmetic every delta equals the sequential sweep's.
 //
-// Workgroup: 8 tile waves and one control wave.  Tile waves own the rows (lane =
-// row) and NC panel columns each; they keep three panels in registers (K for the
-// update, K+1 for the look-ahead partial, K+2 in flight) and touch global memory
-// only to stream H.  The control wave does every cross-workgroup exchange (partials
-// out, flags, reducer sums, the reduced b in, the panel inverse into LDS).  Memory
-// operations complete in issue order per wave, so a flag poll issued by a tile wave
-// would wait for that wave's tile stream; keeping the two in different waves keeps
-// the stream off the critical path.
+// Workgroup: 8 tile waves and one control wave, decoupled.
+//  * Tile waves own the rows (lane = row) and NC panel columns each.  They keep
+//    three panels in registers (K for the update, K+1 already reduced, K+2 for the
+//    next look-ahead partials) and stream a fourth behind them; they touch global
+//    memory only to stream H.  Per step: wait for b_K in LDS, delta_K = M_K b_K,
+//    r -= H_K delta_K, prefetch panel K+3, partials of panel K+2 from the new r.
+//  * The control wave does every cross-workgroup exchange: it publishes the tile
+//    waves' partials, gathers b_K into LDS (with M_K, staged by LDS-direct loads),
+//    keeps the stop statistics, and in the reducer workgroups (w < KP; reducer w
+//    owns panel column j = w) sums the P partials of its column and publishes b.
+//  * The two sides meet only through LDS words (sequence counters), never at a
+//    workgroup barrier, so a reducer's wait for partials does not hold back its own
+//    tile waves.  The tile waves synchronise among themselves with an LDS arrival
+//    counter.  Memory operations complete in issue order per wave, so keeping flag
+//    polls out of the tile waves also keeps the tile stream off the critical path.
 #include "panel.hpp"
 
 namespace cdm {
@@ -25,6 +31,7 @@ namespace cdm {
 constexpr int LA_NWT = 8;                 // tile waves
 constexpr int LA_NT = 64 * (LA_NWT + 1);  // + one control wave
 
+// ---- cross-workgroup flags (control wave only) ------------------------------------
 // One wave: wait until flags[0..count) are all >= target.  Same time-out and abort
 // protocol as wg_wait_flags, without a workgroup barrier.  Uniform result.
 __device__ __forceinline__ bool wave_wait_flags(const uint32_t* flags, int count, uint32_t target,
@@ -61,6 +68,28 @@ __device__ __forceinline__ void wave_publish(uint32_t* flags, int w, uint32_t va
     if ((threadIdx.x & 63) == 0) st_relaxed(&flags[w], value);
 }
 
+// ---- intra-workgroup LDS words ------------------------------------------------------
+// A writer completes its LDS data writes (lgkmcnt = 0) before it bumps a word; LDS
+// operations of one wave are performed in order, so a reader that sees the word
+// (and reads after it) sees the data.
+__device__ __forceinline__ void lds_wait_writes() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt = 0; vmcnt and expcnt left at their maxima
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+__device__ __forceinline__ int lds_get(const int* p) {
+    const int v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return v;
+}
+__device__ __forceinline__ void lds_set(int* p, int v) {
+    lds_wait_writes();
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(int* p, int v) {
+    lds_wait_writes();
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 template <typename T, int KP, int RPL, class Src>
 __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
     using V = cv<T>;
@@ -75,102 +104,244 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
     const int wid = tid >> 6;
     const bool ctl = wid == LA_NWT;
     const int w = blockIdx.x;
-    const int P = gridDim.x;                    // the planner guarantees P >= KP
-    const bool reducer = w < KP;                // reducer w owns panel column j = w
+    const int P = gridDim.x;                    // the planner keeps KP <= P <= 256
+    const bool reducer = w < KP;
     const int B = a.B, U = a.U, np = a.npanels;
     const T lambda = (T)a.lambda;
     if (a.done && *a.done) return;              // uniform for the whole grid
 
-    // packed M_K, staged by the control wave with LDS-direct loads in 1 KiB rows (the
-    // array is padded to whole rows; M's buffer extends past its last panel)
+    // packed M_K (two buffers, by step parity), staged by the control wave with
+    // LDS-direct loads in 1 KiB rows (padded to whole rows; M's buffer extends past
+    // its last panel)
     constexpr int MS_BYTES = (NE * (int)sizeof(V) + 1023) / 1024 * 1024;
-    __shared__ __attribute__((aligned(16))) V Ms[MS_BYTES / sizeof(V)];
-    __shared__ V psh[KP];                       // this workgroup's look-ahead partials
-    __shared__ V bsh[KP];
-    __shared__ V xsh[KP];
-    __shared__ V dsh[KP];
-    constexpr int SCR = (NS * KP > LA_NWT * RPL * 64) ? NS * KP : LA_NWT * RPL * 64;
-    __shared__ V scr[SCR];
-    V(*dpart)[KP] = reinterpret_cast<V(*)[KP]>(scr);
-    V(*axs)[RPL][64] = reinterpret_cast<V(*)[RPL][64]>(scr);
-    __shared__ int ctl_s;                       // 0 run, 1 stop after this sweep, 2 abandoned
+    constexpr int MS_N = MS_BYTES / (int)sizeof(V);
+    __shared__ __attribute__((aligned(16))) V Ms[2][MS_N];
+    __shared__ V psh[2][KP];                    // look-ahead partials, by panel-sequence parity
+    __shared__ V bsh[2][KP];                    // b of the step's panel, by step parity
+    __shared__ V xsh[2][KP];                    // x of the step's panel before its update
+    __shared__ V dsh[2][KP];                    // delta of the step's panel
+    __shared__ V dpart[NS][KP];
+    __shared__ V axs[LA_NWT][RPL][64];
+    // LDS words: b_ready = (last step whose b, x and M are in LDS) + 1; d_ready = (last
+    // step whose delta is in dsh) + 1; p_done[k] = partial panels written by tile wave
+    // k (per wave: a shared count could not tell a fast wave's second panel from a
+    // slow wave's first); stop_w: 1 stopped (converged or T_max), 2 abandoned; t_bar:
+    // tile-wave arrival counter
+    __shared__ int b_ready, d_ready, stop_w, t_bar;
+    __shared__ int p_done[LA_NWT];
+    if (tid == 0) {
+        b_ready = 0;
+        d_ready = 0;
+        stop_w = 0;
+        t_bar = 0;
+    }
+    if (tid < LA_NWT) p_done[tid] = 0;
+    __syncthreads();   // the only workgroup barrier
 
-    // ctr layout: [2] abort, [3] status, [16, 16+P) partial flags, [16+P, 16+P+KP)
-    // reducer flags; a flag holds (panel sequence number of the published data) + 1
     uint32_t* abort_flag = a.ctr + 2;
-    uint32_t* flagsA = a.ctr + 16;
-    uint32_t* flagsB = a.ctr + 16 + P;
-
+    uint32_t* flagsA = a.ctr + 16;              // partials of panel sequence s published: s + 1
+    uint32_t* flagsB = a.ctr + 16 + P;          // b of panel sequence s published: s + 1
     const int row0 = w * 64 * RPL;
-    V r[RPL];
-    using Raw = typename Src::Raw;
-    Raw t0[NC][RPL], t1[NC][RPL], t2[NC][RPL];
+    const uint64_t tmo = a.timeout_ticks;
+
     if (!ctl) {
+        // ===================================== tile waves =====================================
+        if (a.T_max < 1) return;
+        using Raw = typename Src::Raw;
+        V r[RPL];
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
             const int row = row0 + lane + 64 * q;
             r[q] = row < B ? a.r0[row] : czero<T>();
         }
-    }
-
-    // ---- tile waves ---------------------------------------------------------------
-    // the wave index is uniform across the wave: keep column arithmetic scalar
-    const int wu = __builtin_amdgcn_readfirstlane(wid);
-    // Loads are unconditional (a branch around a load would make the wave wait for it
-    // at the join): columns past U and rows past B read a clamped in-range element
-    // instead.  Such columns are inactive (their M rows and columns and their X rows
-    // are zero, so their delta is zero), and rows past B keep r = 0.
-    auto load_tile = [&](Raw(&dst)[NC][RPL], int K) {
-        const int col0 = K * KP + wu;
+        // the wave index is uniform across the wave: keep column arithmetic scalar
+        const int wu = __builtin_amdgcn_readfirstlane(wid);
+        // Loads are unconditional (a branch around a load would make the wave wait for
+        // it at the join): columns past U and rows past B read a clamped in-range
+        // element.  Such columns are inactive (their M rows and columns and their X rows
+        // are zero, so their delta is zero), and rows past B keep r = 0.
+        auto load_tile = [&](Raw(&dst)[NC][RPL], int K) {
+            const int col0 = K * KP + wu;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const int col = min(col0 + LA_NWT * c, U - 1);
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                const uint32_t row = (uint32_t)min(row0 + lane + 64 * q, B - 1);
-                dst[c][q] = a.src.load_raw(col, row, a.ld);
-            }
-        }
-    };
-    // partial products of one panel over this workgroup's rows, into psh
-    auto tile_col = [&](int K, int c) { return min(K * KP + wu + LA_NWT * c, U - 1); };
-    auto partial_to_lds = [&](const Raw(&t)[NC][RPL], int K) {
-        constexpr int NH = (NC >= 2) ? NC / 2 : 1;
-        constexpr int LOG_NH = (NH == 1) ? 0 : (NH == 2) ? 1 : (NH == 4) ? 2 : (NH == 8) ? 3 : (NH == 16) ? 4 : 5;
-        constexpr int HSHIFT = 6 - LOG_NH;
-#pragma unroll
-        for (int h0 = 0; h0 < NC; h0 += NH) {
-            T pr[NH], pi[NH];
-#pragma unroll
-            for (int c = 0; c < NH; ++c) {
-                pr[c] = T(0);
-                pi[c] = T(0);
+            for (int c = 0; c < NC; ++c) {
+                const int col = min(col0 + LA_NWT * c, U - 1);
 #pragma unroll
                 for (int q = 0; q < RPL; ++q) {
-                    const V h = a.src.decode(t[h0 + c][q], tile_col(K, h0 + c));
-                    pr[c] += h.x * r[q].x + h.y * r[q].y;
-                    pi[c] += h.x * r[q].y - h.y * r[q].x;
+                    const uint32_t row = (uint32_t)min(row0 + lane + 64 * q, B - 1);
+                    dst[c][q] = a.src.load_raw(col, row, a.ld);
                 }
             }
-            wave_transpose_sum<T, NH>(pr, lane);
-            wave_transpose_sum<T, NH>(pi, lane);
-            if ((lane & ((1 << HSHIFT) - 1)) == 0) psh[wid + LA_NWT * (h0 + (lane >> HSHIFT))] = cmake<T>(pr[0], pi[0]);
+        };
+        auto tile_col = [&](int K, int c) { return min(K * KP + wu + LA_NWT * c, U - 1); };
+        // partial products of one panel over this workgroup's rows, into psh[s & 1]
+        auto partial = [&](const Raw(&t)[NC][RPL], int K, int s) {
+            constexpr int NH = (NC >= 2) ? NC / 2 : 1;
+            constexpr int LOG_NH = (NH == 1) ? 0 : (NH == 2) ? 1 : (NH == 4) ? 2 : (NH == 8) ? 3 : (NH == 16) ? 4 : 5;
+            constexpr int HSHIFT = 6 - LOG_NH;
+#pragma unroll
+            for (int h0 = 0; h0 < NC; h0 += NH) {
+                T pr[NH], pi[NH];
+#pragma unroll
+                for (int c = 0; c < NH; ++c) {
+                    pr[c] = T(0);
+                    pi[c] = T(0);
+#pragma unroll
+                    for (int q = 0; q < RPL; ++q) {
+                        const V h = a.src.decode(t[h0 + c][q], tile_col(K, h0 + c));
+                        pr[c] += h.x * r[q].x + h.y * r[q].y;
+                        pi[c] += h.x * r[q].y - h.y * r[q].x;
+                    }
+                }
+                wave_transpose_sum<T, NH>(pr, lane);
+                wave_transpose_sum<T, NH>(pi, lane);
+                if ((lane & ((1 << HSHIFT) - 1)) == 0)
+                    psh[s & 1][wu + LA_NWT * (h0 + (lane >> HSHIFT))] = cmake<T>(pr[0], pi[0]);
+            }
+            if (lane == 0) lds_set(&p_done[wu], s + 1);
+        };
+        // waits of the tile waves read LDS and the wall clock only (each bounded by the
+        // same time-out as the cross-workgroup waits); `bad` ends the loop
+        bool bad = false;
+        int nbar = 0;
+        auto tbar = [&]() {   // the 8 tile waves
+            nbar += LA_NWT;
+            if (lane == 0) lds_add(&t_bar, 1);
+            const uint64_t t0 = wall_clock64();
+            while (__builtin_amdgcn_readfirstlane(lds_get(&t_bar)) < nbar) {
+                if (__builtin_amdgcn_readfirstlane(lds_get(&stop_w)) == 2 || wall_clock64() - t0 > tmo) {
+                    bad = true;
+                    return;
+                }
+            }
+        };
+        // wait until b of step q is in LDS; false: stop (converged, T_max or abandoned)
+        auto wait_b = [&](int q) -> bool {
+            const uint64_t t0 = wall_clock64();
+            for (;;) {
+                if (__builtin_amdgcn_readfirstlane(lds_get(&b_ready)) > q) return true;
+                if (__builtin_amdgcn_readfirstlane(lds_get(&stop_w)) != 0) return false;
+                if (wall_clock64() - t0 > 2 * tmo) return false;
+                __builtin_amdgcn_s_sleep(1);
+            }
+        };
+
+        Raw t0[NC][RPL], t1[NC][RPL], t2[NC][RPL];
+        // prologue: panels 0, 1, 2 in flight, set by set; partials of panels 0 and 1 from r0
+        load_tile(t0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        load_tile(t1, np > 1 ? 1 : 0);
+        __builtin_amdgcn_sched_barrier(0);
+        load_tile(t2, 2 % np);
+        __builtin_amdgcn_sched_barrier(0);
+        partial(t0, 0, 0);
+        partial(t1, np > 1 ? 1 : 0, 1);
+
+        int K = 0;
+        int q = 0;
+        // One step: cur = panel K, nn = panel K+2 (its partials come at the end of this
+        // step; the third set holds panel K+1).  A macro: its exits leave the loop directly.
+#define CDM_LA_TSTEP(cur, nn)                                                                         \
+    {                                                                                                 \
+        if (!wait_b(q)) goto tdone;                                                                   \
+        {   /* delta = M_K b; column v of the packed M holds rows v..KP-1 at offset v*KP - v(v-1)/2 */ \
+            constexpr int SV = KP / NS;                                                               \
+            const V* Mq = Ms[q & 1];                                                                  \
+            const V* bq = bsh[q & 1];                                                                 \
+            const int j = tid % KP, sl = tid / KP, v0 = sl * SV, v1 = min(v0 + SV - 1, j);            \
+            V d0 = czero<T>(), d1 = czero<T>();                                                       \
+            int off = v0 * KP - (v0 * (v0 - 1)) / 2 + (j - v0);                                       \
+            int v = v0;                                                                               \
+            for (; v + 1 <= v1; v += 2) {                                                             \
+                cfma(d0, Mq[off], bq[v]);                                                             \
+                off += KP - v - 1;                                                                    \
+                cfma(d1, Mq[off], bq[v + 1]);                                                         \
+                off += KP - v - 2;                                                                    \
+            }                                                                                         \
+            if (v <= v1) cfma(d0, Mq[off], bq[v]);                                                    \
+            dpart[sl][j] = cmake<T>(d0.x + d1.x, d0.y + d1.y);                                        \
+        }                                                                                             \
+        tbar();                                                                                       \
+        if (bad) goto tdone;                                                                          \
+        if (tid < KP) {                                                                               \
+            V s_ = dpart[0][tid];                                                                     \
+            for (int k = 1; k < NS; ++k) {                                                            \
+                s_.x += dpart[k][tid].x;                                                              \
+                s_.y += dpart[k][tid].y;                                                              \
+            }                                                                                         \
+            dsh[q & 1][tid] = s_;                                                                     \
+        }                                                                                             \
+        tbar();                                                                                       \
+        if (bad) goto tdone;                                                                          \
+        if (tid == 0) lds_set(&d_ready, q + 1);                                                       \
+        for (int qq = 0; qq < RPL; ++qq) {                                                            \
+            V acc = czero<T>();                                                                       \
+            for (int c = 0; c < NC; ++c)                                                              \
+                cfma(acc, a.src.decode(cur[c][qq], tile_col(K, c)), dsh[q & 1][wu + LA_NWT * c]);     \
+            axs[wu][qq][lane] = acc;                                                                  \
+        }                                                                                             \
+        tbar();                                                                                       \
+        if (bad) goto tdone;                                                                          \
+        for (int qq = 0; qq < RPL; ++qq) {                                                            \
+            V s_ = czero<T>();                                                                        \
+            for (int v = 0; v < LA_NWT; ++v) {                                                        \
+                s_.x += axs[v][qq][lane].x;                                                           \
+                s_.y += axs[v][qq][lane].y;                                                           \
+            }                                                                                         \
+            if (row0 + lane + 64 * qq < B) {                                                          \
+                r[qq].x -= s_.x;                                                                      \
+                r[qq].y -= s_.y;                                                                      \
+            }                                                                                         \
+        }                                                                                             \
+        load_tile(cur, (K + 3) % np); /* cur is free: stream panel K+3 into it */                    \
+        partial(nn, (K + 2) % np, q + 2); /* look-ahead partials of panel K+2 from r after K */      \
+        K = (K + 1 < np) ? K + 1 : 0;                                                                 \
+        ++q;                                                                                          \
+    }
+        for (;;) {
+            CDM_LA_TSTEP(t0, t2)
+            CDM_LA_TSTEP(t1, t0)
+            CDM_LA_TSTEP(t2, t1)
+        }
+#undef CDM_LA_TSTEP
+    tdone:
+        return;
+    }
+
+    // ==================================== control wave ====================================
+    uint32_t ok = 1;
+    int sweeps = 0;
+    double S = 0.0, Xn = 0.0, rel_last = 0.0;
+    // wait until every tile wave has written its columns of the first `n` partial panels
+    auto wait_parts = [&](int n) -> bool {
+        const uint64_t t0 = wall_clock64();
+        for (;;) {
+            const int v = lds_get(&p_done[lane & (LA_NWT - 1)]);
+            if (__all(v >= n)) return true;
+            if (wall_clock64() - t0 > tmo) return false;
+            __builtin_amdgcn_s_sleep(1);
         }
     };
-
-    // ---- control wave -------------------------------------------------------------
-    auto publish_partials = [&](int slot, uint32_t val) {
+    auto wait_delta = [&](int q) -> bool {
+        const uint64_t t0 = wall_clock64();
+        while (__builtin_amdgcn_readfirstlane(lds_get(&d_ready)) <= q) {
+            if (wall_clock64() - t0 > tmo) return false;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        return true;
+    };
+    // publish the partials of panel sequence s (psh[s & 1]) to part[s & 1]
+    auto publish_partials = [&](int s) {
 #pragma unroll
         for (int i = 0; i < KL; ++i) {
             const int j = lane + 64 * i;
-            if (j < KP) st_dev(&a.part[((int64_t)slot * KP + j) * P + w], psh[j]);
+            if (j < KP) st_dev(&a.part[((int64_t)(s & 1) * KP + j) * P + w], psh[s & 1][j]);
         }
-        wave_publish(flagsA, w, val);
+        wave_publish(flagsA, w, (uint32_t)s + 1);
     };
     // reducer: sum over the P workgroups of column j = w (fixed order per lane, then a
     // fixed butterfly), uniform result
-    auto presum = [&](int slot) -> V {
-        const V* src = a.part + ((int64_t)slot * KP + w) * P;
+    auto presum = [&](int s) -> V {
+        const V* src = a.part + ((int64_t)(s & 1) * KP + w) * P;
         V acc = czero<T>();
         for (int base = 0; base < P; base += 256) {
             V v[4];
@@ -186,8 +357,8 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
         acc.y = wave_allsum(acc.y);
         return acc;
     };
-    // reducer: publish b_j = g_j - lambda x_j (+ bias) of panel K for its column
-    auto publish_b = [&](int K, int slot, V g, uint32_t val) {
+    // reducer: publish b_j = g_j - lambda x_j (+ bias) of panel K (sequence s)
+    auto publish_b = [&](int K, int s, V g) {
         if (lane == 0) {
             const int u = K * KP + w;
             const V xo = (u < U) ? a.x[u] : czero<T>();
@@ -199,254 +370,126 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
             V b;
             b.x = g.x - lambda * xo.x;
             b.y = g.y - lambda * xo.y;
-            st_dev(&a.gbuf[((int64_t)slot * KP + w) * 2 + 0], b);
-            st_dev(&a.gbuf[((int64_t)slot * KP + w) * 2 + 1], xo);
+            st_dev(&a.gbuf[((int64_t)(s & 1) * KP + w) * 2 + 0], b);
+            st_dev(&a.gbuf[((int64_t)(s & 1) * KP + w) * 2 + 1], xo);
         }
-        wave_publish(flagsB, w, val);
+        wave_publish(flagsB, w, (uint32_t)s + 1);
     };
-    auto stage_M = [&](int K) {
+    auto stage_M = [&](int K, int buf) {
         // global -> LDS without passing through registers: lane l of each load moves
         // bytes [16 l, 16 l + 16) of a 1 KiB row
         const char* src = reinterpret_cast<const char*>(a.M + (int64_t)K * NE) + lane * 16;
-        char* dst = reinterpret_cast<char*>(Ms);
+        char* dst = reinterpret_cast<char*>(Ms[buf]);
 #pragma unroll 4
         for (int off = 0; off < MS_BYTES; off += 1024)
             __builtin_amdgcn_global_load_lds(src + off, (__attribute__((address_space(3))) void*)(dst + off), 16, 0, 0);
     };
 
-    // The tile waves and the control wave run separate loops that meet at the same
-    // sequence of workgroup barriers (six per panel step: A partials ready, B reduced
-    // b in LDS, C matvec partials, C' delta ready, D update and decisions, E end of
-    // step).  Separate loops keep each wave class's memory-wait bookkeeping apart.
-    // tile-wave pieces of a panel step
-    auto tile_matvec = [&]() {
-        // delta = M_K b; column v of the packed M holds rows v..KP-1 at offset
-        // v*KP - v(v-1)/2; NS threads per row j over contiguous slices of v
-        constexpr int SV = KP / NS;
-        const int j = tid % KP;
-        const int sl = tid / KP;
-        const int v0 = sl * SV;
-        const int v1 = min(v0 + SV - 1, j);
-        V d0 = czero<T>(), d1 = czero<T>();
-        int off = v0 * KP - (v0 * (v0 - 1)) / 2 + (j - v0);
-        int v = v0;
-        for (; v + 1 <= v1; v += 2) {
-            cfma(d0, Ms[off], bsh[v]);
-            off += KP - v - 1;
-            cfma(d1, Ms[off], bsh[v + 1]);
-            off += KP - v - 2;
-        }
-        if (v <= v1) cfma(d0, Ms[off], bsh[v]);
-        V d;
-        d.x = d0.x + d1.x;
-        d.y = d0.y + d1.y;
-        dpart[sl][j] = d;
-    };
-    auto tile_dsum = [&]() {
-        if (tid < KP) {
-            V s = dpart[0][tid];
-#pragma unroll
-            for (int k = 1; k < NS; ++k) {
-                s.x += dpart[k][tid].x;
-                s.y += dpart[k][tid].y;
-            }
-            dsh[tid] = s;
-        }
-    };
-    auto tile_axs = [&](const Raw(&cur)[NC][RPL], int K) {
-#pragma unroll
-        for (int qq = 0; qq < RPL; ++qq) {
-            V acc = czero<T>();
-#pragma unroll
-            for (int c = 0; c < NC; ++c) cfma(acc, a.src.decode(cur[c][qq], tile_col(K, c)), dsh[wid + LA_NWT * c]);
-            axs[wid][qq][lane] = acc;
-        }
-    };
-    auto tile_update = [&]() {
-#pragma unroll
-        for (int qq = 0; qq < RPL; ++qq) {
-            V s = czero<T>();
-#pragma unroll
-            for (int v = 0; v < LA_NWT; ++v) {
-                s.x += axs[v][qq][lane].x;
-                s.y += axs[v][qq][lane].y;
-            }
-            if (row0 + lane + 64 * qq < B) {
-                r[qq].x -= s.x;
-                r[qq].y -= s.y;
-            }
-        }
-    };
-
-    if (!ctl) {
-        // ================================ tile waves ================================
-        if (a.T_max >= 1) {
-            // issued set by set (no interleaving by the scheduler): the wait before the
-            // first step's partial then only has to cover the second set
-            load_tile(t0, 0);
-            __builtin_amdgcn_sched_barrier(0);
-            load_tile(t1, np > 1 ? 1 : 0);
-            __builtin_amdgcn_sched_barrier(0);
-            load_tile(t2, 2 % np);
-            __builtin_amdgcn_sched_barrier(0);
-            partial_to_lds(t0, 0);    // panel 0's partials from r0
-        }
-        __syncthreads();              // prologue A
-        __syncthreads();              // prologue end (ctl_s = outcome)
-        if (a.T_max < 1 || __builtin_amdgcn_readfirstlane(ctl_s) != 0) return;
-        int K = 0;
-        // One panel step with cur = panel K and nx = panel K+1 (the third register set
-        // holds panel K+2, in flight).  A macro, not a function: the exits jump straight
-        // out of the loop, so no control-flow join mixes a path without the step's
-        // prefetch into the wait bookkeeping of the next step.
-#define CDM_LA_TSTEP(cur, nx)                                                                        \
-    {                                                                                                \
-        const int K1 = (K + 1 < np) ? K + 1 : 0;                                                    \
-        partial_to_lds(nx, K1); /* look-ahead partials of panel K+1, from r before K's update */    \
-        __syncthreads();        /* A */                                                             \
-        __syncthreads();        /* B */                                                             \
-        tile_matvec();                                                                               \
-        __syncthreads();        /* C */                                                             \
-        tile_dsum();                                                                                 \
-        __syncthreads();        /* C' */                                                            \
-        tile_axs(cur, K);                                                                            \
-        __syncthreads();        /* D */                                                             \
-        tile_update();                                                                               \
-        K = K1;                                                                                      \
-        load_tile(cur, (K + 2) % np); /* cur is free: stream the new panel K+2 into it */           \
-        __syncthreads();        /* E (axs and dpart share scratch) */                               \
-    }
-        // Steps run in groups of three (one per register-set rotation) and the loop has
-        // a single exit at the end of a group: once the control wave has decided to stop
-        // (converged, T_max, or abandoned), the remaining steps of the group are idle
-        // steps (same barriers, nothing published), so every path into a step has
-        // issued the same prefetches.
-        for (;;) {
-            CDM_LA_TSTEP(t0, t1)
-            CDM_LA_TSTEP(t1, t2)
-            CDM_LA_TSTEP(t2, t0)
-            if (__builtin_amdgcn_readfirstlane(ctl_s) != 0) break;
-        }
-#undef CDM_LA_TSTEP
-        return;
-    }
-
-    // ================================ control wave ================================
-    uint32_t ok = 1;
-    int sweeps = 0;
-    double S = 0.0, Xn = 0.0, rel_last = 0.0;
-    __syncthreads();                  // prologue A
+    int state = 0;   // 0 running, 1 stopped (converged or T_max), 2 abandoned
     if (a.T_max >= 1) {
-        publish_partials(0, 1u);
-        if (reducer) {
-            ok = wave_wait_flags(flagsA, P, 1u, abort_flag, a.timeout_ticks);
-            if (ok) publish_b(0, 0, presum(0), 1u);   // no correction for the first panel
+        // prologue: partials of panels 0 and 1 (both from r0); b of panel 0 (no correction)
+        ok = wait_parts(1);
+        if (ok) publish_partials(0);
+        if (ok) ok = wait_parts(2);
+        if (ok) publish_partials(1);
+        if (ok && reducer) {
+            ok = wave_wait_flags(flagsA, P, 1u, abort_flag, tmo);
+            if (ok) publish_b(0, 0, presum(0));
         }
-    }
-    if (lane == 0) ctl_s = ok ? 0 : 2;
-    __syncthreads();                  // prologue end
-    if (a.T_max >= 1 && ok) {
         int K = 0, t = 1;
-        uint32_t q = 0;
-        int state = 0;                // 0 running, 1 stopped, 2 abandoned (sticky)
-        for (;;) {
-            for (int g = 0; g < 3; ++g) {
-                const bool live = state == 0;
-                const int K1 = (K + 1 < np) ? K + 1 : 0;
-                V presum_j = czero<T>();
-                V xr[KL];
-                __syncthreads();      // A
-                if (live) {
-                    publish_partials((q + 1) & 1, q + 2);
-                    stage_M(K);
-                    if (reducer) {
+        for (int q = 0; ok; ++q) {
+            const int K1 = (K + 1 < np) ? K + 1 : 0;
+            // b, x and M of this step's panel into LDS buffer q & 1 (free: the tile waves
+            // finished step q - 2, whose delta this wave has already seen)
+            stage_M(K, q & 1);
+            V xr[KL];
+            if (reducer) {
 #pragma unroll
-                        for (int i = 0; i < KL; ++i) {
-                            const int v = lane + 64 * i;
-                            xr[i] = (v < KP) ? a.X[((int64_t)K1 * KP + w) * KP + v] : czero<T>();
-                        }
-                        if (ok) ok = wave_wait_flags(flagsA, P, q + 2, abort_flag, a.timeout_ticks);
-                        if (ok) presum_j = presum((q + 1) & 1);
-                    }
-                    if (ok) ok = wave_wait_flags(flagsB, KP, q + 1, abort_flag, a.timeout_ticks);
-                    if (ok) {
-#pragma unroll
-                        for (int i = 0; i < KL; ++i) {
-                            const int j = lane + 64 * i;
-                            if (j < KP) {
-                                bsh[j] = ld_dev(&a.gbuf[((int64_t)(q & 1) * KP + j) * 2 + 0]);
-                                xsh[j] = ld_dev(&a.gbuf[((int64_t)(q & 1) * KP + j) * 2 + 1]);
-                            }
-                        }
-                    }
-                    wave_drain_vmem();    // includes the LDS-direct loads of M_K
-                    if (!ok) state = 2;
+                for (int i = 0; i < KL; ++i) {
+                    const int v = lane + 64 * i;
+                    xr[i] = (v < KP) ? a.X[((int64_t)K1 * KP + w) * KP + v] : czero<T>();
                 }
-                __syncthreads();      // B
-                __syncthreads();      // C
-                __syncthreads();      // C'
-                if (live && ok) {
-                    // statistics, x of panel K, and b of panel K+1 (corrected by X_{K+1} delta_K)
-                    double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                    for (int i = 0; i < KL; ++i) {
-                        const int j = lane + 64 * i;
-                        if (j < KP) {
-                            const V d = dsh[j];
-                            V xn;
-                            xn.x = xsh[j].x + d.x;
-                            xn.y = xsh[j].y + d.y;
-                            s1 += cabs2d(d);
-                            s2 += cabs2d(xn);
-                        }
-                    }
-                    S += wave_allsum(s1);
-                    Xn += wave_allsum(s2);
-                    if (reducer) {
-                        V c = czero<T>();
-#pragma unroll
-                        for (int i = 0; i < KL; ++i) {
-                            const int v = lane + 64 * i;
-                            if (v < KP) cfma(c, xr[i], dsh[v]);
-                        }
-                        c.x = wave_allsum(c.x);
-                        c.y = wave_allsum(c.y);
-                        if (lane == 0) {
-                            const int u = K * KP + w;
-                            if (u < U) {
-                                V xn;
-                                xn.x = xsh[w].x + dsh[w].x;
-                                xn.y = xsh[w].y + dsh[w].y;
-                                a.x[u] = xn;
-                            }
-                        }
-                        V gg;
-                        gg.x = presum_j.x - c.x;
-                        gg.y = presum_j.y - c.y;
-                        publish_b(K1, (q + 1) & 1, gg, q + 2);
-                    }
-                    if (K == np - 1) {
-                        sweeps = t;
-                        rel_last = (Xn > 0.0) ? sqrt(S / Xn) : (S > 0.0 ? INFINITY : 0.0);
-                        if (t >= a.T_max || (a.tol > 0.0 && sqrt(S) <= a.tol * sqrt(Xn))) state = 1;
-                        S = 0.0;
-                        Xn = 0.0;
-                        ++t;
-                    }
-                }
-                if (lane == 0) ctl_s = state;
-                __syncthreads();      // D
-                K = K1;
-                ++q;
-                __syncthreads();      // E
             }
-            if (state != 0) break;
+            ok = wave_wait_flags(flagsB, KP, (uint32_t)q + 1, abort_flag, tmo);
+            if (!ok) break;
+#pragma unroll
+            for (int i = 0; i < KL; ++i) {
+                const int j = lane + 64 * i;
+                if (j < KP) {
+                    bsh[q & 1][j] = ld_dev(&a.gbuf[((int64_t)(q & 1) * KP + j) * 2 + 0]);
+                    xsh[q & 1][j] = ld_dev(&a.gbuf[((int64_t)(q & 1) * KP + j) * 2 + 1]);
+                }
+            }
+            wave_drain_vmem();   // includes the LDS-direct loads of M_K
+            if (lane == 0) lds_set(&b_ready, q + 1);
+            // statistics and x of panel K once the tile waves have delta
+            ok = wait_delta(q);
+            if (!ok) break;
+            double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int i = 0; i < KL; ++i) {
+                const int j = lane + 64 * i;
+                if (j < KP) {
+                    const V d = dsh[q & 1][j];
+                    V xn;
+                    xn.x = xsh[q & 1][j].x + d.x;
+                    xn.y = xsh[q & 1][j].y + d.y;
+                    s1 += cabs2d(d);
+                    s2 += cabs2d(xn);
+                }
+            }
+            S += wave_allsum(s1);
+            Xn += wave_allsum(s2);
+            if (reducer && lane == 0) {
+                const int u = K * KP + w;
+                if (u < U) {
+                    V xn;
+                    xn.x = xsh[q & 1][w].x + dsh[q & 1][w].x;
+                    xn.y = xsh[q & 1][w].y + dsh[q & 1][w].y;
+                    a.x[u] = xn;
+                }
+            }
+            if (K == np - 1) {
+                sweeps = t;
+                rel_last = (Xn > 0.0) ? sqrt(S / Xn) : (S > 0.0 ? INFINITY : 0.0);
+                const bool done = t >= a.T_max || (a.tol > 0.0 && sqrt(S) <= a.tol * sqrt(Xn));
+                S = 0.0;
+                Xn = 0.0;
+                ++t;
+                if (done) {
+                    state = 1;
+                    break;
+                }
+            }
+            // reducer: b of panel K+1 = (sum of its look-ahead partials) - X_{K+1} delta_K
+            // - lambda x (the partials were published one step ago)
+            if (reducer) {
+                ok = wave_wait_flags(flagsA, P, (uint32_t)q + 2, abort_flag, tmo);
+                if (!ok) break;
+                const V g = presum(q + 1);
+                V c = czero<T>();
+#pragma unroll
+                for (int i = 0; i < KL; ++i) {
+                    const int v = lane + 64 * i;
+                    if (v < KP) cfma(c, xr[i], dsh[q & 1][v]);
+                }
+                c.x = wave_allsum(c.x);
+                c.y = wave_allsum(c.y);
+                publish_b(K1, q + 1, cmake<T>(g.x - c.x, g.y - c.y));
+            }
+            // the tile waves' partials of panel K+2 (sequence q + 2)
+            ok = wait_parts(q + 3);
+            if (!ok) break;
+            publish_partials(q + 2);
+            K = K1;
         }
     }
+    if (!ok) state = 2;
+    if (lane == 0) lds_set(&stop_w, state == 0 ? 1 : state);
     if (w == 0 && lane == 0) {
         int fl = 0;
         if (a.tol > 0.0 && !(rel_last <= a.tol)) fl |= CDM_INFO_NOT_CONVERGED;
-        if (!ok) fl |= CDM_INFO_TIMEOUT;
+        if (state == 2) fl |= CDM_INFO_TIMEOUT;
         cdm_info o;
         o.sweeps = sweeps;
         o.flags = fl;

@@ -65,6 +65,7 @@ struct cdm_plan {
     // PANEL engine
     int kp = 128, rpl = 1, P = 1, npanels = 1, nsplit = 1;
     bool la = false;          // look-ahead schedule (k_cd_panel_la)
+    size_t part_bytes = 0, gbuf_bytes = 0;
     void* X = nullptr;        // its cross blocks H_K^H H_{K-1}
     uint64_t timeout_ticks = 0;
     // workspace
@@ -286,6 +287,11 @@ static int32_t run_sparse(cdm_plan* p, const void* val, const int32_t* rowptr, c
 
 static constexpr int kInnerSweeps = 8;   // low-precision CD sweeps per outer refinement step
 
+// The panel sweep launch (look-ahead or two-hop schedule).
+static hipError_t launch_sweep(cdm_plan* p, const PanelLaunch& L, hipStream_t st) {
+    return p->la ? launch_panel_la(L, st) : launch_panel(L, st);
+}
+
 static int32_t run_resid(cdm_plan* p, const void* H, int64_t ldh, const void* y, double lambda, const void* x,
                          double* out, hipStream_t st);
 
@@ -382,7 +388,7 @@ static int32_t solve_mixed(cdm_plan* p, const void* H, int64_t ldh, const void* 
     L.info = (cdm_info*)((char*)p->mx_done + 32);   // the inner launches' own record (unused)
     for (int k = 0; k < d.T_max; ++k) {
         HIP_TRY(launch_mixed_outer_head(M, st));
-        HIP_TRY(p->la ? launch_panel_la(L, st) : launch_panel(L, st));
+        HIP_TRY(launch_sweep(p, L, st));
         HIP_TRY(launch_mixed_outer_tail(M, st));
     }
     HIP_TRY(launch_mixed_finish(M, st));
@@ -492,7 +498,7 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
             // look-ahead schedule: 64-row blocks, one reducer workgroup per panel column
             const int kp = p->c128 ? 64 : 128;
             const int P = (d.B + 63) / 64;
-            if ((!d.panel || d.panel == kp) && P >= kp && P <= panel_la_max_coresident(p->c128, kp) &&
+            if ((!d.panel || d.panel == kp) && P >= kp && P <= 256 && P <= panel_la_max_coresident(p->c128, kp) &&
                 16 + P + kp <= kCtrWords) {
                 p->kp = kp;
                 p->rpl = 1;
@@ -526,8 +532,10 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         o_r0 = ar.take(p->esz * d.B);
         o_M = ar.take(p->esz * kk);
         o_gpart = ar.take(p->esz * kk * std::max(2, p->nsplit));
-        o_part = ar.take(p->esz * 2 * (size_t)p->kp * p->P);
-        o_gbuf = ar.take(p->esz * 2 * (size_t)p->kp * 2);
+        p->part_bytes = p->esz * 2 * (size_t)p->kp * p->P;
+        p->gbuf_bytes = p->esz * 2 * (size_t)p->kp * 2;
+        o_part = ar.take(p->part_bytes);
+        o_gbuf = ar.take(p->gbuf_bytes);
         o_e = ar.take(sizeof(double) * d.U);
         o_rpart = ar.take(16 * (size_t)p->nchunk * d.B);
         if (p->la) o_X = ar.take(p->esz * kk);
@@ -801,7 +809,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         L.T_max = d.T_max;
         L.tol = d.tol;
         L.timeout_ticks = p->timeout_ticks;
-        HIP_TRY(p->la ? launch_panel_la(L, st) : launch_panel(L, st));
+        HIP_TRY(launch_sweep(p, L, st));
         ev_record(p, 3, st);
         HIP_TRY(launch_finalize(x, d.U, p->c128, p->ctr + 2, inf, st));
     }
