@@ -31,42 +31,53 @@ namespace cdm {
 constexpr int LA_NWT = 8;                 // tile waves
 constexpr int LA_NT = 64 * (LA_NWT + 1);  // + one control wave
 
-// ---- cross-workgroup flags (control wave only) ------------------------------------
-// One wave: wait until flags[0..count) are all >= target.  Same time-out and abort
-// protocol as wg_wait_flags, without a workgroup barrier.  Uniform result.
-__device__ __forceinline__ bool wave_wait_flags(const uint32_t* flags, int count, uint32_t target,
-                                                uint32_t* abort_flag, uint64_t timeout_ticks) {
-    const int lane = threadIdx.x & 63;
-    uint64_t t0 = 0;
-    bool started = false;
-    for (;;) {
-        bool mine = true;
-        for (int base = 0; base < count; base += 256) {
-            uint32_t v[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = ld_relaxed(&flags[min(base + lane + 64 * k, count - 1)]);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) mine &= (v[k] >= target);
-        }
-        if (__all(mine)) return true;
-        if (!started) {
-            t0 = wall_clock64();
-            started = true;
-        }
-        if (ld_relaxed(abort_flag)) return false;
-        if (wall_clock64() - t0 > timeout_ticks) {
-            if (lane == 0) st_relaxed(abort_flag, 1u);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(1);
+// Tagged words: a 32-bit payload and a 32-bit tag (panel sequence number + 1) in one
+// 64-bit word, stored and loaded single-copy atomically at agent scope.  A reader
+// that sees the expected tag in every word of a value has that value, so the data is
+// its own arrival signal: no store drain, no separate flag and no second read.  The
+// exchange buffers are cleared before each launch.
+__device__ __forceinline__ void st_tag(uint64_t* p, uint32_t payload, uint32_t tag) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), ((unsigned long long)tag << 32) | payload,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_tag(const uint64_t* p) {
+    return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T> struct Tagged;
+template <> struct Tagged<double> {             // complex128: four words (lo, hi of re and im)
+    static constexpr int NW = 4;
+    __device__ static void put(uint64_t* p, double2 v, uint32_t tag) {
+        const unsigned long long a = __double_as_longlong(v.x), b = __double_as_longlong(v.y);
+        st_tag(p + 0, (uint32_t)a, tag);
+        st_tag(p + 1, (uint32_t)(a >> 32), tag);
+        st_tag(p + 2, (uint32_t)b, tag);
+        st_tag(p + 3, (uint32_t)(b >> 32), tag);
     }
-}
-
-// One wave: after this wave's st_dev stores, set flags[w] = value.
-__device__ __forceinline__ void wave_publish(uint32_t* flags, int w, uint32_t value) {
-    wave_drain_vmem();
-    if ((threadIdx.x & 63) == 0) st_relaxed(&flags[w], value);
-}
+    // the words are loaded before any is tested (one memory round trip per attempt)
+    __device__ static bool get(const uint64_t* p, uint32_t tag, double2& v) {
+        const uint64_t w0 = ld_tag(p + 0), w1 = ld_tag(p + 1), w2 = ld_tag(p + 2), w3 = ld_tag(p + 3);
+        const bool ok = ((uint32_t)(w0 >> 32) == tag) & ((uint32_t)(w1 >> 32) == tag) &
+                        ((uint32_t)(w2 >> 32) == tag) & ((uint32_t)(w3 >> 32) == tag);
+        v.x = __longlong_as_double((long long)(((w1 & 0xffffffffull) << 32) | (w0 & 0xffffffffull)));
+        v.y = __longlong_as_double((long long)(((w3 & 0xffffffffull) << 32) | (w2 & 0xffffffffull)));
+        return ok;
+    }
+};
+template <> struct Tagged<float> {              // complex64: two words
+    static constexpr int NW = 2;
+    __device__ static void put(uint64_t* p, float2 v, uint32_t tag) {
+        st_tag(p + 0, __float_as_uint(v.x), tag);
+        st_tag(p + 1, __float_as_uint(v.y), tag);
+    }
+    __device__ static bool get(const uint64_t* p, uint32_t tag, float2& v) {
+        const uint64_t w0 = ld_tag(p + 0), w1 = ld_tag(p + 1);
+        const bool ok = ((uint32_t)(w0 >> 32) == tag) & ((uint32_t)(w1 >> 32) == tag);
+        v.x = __uint_as_float((uint32_t)w0);
+        v.y = __uint_as_float((uint32_t)w1);
+        return ok;
+    }
+};
 
 // ---- intra-workgroup LDS words ------------------------------------------------------
 // A writer completes its LDS data writes (lgkmcnt = 0) before it bumps a word; LDS
@@ -139,8 +150,6 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
     __syncthreads();   // the only workgroup barrier
 
     uint32_t* abort_flag = a.ctr + 2;
-    uint32_t* flagsA = a.ctr + 16;              // partials of panel sequence s published: s + 1
-    uint32_t* flagsB = a.ctr + 16 + P;          // b of panel sequence s published: s + 1
     const int row0 = w * 64 * RPL;
     const uint64_t tmo = a.timeout_ticks;
 
@@ -329,33 +338,116 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
         }
         return true;
     };
-    // publish the partials of panel sequence s (psh[s & 1]) to part[s & 1]
+    // exchange buffers of tagged words: part [2][KP][P][NW] (slot, column, workgroup),
+    // gbuf [2][KP][2][NW] (slot, column, {b, x})
+    using TG = Tagged<T>;
+    constexpr int NW = TG::NW;
+    uint64_t* part64 = reinterpret_cast<uint64_t*>(a.part);
+    uint64_t* gb64 = reinterpret_cast<uint64_t*>(a.gbuf);
+    // common poll loop: `more()` re-reads what has not arrived yet and returns true
+    // while something is still missing in this lane
+    auto poll = [&](auto&& more) -> bool {
+        uint64_t t0 = 0;
+        bool started = false;
+        for (;;) {
+            if (!__any(more())) return true;
+            if (!started) {
+                t0 = wall_clock64();
+                started = true;
+            }
+            if (ld_relaxed(abort_flag)) return false;
+            if (wall_clock64() - t0 > tmo) {
+                if (lane == 0) st_relaxed(abort_flag, 1u);
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    };
+    // publish the partials of panel sequence s (psh[s & 1]); fire and forget
     auto publish_partials = [&](int s) {
 #pragma unroll
         for (int i = 0; i < KL; ++i) {
             const int j = lane + 64 * i;
-            if (j < KP) st_dev(&a.part[((int64_t)(s & 1) * KP + j) * P + w], psh[s & 1][j]);
+            if (j < KP) TG::put(part64 + (((int64_t)(s & 1) * KP + j) * P + w) * NW, psh[s & 1][j], (uint32_t)s + 1);
         }
-        wave_publish(flagsA, w, (uint32_t)s + 1);
     };
-    // reducer: sum over the P workgroups of column j = w (fixed order per lane, then a
-    // fixed butterfly), uniform result
-    auto presum = [&](int s) -> V {
-        const V* src = a.part + ((int64_t)(s & 1) * KP + w) * P;
-        V acc = czero<T>();
-        for (int base = 0; base < P; base += 256) {
-            V v[4];
+    // reducer: wait for the P partials of column j = w of sequence s and sum them (fixed
+    // order per lane, then a fixed butterfly); uniform result
+    auto gather_partials = [&](int s, V& out) -> bool {
+        const uint64_t* src = part64 + ((int64_t)(s & 1) * KP + w) * P * NW;
+        const uint32_t tag = (uint32_t)s + 1;
+        V v[4];
+        bool have[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = (base + lane + 64 * k < P) ? ld_dev(&src[base + lane + 64 * k]) : czero<T>();
+        for (int k = 0; k < 4; ++k) {
+            v[k] = czero<T>();
+            have[k] = lane + 64 * k >= P;   // lanes past P contribute zero
+        }
+        auto more = [&]() {
+            // every attempt reloads all four (unconditional loads issue back to back)
+            V nv[4];
+            bool ok4[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ok4[k] = TG::get(src + (int64_t)min(lane + 64 * k, P - 1) * NW, tag, nv[k]);
+            bool miss = false;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                acc.x += v[k].x;
-                acc.y += v[k].y;
+                if (!have[k] && ok4[k]) {
+                    v[k] = nv[k];
+                    have[k] = true;
+                }
+                miss |= !have[k];
             }
+            return miss;
+        };
+        if (!poll(more)) return false;
+        V acc = czero<T>();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            acc.x += v[k].x;
+            acc.y += v[k].y;
         }
         acc.x = wave_allsum(acc.x);
         acc.y = wave_allsum(acc.y);
-        return acc;
+        out = acc;
+        return true;
+    };
+    // everyone: wait for b and x of sequence q (the step's panel) and put them in LDS
+    auto gather_b = [&](int q) -> bool {
+        const uint32_t tag = (uint32_t)q + 1;
+        V bv[KL], xv[KL];
+        bool hb[KL], hx[KL];
+#pragma unroll
+        for (int i = 0; i < KL; ++i) hb[i] = hx[i] = lane + 64 * i >= KP;
+        auto more = [&]() {
+            bool miss = false;
+#pragma unroll
+            for (int i = 0; i < KL; ++i) {
+                const uint64_t* q0 = gb64 + (((int64_t)(q & 1) * KP + min(lane + 64 * i, KP - 1)) * 2) * NW;
+                V nb, nx;
+                const bool okb = TG::get(q0, tag, nb), okx = TG::get(q0 + NW, tag, nx);
+                if (!hb[i] && okb) {
+                    bv[i] = nb;
+                    hb[i] = true;
+                }
+                if (!hx[i] && okx) {
+                    xv[i] = nx;
+                    hx[i] = true;
+                }
+                miss |= !(hb[i] && hx[i]);
+            }
+            return miss;
+        };
+        if (!poll(more)) return false;
+#pragma unroll
+        for (int i = 0; i < KL; ++i) {
+            const int j = lane + 64 * i;
+            if (j < KP) {
+                bsh[q & 1][j] = bv[i];
+                xsh[q & 1][j] = xv[i];
+            }
+        }
+        return true;
     };
     // reducer: publish b_j = g_j - lambda x_j (+ bias) of panel K (sequence s)
     auto publish_b = [&](int K, int s, V g) {
@@ -370,10 +462,10 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
             V b;
             b.x = g.x - lambda * xo.x;
             b.y = g.y - lambda * xo.y;
-            st_dev(&a.gbuf[((int64_t)(s & 1) * KP + w) * 2 + 0], b);
-            st_dev(&a.gbuf[((int64_t)(s & 1) * KP + w) * 2 + 1], xo);
+            uint64_t* q0 = gb64 + (((int64_t)(s & 1) * KP + w) * 2) * NW;
+            TG::put(q0, b, (uint32_t)s + 1);
+            TG::put(q0 + NW, xo, (uint32_t)s + 1);
         }
-        wave_publish(flagsB, w, (uint32_t)s + 1);
     };
     auto stage_M = [&](int K, int buf) {
         // global -> LDS without passing through registers: lane l of each load moves
@@ -393,8 +485,9 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
         if (ok) ok = wait_parts(2);
         if (ok) publish_partials(1);
         if (ok && reducer) {
-            ok = wave_wait_flags(flagsA, P, 1u, abort_flag, tmo);
-            if (ok) publish_b(0, 0, presum(0));
+            V g0;
+            ok = gather_partials(0, g0);
+            if (ok) publish_b(0, 0, g0);   // no correction for the first panel
         }
         int K = 0, t = 1;
         for (int q = 0; ok; ++q) {
@@ -410,17 +503,9 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
                     xr[i] = (v < KP) ? a.X[((int64_t)K1 * KP + w) * KP + v] : czero<T>();
                 }
             }
-            ok = wave_wait_flags(flagsB, KP, (uint32_t)q + 1, abort_flag, tmo);
+            ok = gather_b(q);
             if (!ok) break;
-#pragma unroll
-            for (int i = 0; i < KL; ++i) {
-                const int j = lane + 64 * i;
-                if (j < KP) {
-                    bsh[q & 1][j] = ld_dev(&a.gbuf[((int64_t)(q & 1) * KP + j) * 2 + 0]);
-                    xsh[q & 1][j] = ld_dev(&a.gbuf[((int64_t)(q & 1) * KP + j) * 2 + 1]);
-                }
-            }
-            wave_drain_vmem();   // includes the LDS-direct loads of M_K
+            wave_drain_vmem();   // the LDS-direct loads of M_K have landed
             if (lane == 0) lds_set(&b_ready, q + 1);
             // statistics and x of panel K once the tile waves have delta
             ok = wait_delta(q);
@@ -464,9 +549,9 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
             // reducer: b of panel K+1 = (sum of its look-ahead partials) - X_{K+1} delta_K
             // - lambda x (the partials were published one step ago)
             if (reducer) {
-                ok = wave_wait_flags(flagsA, P, (uint32_t)q + 2, abort_flag, tmo);
+                V g;
+                ok = gather_partials(q + 1, g);
                 if (!ok) break;
-                const V g = presum(q + 1);
                 V c = czero<T>();
 #pragma unroll
                 for (int i = 0; i < KL; ++i) {

@@ -287,9 +287,14 @@ static int32_t run_sparse(cdm_plan* p, const void* val, const int32_t* rowptr, c
 
 static constexpr int kInnerSweeps = 8;   // low-precision CD sweeps per outer refinement step
 
-// The panel sweep launch (look-ahead or two-hop schedule).
+// The panel sweep launch.  The look-ahead schedule's exchange buffers carry sequence
+// tags and start each launch cleared (a fill kernel, so the solve stays capturable).
 static hipError_t launch_sweep(cdm_plan* p, const PanelLaunch& L, hipStream_t st) {
-    return p->la ? launch_panel_la(L, st) : launch_panel(L, st);
+    if (!p->la) return launch_panel(L, st);
+    hipError_t e = launch_zero_u32((uint32_t*)p->part, (int)(p->part_bytes / 4), st);
+    if (e == hipSuccess) e = launch_zero_u32((uint32_t*)p->gbuf, (int)(p->gbuf_bytes / 4), st);
+    if (e == hipSuccess) e = launch_panel_la(L, st);
+    return e;
 }
 
 static int32_t run_resid(cdm_plan* p, const void* H, int64_t ldh, const void* y, double lambda, const void* x,
@@ -532,8 +537,9 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         o_r0 = ar.take(p->esz * d.B);
         o_M = ar.take(p->esz * kk);
         o_gpart = ar.take(p->esz * kk * std::max(2, p->nsplit));
-        p->part_bytes = p->esz * 2 * (size_t)p->kp * p->P;
-        p->gbuf_bytes = p->esz * 2 * (size_t)p->kp * 2;
+        // the look-ahead schedule exchanges tagged words: twice the bytes per value
+        p->part_bytes = (p->la ? 2 : 1) * p->esz * 2 * (size_t)p->kp * p->P;
+        p->gbuf_bytes = (p->la ? 2 : 1) * p->esz * 2 * (size_t)p->kp * 2;
         o_part = ar.take(p->part_bytes);
         o_gbuf = ar.take(p->gbuf_bytes);
         o_e = ar.take(sizeof(double) * d.U);
