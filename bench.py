@@ -27,6 +27,27 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the sweep kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# passes scaled by the copy-kernel calibration (profiles/k_cd_panel_la_c128_16384x8192.md),
+# valid only while the kernel sources hash to the recorded value.
+TRAFFIC = {
+    ("k_cd_panel_la", "c128", 16384, 8192, 1e-11): {"sources_sha256_16": "0e6dc0ce277c9d31", "bytes": 144998758445.0},
+}
+TRAFFIC_SOURCES = ["paper_1902_08653_amd/csrc/k_panel_la.hip", "paper_1902_08653_amd/csrc/panel.hpp",
+                   "paper_1902_08653_amd/csrc/common.hpp"]
+
+
+def measured_traffic(kernel, prec, B, U, tol):
+    import hashlib
+    rec = TRAFFIC.get((kernel, prec, B, U, tol))
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return rec["bytes"] if h.hexdigest()[:16] == rec["sources_sha256_16"] else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -194,7 +215,8 @@ def main():
                    "B": a.B, "U": a.U, "precision": prec, "tol": tol, "eps": eps,
                    "engine": json.loads(plan.describe())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(sweep_kernel, prec, a.B, a.U, tol),
                      "kernel": sweep_kernel, "algorithmic_bytes_per_launch": mean_sweeps * h_bytes,
                      "avg_launch_ms": sweep_ms},
         "cpu_baseline": cpu,
