@@ -72,6 +72,8 @@ def parse():
                          "warm: learned warm start against a cold start on 4096 held-out uneven instances")
     ap.add_argument("--train", type=int, default=50000, help="warm: training instances")
     ap.add_argument("--epochs", type=int, default=3, help="warm: training epochs")
+    ap.add_argument("--inner", default="c64", choices=["c64", "bf16"],
+                    help="warm: inner copy of the mixed-precision form")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--sample", type=int, default=12, help="batched: instances checked against the oracle")
     return ap.parse_args()
@@ -155,22 +157,7 @@ def main():
     mean_sweeps = float(np.mean(sweeps))
     achieved = mean_sweeps * h_bytes / (sweep_ms * 1e-3) / 1e9
 
-    copy_gbs = None
-    if a.copy_probe:
-        nb = 1 << 30
-        src = torch.empty(nb // 16, dtype=torch.complex128, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(2):
-            cdm.stream_copy(src, dst)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(5):
-            cdm.stream_copy(src, dst)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        copy_gbs = 2 * nb * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        del src, dst
+    copy_gbs = _copy_probe(cdm, dev, stream) if a.copy_probe else None
 
     oracle_err = None
     cpu = None
@@ -322,10 +309,31 @@ def bench_batched(a):
         "accuracy": {"sweeps_mean": float(sweeps.mean()), "sweeps_max": int(sweeps.max()),
                      "flags_or": int(np.bitwise_or.reduce(rec["flags"])),
                      "max_rel_err_vs_oracle_sample": max(errs) if errs else None,
-                     "within_eps": (max(errs) <= eps) if errs else None},
+                     "within_eps": bool(max(errs) <= eps) if errs else None},
     }
+    if a.copy_probe:
+        out["copy_probe_gbs"] = _copy_probe(cdm, dev, stream)
     print(json.dumps(out))
     plan.close()
+
+
+def _copy_probe(cdm, dev, stream):
+    """GB/s of the library's plain copy kernel over 1 GiB (read + write); its HBM
+    counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    nb = 1 << 30
+    src = torch.empty(nb // 16, dtype=torch.complex128, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        cdm.stream_copy(src, dst)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        cdm.stream_copy(src, dst)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return 2 * nb * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
 def _graph(fn):
@@ -365,7 +373,9 @@ def bench_warm(a):
     chunks of 4096) solved to a relative step of 1e-11; per-coordinate features and
     solutions train the 8 -> 512 -> 512 -> 2 network.  Held out: 4096 instances (seeds
     0..4095) solved to a relative step of 1e-8 from x0 = 0 (cold) and from the
-    network's x0 (warm: feature pass + network + solve, all in one HIP graph)."""
+    network's x0 (warm: feature pass + network + solve, all in one HIP graph), both with
+    plain complex128 sweeps and with the mixed-precision refinement; `value` is the warm
+    mixed-precision form."""
     import torch
 
     from paper_1902_08653_amd import cdm, inputs
@@ -405,52 +415,75 @@ def bench_warm(a):
     lin_mse = float(((T.double() - lin_a * zs) ** 2).mean())
     del F, T, zs
     # ---- held-out comparison ---------------------------------------------------------
+    # four forms on the same batch, each one HIP graph: plain complex128 sweeps and the
+    # mixed-precision refinement (complex64 or BF16 inner copy), each cold (x0 = 0) and
+    # warm (feature pass + network + solve)
     H, y, m, n = inputs.batch_uneven_device(a.batch, seed0=0, dtype=c128, device=dev)
-    plan = cdm.BatchedPlan(m, n, precision="c128", T_max=500, tol=tol, autotune=True)
+    inner = {"c64": "mixed-c64", "bf16": "bf16"}[a.inner]
+    plans = {"plain": cdm.BatchedPlan(m, n, precision="c128", T_max=500, tol=tol, autotune=True),
+             "mixed": cdm.BatchedPlan(m, n, precision=inner, T_max=8 if a.inner == "c64" else 16, tol=tol,
+                                      autotune=True)}
     N = int(n.astype(np.int64).sum())
-    xc = torch.empty(N, dtype=c128, device=dev)
-    xw = torch.empty(N, dtype=c128, device=dev)
     x0 = torch.empty(N, dtype=c128, device=dev)
-    ic = torch.empty(32 * a.batch, dtype=torch.uint8, device=dev)
-    iw = torch.empty(32 * a.batch, dtype=torch.uint8, device=dev)
     Fh = torch.empty((N, 8), dtype=torch.float32, device=dev)
+    xs = {k: torch.empty(N, dtype=c128, device=dev) for k in ("plain_cold", "plain_warm", "mixed_cold", "mixed_warm")}
+    infos = {k: torch.empty(32 * a.batch, dtype=torch.uint8, device=dev) for k in xs}
 
-    def cold():
-        plan.solve(H, y, N0=a.lam, x=xc, info=ic)
+    def form(name):
+        plan = plans[name.split("_")[0]]
+        if name.endswith("cold"):
+            return lambda: plan.solve(H, y, N0=a.lam, x=xs[name], info=infos[name])
+        return lambda: ws.solve(plan, H, y, N0=a.lam, x0=x0, feat=Fh, x=xs[name], info=infos[name])
 
-    def warm():
-        ws.solve(plan, H, y, N0=a.lam, x0=x0, feat=Fh, x=xw, info=iw)
-
-    gc, gw = _graph(cold), _graph(warm)
-    ms_c = _time_graph(gc, a.steps, a.warmup)
-    ms_w = _time_graph(gw, a.steps, a.warmup)
-    # stage split of the warm path (eager, events on the current stream)
+    ms = {}
+    for k in xs:
+        g = _graph(form(k))
+        ms[k] = _time_graph(g, a.steps, a.warmup)
+        del g
+    # stage split of the warm mixed form (eager, events on the current stream)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ev[0].record()
-    plan.features(H, y, N0=a.lam, out=Fh)
+    plans["mixed"].features(H, y, N0=a.lam, out=Fh)
     ev[1].record()
     ws.net.predict(Fh, c128, out=x0)
     ev[2].record()
-    plan.solve(H, y, N0=a.lam, x0=x0, x=xw, info=iw)
+    plans["mixed"].solve(H, y, N0=a.lam, x0=x0, x=xs["mixed_warm"], info=infos["mixed_warm"])
     ev[3].record()
     torch.cuda.synchronize()
     st = [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
-    rc, rw = cdm.parse_info(ic), cdm.parse_info(iw)
-    sc, sw = rc["sweeps"].astype(np.int64), rw["sweeps"].astype(np.int64)
-    hbytes = (m.astype(np.int64) * n.astype(np.int64)) * 16
-    log("cold %.2f ms (sweeps mean %.2f), warm %.2f ms (sweeps mean %.2f); warm stages feat %.2f "
-        "mlp %.2f solve %.2f ms" % (ms_c, sc.mean(), ms_w, sw.mean(), st[0], st[1], st[2]))
+    rec = {k: cdm.parse_info(v) for k, v in infos.items()}
+    mn = m.astype(np.int64) * n.astype(np.int64)
+    lowsz = 8 if a.inner == "c64" else 4
+
+    def stats(k):
+        r = rec[k]
+        d = {"ms": ms[k], "instance_solves_per_s": a.batch * 1000.0 / ms[k],
+             "flags_or": int(np.bitwise_or.reduce(r["flags"]))}
+        if k.startswith("plain"):
+            d["sweeps_mean"] = float(r["sweeps"].mean())
+        else:
+            d["outer_mean"] = float(r["sweeps"].mean())
+            d["inner_sweeps_mean"] = float(r["reserved"].mean())
+        return d
+
+    for k in ms:
+        log("%s: %.2f ms %s" % (k, ms[k], {q: v for q, v in stats(k).items() if q != "ms"}))
+    # algorithmic bytes of the mixed kernel per instance: complex128 passes (the first
+    # step of a cold start needs only g), inner sweeps over the copy, the copy's write
+    rm = rec["mixed_warm"]
+    passes = 2 * rm["sweeps"].astype(np.int64)
+    mixed_bytes = float((mn * (16 * passes + lowsz * rm["reserved"].astype(np.int64) + lowsz)).sum())
     mlp_flop = 2.0 * N * (8 * 512 + 512 * 512 + 512 * 2)
     cpu, errs = None, []
     if not a.no_oracle:
         from oracle import oracle
         oracle.build()
-        order = np.argsort(-(m.astype(np.int64) * n))
+        order = np.argsort(-mn)
         pick = order[np.linspace(0, a.batch - 1, a.sample).astype(int)]
-        ho = np.concatenate([[0], np.cumsum(m.astype(np.int64) * n)[:-1]])
+        ho = np.concatenate([[0], np.cumsum(mn)[:-1]])
         yo = np.concatenate([[0], np.cumsum(m.astype(np.int64))[:-1]])
         xo = np.concatenate([[0], np.cumsum(n.astype(np.int64))[:-1]])
-        xcg, xwg = xc.cpu().numpy(), xw.cpu().numpy()
+        xg = {k: v.cpu().numpy() for k, v in xs.items()}
         cpu_s, cpu_bytes = 0.0, 0.0
         for i in pick:
             Hi = H[ho[i]:ho[i] + m[i] * n[i]].cpu().numpy().reshape(n[i], m[i]).T
@@ -458,49 +491,50 @@ def bench_warm(a):
             tc = time.perf_counter()
             ref = oracle.local_cd(Hi, yi, a.lam, T_max=500, tol=tol)
             cpu_s += time.perf_counter() - tc
-            cpu_bytes += ref["sweeps"] * float(hbytes[i])
+            cpu_bytes += ref["sweeps"] * float(mn[i] * 16)
             exact = oracle.local_cd(Hi, yi, a.lam, T_max=2000, tol=1e-13)["x"]
             nr = np.linalg.norm(exact)
             sl = slice(xo[i], xo[i] + n[i])
-            errs.append(max(np.linalg.norm(xcg[sl] - exact), np.linalg.norm(xwg[sl] - exact)) / nr)
-        full = float((sc * hbytes).sum())
+            errs.append(max(np.linalg.norm(v[sl] - exact) for v in xg.values()) / nr)
+        full = float((rec["plain_cold"]["sweeps"].astype(np.int64) * mn * 16).sum())
         cpu = {"value": a.batch / (cpu_s * full / cpu_bytes), "unit": "instance solves/s", "cores": 1,
                "kind": "oracle",
                "sample": "%d held-out instances spread over the size range, cold oracle to rel. step %g "
                          "on one thread (%.1f s), scaled by the batch's sweep-weighted H bytes"
                          % (len(pick), tol, cpu_s)}
-    alg_bytes = float((sw * hbytes).sum())
-    achieved = alg_bytes / (st[2] * 1e-3) / 1e9
+    achieved = mixed_bytes / (st[2] * 1e-3) / 1e9
     out = {
         "metric": "solves/sec to fixed rel. tolerance vs FP64 oracle",
-        "value": a.batch * 1000.0 / ms_w,
+        "value": a.batch * 1000.0 / ms["mixed_warm"],
         "unit": "instance solves/s",
-        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_w,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms["mixed_warm"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if a.inner == "c64" else "bf16+f32+f64",
         "data": "synthetic",
-        "config": {"workload": "learned warm start: %d held-out uneven uplink instances, m~U{64..2048}, n=m/2, "
-                               "complex128, lambda=%g, rel-step tol %g; network 8-512-512-2 trained on %d "
-                               "instances (%d epochs)" % (a.batch, a.lam, tol, a.train, a.epochs)},
+        "config": {"workload": "warm-started mixed-precision batched solve: %d held-out uneven uplink instances, "
+                               "m~U{64..2048}, n=m/2, complex128 data, lambda=%g, rel. tol %g; network "
+                               "8-512-512-2 trained on %d instances (%d epochs); inner copy %s"
+                               % (a.batch, a.lam, tol, a.train, a.epochs, a.inner),
+                   "engine": json.loads(plans["mixed"].describe())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_cd_wg (warm solve)",
-                     "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": st[2]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_cd_wg_mixed (warm solve)",
+                     "algorithmic_bytes_per_launch": mixed_bytes, "avg_launch_ms": st[2]},
         "cpu_baseline": cpu,
-        "warm_vs_cold": {
-            "cold_ms": ms_c, "warm_ms": ms_w, "speedup": ms_c / ms_w,
-            "cold_sweeps_mean": float(sc.mean()), "cold_sweeps_median": float(np.median(sc)),
-            "warm_sweeps_mean": float(sw.mean()), "warm_sweeps_median": float(np.median(sw)),
-            "warm_stage_ms": {"features": st[0], "network": st[1], "solve": st[2]},
-            "network_tflops": mlp_flop / (st[1] * 1e-3) / 1e12,
-            "train": {"rows": train_rows, "steps": a.epochs * steps_per_epoch, "seconds": train_s,
-                      "tflops": train_flop / train_s / 1e12, "loss_per_epoch": hist,
-                      "linear_shrinkage_mse": lin_mse},
-            "flags_or": int(np.bitwise_or.reduce(rc["flags"]) | np.bitwise_or.reduce(rw["flags"])),
-            "max_rel_err_vs_oracle_sample": max(errs) if errs else None,
-            "within_eps": (max(errs) <= eps) if errs else None},
+        "forms": {k: stats(k) for k in ms},
+        "speedup_vs_plain_cold": {k: ms["plain_cold"] / ms[k] for k in ms},
+        "warm_stage_ms": {"features": st[0], "network": st[1], "solve": st[2]},
+        "network_tflops": mlp_flop / (st[1] * 1e-3) / 1e12,
+        "train": {"rows": train_rows, "steps": a.epochs * steps_per_epoch, "seconds": train_s,
+                  "tflops": train_flop / train_s / 1e12, "loss_per_epoch": hist,
+                  "linear_shrinkage_mse": lin_mse},
+        "accuracy": {"max_rel_err_vs_oracle_sample": max(errs) if errs else None, "eps": eps,
+                     "within_eps": bool(max(errs) <= eps) if errs else None},
     }
     print(json.dumps(out))
+    for pl in plans.values():
+        pl.close()
     ws.close()
-    plan.close()
 
 
 if __name__ == "__main__":

@@ -54,10 +54,11 @@ typedef enum cdm_status {
 typedef enum cdm_problem { CDM_UPLINK_LMMSE = 0, CDM_DOWNLINK_ZF = 1 } cdm_problem;
 
 /* Arithmetic of the sweep.  CDM_MIXED_* keep H, y and x in FP64 (C128 storage)
- * and run the inner operator products from BF16 or FP8-e4m3 copies of H with an
- * FP64 residual refinement outside (see cdm_solve). */
+ * and run the inner operator products from a low-precision copy of H (BF16,
+ * FP8-e4m3, or the complex64 rounding) with an FP64 residual refinement outside
+ * (see cdm_solve and cdm_solve_batched).  CDM_MIXED_C64 is for batched plans only. */
 typedef enum cdm_precision {
-    CDM_C128 = 0, CDM_C64 = 1, CDM_MIXED_BF16 = 2, CDM_MIXED_FP8 = 3
+    CDM_C128 = 0, CDM_C64 = 1, CDM_MIXED_BF16 = 2, CDM_MIXED_FP8 = 3, CDM_MIXED_C64 = 4
 } cdm_precision;
 
 typedef enum cdm_layout { CDM_DENSE = 0, CDM_CSR = 1 } cdm_layout;
@@ -109,7 +110,7 @@ typedef struct cdm_info {
     int32_t flags;       /* CDM_INFO_* */
     double rel_step;     /* sqrt(sum_u |delta_u|^2) / ||x||_2 of the last sweep */
     double resid;        /* ||H^H(y - Hx) - lambda x|| / ||H^H y|| in FP64 if CDM_F_RESIDUAL, else -1 */
-    double reserved;
+    double reserved;     /* mixed precisions: inner low-precision sweeps performed; else 0 */
 } cdm_info;              /* 32 bytes */
 
 typedef struct cdm_plan cdm_plan;
@@ -158,12 +159,27 @@ int32_t cdm_solve(cdm_plan* plan, const void* H, int64_t ldh, const int32_t* row
 
 /* Create a plan for a batch of independent uplink instances of uneven size
  * (Algorithm 1 with C = 1 per instance).  m, n: host int32[batch], rows (antennas)
- * and columns (users) of each instance, 1 <= n, 1 <= m <= 16384.  Packing rule for
+ * and columns (users) of each instance, 1 <= n, 1 <= m <= 8192 (2048 for the mixed
+ * precisions); the largest n must fit the per-instance LDS state (32 n B for
+ * complex128, 16 n B for complex64, 40 n B mixed, at most about 150 KB).  Packing rule for
  * the solve: instance i's H is m_i x n_i column-major with ld = m_i starting at
  * element offset H_off[i] = sum_{k<i} m_k n_k of the packed H buffer; y_i starts at
  * y_off[i] = sum_{k<i} m_k and x_i at x_off[i] = sum_{k<i} n_k.  The plan fixes the
  * launch schedule (largest instances first) and the tiles per size bucket.
- * desc->precision: CDM_C128 or CDM_C64; desc->T_max, tol as in cdm_desc. */
+ * desc->precision: CDM_C128 or CDM_C64 (plain sweeps; T_max, tol as in cdm_desc), or
+ * CDM_MIXED_C64 / CDM_MIXED_BF16: mixed-precision refinement per instance, with H, y
+ * and x in complex128 (m <= 2048).  Outer step: r = y - H x and g = H^H r - lambda x
+ * in FP64 (two streaming launches over the batch), then inner CD sweeps (Algorithm
+ * 1's rule with bias g) on the correction d from the complex64 or BF16 copy of H in
+ * FP32 (one persistent launch), then x += d.  The copy is written by the first
+ * gradient pass (plan workspace: 8 or 4 B per element of the batch).  An instance is
+ * done after the first inner sweep with ||d|| <= tol ||x + d|| (tol > 0 required); a
+ * step's inner loop stops once its own sweep step is <= tau ||d|| (tau = 1e-5 for the
+ * complex64 copy, 3e-2 for BF16) or after 64 sweeps.  The solve enqueues T_max outer
+ * steps (keep it small, e.g. 8); finished instances skip the remaining ones.
+ * cdm_info.sweeps then counts outer steps and cdm_info.reserved the inner sweeps.
+ * Errors: CDM_EINVAL (tol <= 0 for a mixed precision), CDM_ESHAPE, CDM_ENOTIMPL
+ * (CDM_MIXED_FP8, downlink, CSR), CDM_ENOMEM, CDM_ENODEV. */
 int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m,
                            const int32_t* n, cdm_plan** plan);
 

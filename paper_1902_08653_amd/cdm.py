@@ -18,7 +18,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcdm.so")
 
 UPLINK_LMMSE, DOWNLINK_ZF = 0, 1
-C128, C64, MIXED_BF16, MIXED_FP8 = 0, 1, 2, 3
+C128, C64, MIXED_BF16, MIXED_FP8, MIXED_C64 = 0, 1, 2, 3, 4
 DENSE, CSR = 0, 1
 ENGINE_AUTO, ENGINE_WG, ENGINE_PANEL = 0, 1, 2
 F_RESIDUAL = 1
@@ -28,7 +28,7 @@ F_NO_LOOKAHEAD = 8
 
 INFO_ZERO_COLUMN, INFO_NONFINITE, INFO_NOT_CONVERGED, INFO_TIMEOUT = 1, 2, 4, 8
 
-_PREC = {"c128": C128, "c64": C64, "bf16": MIXED_BF16, "fp8": MIXED_FP8}
+_PREC = {"c128": C128, "c64": C64, "bf16": MIXED_BF16, "fp8": MIXED_FP8, "mixed-c64": MIXED_C64}
 _ENGINE = {"auto": ENGINE_AUTO, "wg": ENGINE_WG, "panel": ENGINE_PANEL}
 
 
@@ -144,7 +144,7 @@ def parse_info(info_tensor):
 
 def _cdtype(precision):
     import torch
-    return torch.complex128 if precision in ("c128", "bf16", "fp8") else torch.complex64
+    return torch.complex128 if precision in ("c128", "bf16", "fp8", "mixed-c64") else torch.complex64
 
 
 class Plan:

@@ -49,6 +49,29 @@ template <typename T> __device__ __forceinline__ T wave_allsum(T v) {
     return v;
 }
 
+// Sum over the 64 lanes of a wave into lane 63 only, with DPP moves (no LDS
+// permute): quad swaps, row shifts by 4 and 8 (each row of 16 lanes then holds its
+// sum in lane 15), then the row-15 and row-31 broadcasts fold the four rows into
+// lane 63.  The other lanes end with partial sums.  Fixed order: deterministic.
+template <int CTRL, int ROW_MASK> __device__ __forceinline__ float dpp_take(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+template <int CTRL, int ROW_MASK> __device__ __forceinline__ double dpp_take(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <typename T> __device__ __forceinline__ T wave_sum_last(T v) {
+    v += dpp_take<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v += dpp_take<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v += dpp_take<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_take<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_take<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_take<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Transpose-reduce of NV per-lane values (NV a power of two, 1 <= NV <= 64) over
 // the 64 lanes.  On return v[0] of lane L holds the full 64-lane sum of value
 // index  c = L >> (6 - log2(NV)); all lanes with that high part hold equal bits.

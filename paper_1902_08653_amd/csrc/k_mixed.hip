@@ -13,22 +13,11 @@
 // so a fixed number of outer launches can be enqueued without host round trips.
 #include "common.hpp"
 #include "launch.hpp"
+#include "quant.hpp"
 
 namespace cdm {
 
 // ---- quantisers ---------------------------------------------------------------
-// BF16 code of a real value: round to FP32 (nearest even), then keep the top 16
-// bits with round-to-nearest-even on the dropped half.
-__device__ __forceinline__ uint16_t bf16_code(double v) {
-    const float f = (float)v;
-    const uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
-    uint32_t q = u >> 16;
-    const uint32_t rem = u & 0xffffu;
-    if (rem > 0x8000u || (rem == 0x8000u && (q & 1u))) q += 1u;
-    return (uint16_t)q;
-}
-
 // OCP E4M3 code of v: nearest representable value, ties to the even code, |v| >= 448
 // saturating to 448 (the format has no infinities).
 __device__ __forceinline__ uint8_t e4m3_code(float v) {

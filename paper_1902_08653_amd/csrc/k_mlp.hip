@@ -4,6 +4,8 @@
 // MFMA (v_mfma_f32_16x16x16_bf16) with FP32 accumulation; FP32 master weights and
 // Adam state.  The GEMM is generic over strides so that one kernel serves the
 // forward products, the weight gradients (A^T B) and the input gradients (A B^T).
+#include <algorithm>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -248,6 +250,179 @@ hipError_t launch_out_complex(const float* O, void* x, int64_t n, bool c128, hip
     return hipGetLastError();
 }
 
+// ---- fused inference (warm-start prediction) -------------------------------------
+// One launch evaluates the whole network for a tile of MI_R rows, with the same
+// operand rounding as the layered forward pass (BF16 operands, FP32 accumulation):
+//   layer 1 (nin <= 16, VALU): A1 = relu(bf16(X) bf16(W1) + b1), kept as BF16 in LDS;
+//   layer 2 (MFMA 16x16x16): Z2 = A1 bf16(W2) + b2 by column blocks of 64 (one 16-column
+//            slice per wave), B fragments straight from a transposed BF16 copy of W2;
+//   layer 3 in the epilogue of each block: Y += bf16(relu(Z2)) bf16(W3), reduced over the
+//            slice's 16 lanes and kept per wave in LDS; the waves' sums are added in a
+//            fixed order at the end and written as the complex warm start.
+// Only the activations of one tile ever exist, in LDS: nothing but X and x0 touches HBM.
+constexpr int MI_R = 128;      // rows per workgroup
+constexpr int MI_NT = 256;     // 4 waves
+
+// packed inference weights: W1 and W3 as BF16-rounded FP32, W2 transposed as BF16 bits
+__global__ void k_mlp_pack(const float* __restrict__ w, int nin, int hid, int64_t oW1, int64_t oW2, int64_t oW3,
+                           float* __restrict__ w1r, unsigned short* __restrict__ w2t, float* __restrict__ w3r) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t hh = (int64_t)hid * hid;
+    if (i < hh) {
+        const int n = (int)(i / hid), k = (int)(i % hid);   // w2t[n][k] = W2[k][n]
+        w2t[i] = f32_to_bf16(w[oW2 + (int64_t)k * hid + n]);
+    }
+    if (i < (int64_t)nin * hid) w1r[i] = __uint_as_float((uint32_t)f32_to_bf16(w[oW1 + i]) << 16);
+    if (i < (int64_t)hid * 2) w3r[i] = __uint_as_float((uint32_t)f32_to_bf16(w[oW3 + i]) << 16);
+}
+
+template <int HID, typename V>
+__global__ __launch_bounds__(MI_NT) void k_mlp_infer(const float* __restrict__ X, int64_t rows, int nin,
+                                                     const float* __restrict__ w1r, const float* __restrict__ b1,
+                                                     const unsigned short* __restrict__ w2t,
+                                                     const float* __restrict__ b2, const float* __restrict__ w3r,
+                                                     const float* __restrict__ b3, V* __restrict__ x0) {
+    constexpr int LDA = HID + 8;                     // BF16 row stride of A1 (16 B pad: conflict-free b64 reads)
+    extern __shared__ unsigned char smem_raw[];
+    unsigned short* A1 = reinterpret_cast<unsigned short*>(smem_raw);           // [MI_R][LDA]
+    float* xs = reinterpret_cast<float*>(A1 + MI_R * LDA);                      // [MI_R][16] BF16-rounded X
+    float* yp = xs + MI_R * 16;                                                 // [4 waves][MI_R][2]
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * MI_R;
+    // ---- stage X (rows past the end read as 0) and clear the layer-3 partials
+    for (int e = tid; e < MI_R * 16; e += MI_NT) {
+        const int r = e >> 4, k = e & 15;
+        const float v = (k < nin && r0 + r < rows) ? X[(r0 + r) * nin + k] : 0.f;
+        xs[e] = __uint_as_float((uint32_t)f32_to_bf16(v) << 16);
+    }
+    for (int e = tid; e < 4 * MI_R * 2; e += MI_NT) yp[e] = 0.f;
+    __syncthreads();
+    // ---- layer 1: thread t owns columns 2t', 2t'+1 (t' = t, t + 256, ... while < HID/2)
+    for (int cp = tid; cp < HID / 2; cp += MI_NT) {
+        const int c = 2 * cp;
+        float wa[16], wb[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            wa[k] = k < nin ? w1r[(int64_t)k * HID + c] : 0.f;
+            wb[k] = k < nin ? w1r[(int64_t)k * HID + c + 1] : 0.f;
+        }
+        const float ba = b1[c], bb = b1[c + 1];
+        for (int r = 0; r < MI_R; ++r) {
+            float za = 0.f, zb = 0.f;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const float xv = xs[r * 16 + k];
+                za += xv * wa[k];
+                zb += xv * wb[k];
+            }
+            za += ba;
+            zb += bb;
+            const uint32_t pa = f32_to_bf16(za > 0.f ? za : 0.f), pb = f32_to_bf16(zb > 0.f ? zb : 0.f);
+            *reinterpret_cast<uint32_t*>(&A1[r * LDA + c]) = pa | (pb << 16);
+        }
+    }
+    __syncthreads();
+    // ---- layers 2 and 3
+    const int kq = 4 * (lane >> 4);                  // this lane's k offset inside a 16-step
+    float y0[MI_R / 16][4], y1[MI_R / 16][4];        // layer-3 partials of this lane's rows
+#pragma unroll
+    for (int i = 0; i < MI_R / 16; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) y0[i][r] = y1[i][r] = 0.f;
+    for (int nb = 0; nb < HID; nb += 64) {
+        const int col = nb + 16 * wid + (lane & 15);
+        const unsigned short* bsrc = w2t + (int64_t)col * HID + kq;
+        f32x4_t acc[MI_R / 16];
+#pragma unroll
+        for (int i = 0; i < MI_R / 16; ++i) acc[i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        bf16x4_t bn = *reinterpret_cast<const bf16x4_t*>(bsrc);
+        for (int k0 = 0; k0 < HID; k0 += 16) {
+            const bf16x4_t b = bn;
+            if (k0 + 16 < HID) bn = *reinterpret_cast<const bf16x4_t*>(bsrc + k0 + 16);
+#pragma unroll
+            for (int i = 0; i < MI_R / 16; ++i) {
+                const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(&A1[(16 * i + (lane & 15)) * LDA + k0 + kq]);
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i], 0, 0, 0);
+            }
+        }
+        // epilogue: lane holds Z2[16 i + 4 (lane >> 4) + r][col]
+        const float bz = b2[col];
+        const float wo0 = w3r[(int64_t)col * 2], wo1 = w3r[(int64_t)col * 2 + 1];
+#pragma unroll
+        for (int i = 0; i < MI_R / 16; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float z = acc[i][r] + bz;
+                const float a2 = __uint_as_float((uint32_t)f32_to_bf16(z > 0.f ? z : 0.f) << 16);
+                y0[i][r] += a2 * wo0;
+                y1[i][r] += a2 * wo1;
+            }
+    }
+    // sum over the 16 lanes of each row group (the wave's columns), then per wave into LDS
+#pragma unroll
+    for (int i = 0; i < MI_R / 16; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float a = y0[i][r], b = y1[i][r];
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                a += __shfl_xor(a, o);
+                b += __shfl_xor(b, o);
+            }
+            if ((lane & 15) == 0) {
+                const int row = 16 * i + 4 * (lane >> 4) + r;
+                yp[(wid * MI_R + row) * 2 + 0] = a;
+                yp[(wid * MI_R + row) * 2 + 1] = b;
+            }
+        }
+    __syncthreads();
+    if (tid < MI_R && r0 + tid < rows) {
+        float o0 = b3[0], o1 = b3[1];
+        float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            s0 += yp[(w * MI_R + tid) * 2 + 0];
+            s1 += yp[(w * MI_R + tid) * 2 + 1];
+        }
+        V v;
+        v.x = s0 + o0;
+        v.y = s1 + o1;
+        x0[r0 + tid] = v;
+    }
+}
+
+size_t mlp_infer_lds(int hid) { return (size_t)MI_R * (hid + 8) * 2 + (size_t)MI_R * 16 * 4 + 4 * MI_R * 2 * 4; }
+
+// hid in {256, 512}; nin <= 16; nout = 2
+hipError_t launch_mlp_infer(const float* w, int nin, int hid, int64_t oW1, int64_t ob1, int64_t oW2, int64_t ob2,
+                            int64_t oW3, int64_t ob3, float* w1r, unsigned short* w2t, float* w3r, const float* X,
+                            int64_t rows, void* x0, bool c128, hipStream_t st) {
+    const int64_t pk = std::max<int64_t>((int64_t)hid * hid, (int64_t)nin * hid);
+    hipLaunchKernelGGL(k_mlp_pack, dim3((unsigned)((pk + 255) / 256)), dim3(256), 0, st, w, nin, hid, oW1, oW2, oW3,
+                       w1r, w2t, w3r);
+    const size_t lds = mlp_infer_lds(hid);
+    const dim3 grid((unsigned)((rows + MI_R - 1) / MI_R));
+#define CDM_MI_LAUNCH(H_, V_)                                                                                     \
+    do {                                                                                                         \
+        hipError_t e_ = hipFuncSetAttribute((const void*)k_mlp_infer<H_, V_>,                                    \
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);               \
+        if (e_ != hipSuccess) return e_;                                                                         \
+        hipLaunchKernelGGL((k_mlp_infer<H_, V_>), grid, dim3(MI_NT), lds, st, X, rows, nin, w1r, w + ob1, w2t,   \
+                           w + ob2, w3r, w + ob3, (V_*)x0);                                                      \
+    } while (0)
+    if (hid == 512) {
+        if (c128) CDM_MI_LAUNCH(512, double2);
+        else CDM_MI_LAUNCH(512, float2);
+    } else if (hid == 256) {
+        if (c128) CDM_MI_LAUNCH(256, double2);
+        else CDM_MI_LAUNCH(256, float2);
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef CDM_MI_LAUNCH
+    return hipGetLastError();
+}
+
 }  // namespace cdm
 
 // ============================================================================
@@ -259,6 +434,9 @@ struct Mlp {
     int64_t nparam;
     float *w = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;
     float *Z1, *A1, *Z2, *A2, *O, *dO, *dA2, *dZ2, *dA1, *dZ1, *part;
+    float *w1r = nullptr, *w3r = nullptr;     // fused inference: BF16-rounded W1, W3
+    unsigned short* w2t = nullptr;            // and W2 transposed as BF16
+    bool fused = false;                       // shape served by k_mlp_infer
     void* ws = nullptr;
     int64_t step = 0;
     // parameter block offsets: W1 b1 W2 b2 W3 b3
@@ -340,7 +518,10 @@ int32_t cdm_mlp_create(int32_t nin, int32_t h1, int32_t h2, int32_t nout, int32_
     n->ob3 = n->oW3 + (int64_t)h2 * nout;
     n->nparam = n->ob3 + nout;
     const int64_t R = max_rows;
-    const int64_t fl = 4 * n->nparam + R * (4 * (int64_t)h1 + 4 * (int64_t)h2 + 2 * nout) + (R * nout + 255) / 256 + 64;
+    n->fused = nin <= 16 && h1 == h2 && (h1 == 256 || h1 == 512) && nout == 2;
+    // fused inference weights: nin*h1 + 2*h2 floats and h1*h2 BF16 (as floats: half of it)
+    const int64_t fw = n->fused ? (int64_t)nin * h1 + 2 * (int64_t)h2 + ((int64_t)h1 * h2 + 1) / 2 + 64 : 0;
+    const int64_t fl = 4 * n->nparam + R * (4 * (int64_t)h1 + 4 * (int64_t)h2 + 2 * nout) + (R * nout + 255) / 256 + 64 + fw;
     if (hipMalloc(&n->ws, sizeof(float) * fl) != hipSuccess) {
         delete n;
         return CDM_ENOMEM;
@@ -360,7 +541,12 @@ int32_t cdm_mlp_create(int32_t nin, int32_t h1, int32_t h2, int32_t nout, int32_
     n->dZ2 = p; p += R * h2;
     n->O = p; p += R * nout;
     n->dO = p; p += R * nout;
-    n->part = p;
+    n->part = p; p += (R * nout + 255) / 256 + 64;
+    if (n->fused) {
+        n->w1r = p; p += (int64_t)nin * h1;
+        n->w3r = p; p += 2 * (int64_t)h2 + 64;
+        n->w2t = reinterpret_cast<unsigned short*>(p);
+    }
     if (hipMemset(n->m1, 0, sizeof(float) * 2 * n->nparam) != hipSuccess) {
         (void)hipFree(n->ws);
         delete n;
@@ -425,6 +611,11 @@ int32_t cdm_mlp_predict(cdm_mlp* n, const float* X, int64_t rows, void* x0, int3
     hipStream_t st = (hipStream_t)stream;
     const bool c128 = precision == CDM_C128;
     const size_t esz = c128 ? 16 : 8;
+    if (n->fused) {   // one launch, activations in LDS only
+        MLP_TRY(launch_mlp_infer(n->w, n->nin, n->h1, n->oW1, n->ob1, n->oW2, n->ob2, n->oW3, n->ob3, n->w1r, n->w2t,
+                                 n->w3r, X, rows, x0, c128, st));
+        return CDM_OK;
+    }
     for (int64_t r0 = 0; r0 < rows; r0 += n->max_rows) {
         const int cnt = (int)std::min<int64_t>(n->max_rows, rows - r0);
         MLP_TRY(mlp_forward(n, X + r0 * n->nin, cnt, st));

@@ -12,6 +12,7 @@
 // (m_u, n_u) live in LDS.
 #include "common.hpp"
 #include "launch.hpp"
+#include "wg.hpp"
 
 namespace cdm {
 
@@ -151,76 +152,8 @@ __device__ __forceinline__ void cd_instance(const WgJob& jb, const cv<T>* __rest
         }
         if (nf) atomicOr(&flag_s, CDM_INFO_NONFINITE);
         __syncthreads();
-        // optional FP64 check of the stationarity of eq. (1):
-        //   ||H^H (y - H x) - lambda x|| / ||H^H y||, with r = y - H x formed in FP64
-        double res = -1.0;
-        if (resid) {
-            const double lam64 = lambda_d;   // the caller's lambda, not its rounding to T
-            double2 r64[RPT];
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                const int i = tid + q * NT;
-                const V yv = (i < m) ? Y[jb.y_off + i] : czero<T>();
-                r64[q] = make_double2((double)yv.x, (double)yv.y);
-            }
-            for (int u = 0; u < n; ++u) {
-                const V xv = x_s[u];
-                const double xr = xv.x, xi = xv.y;
-#pragma unroll
-                for (int q = 0; q < RPT; ++q) {
-                    const int i = tid + q * NT;
-                    if (i < m) {
-                        const V h = Hj[(int64_t)u * ld + i];
-                        r64[q].x -= (double)h.x * xr - (double)h.y * xi;
-                        r64[q].y -= (double)h.x * xi + (double)h.y * xr;
-                    }
-                }
-            }
-            double A2 = 0.0, B2 = 0.0;
-            for (int u = 0; u < n; ++u) {
-                double ar = 0, ai = 0, br = 0, bi = 0;
-#pragma unroll
-                for (int q = 0; q < RPT; ++q) {
-                    const int i = tid + q * NT;
-                    if (i < m) {
-                        const V h = Hj[(int64_t)u * ld + i];
-                        const V yv = Y[jb.y_off + i];
-                        const double hr = h.x, hi = h.y;
-                        ar += hr * r64[q].x + hi * r64[q].y;
-                        ai += hr * r64[q].y - hi * r64[q].x;
-                        br += hr * (double)yv.x + hi * (double)yv.y;
-                        bi += hr * (double)yv.y - hi * (double)yv.x;
-                    }
-                }
-                ar = wave_allsum(ar);
-                ai = wave_allsum(ai);
-                br = wave_allsum(br);
-                bi = wave_allsum(bi);
-                const int par = u & 1;
-                if (lane == 0) {
-                    red64[par][wid][0] = ar;
-                    red64[par][wid][1] = ai;
-                    red64[par][wid][2] = br;
-                    red64[par][wid][3] = bi;
-                }
-                __syncthreads();
-                double sa = 0, sb = 0, sc = 0, sd = 0;
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    sa += red64[par][w][0];
-                    sb += red64[par][w][1];
-                    sc += red64[par][w][2];
-                    sd += red64[par][w][3];
-                }
-                const V xv = x_s[u];
-                sa -= lam64 * (double)xv.x;
-                sb -= lam64 * (double)xv.y;
-                A2 += sa * sa + sb * sb;
-                B2 += sc * sc + sd * sd;
-            }
-            res = B2 > 0.0 ? sqrt(A2 / B2) : sqrt(A2);
-            __syncthreads();
-        }
+        // optional FP64 check of the stationarity of eq. (1)
+        const double res = resid ? wg_fp64_resid<T, NT, RPT>(Hj, ld, Y + jb.y_off, x_s, m, n, lambda_d, red64) : -1.0;
         if (tid == 0) {
             const double rel = (Xn > 0.0) ? sqrt(S / Xn) : (S > 0.0 ? INFINITY : 0.0);
             int fl = flag_s;

@@ -48,6 +48,42 @@ hipError_t launch_wg(const WgLaunch& L, hipStream_t st);
 // Algorithm 2 (downlink ZF precoding), same job and tile conventions; Y is s (U).
 hipError_t launch_zf(const WgLaunch& L, hipStream_t st);
 size_t wg_lds_bytes(int n_max, bool c128);
+// Mixed-precision refinement of an uneven batch (complex128 H, y, x): per outer step
+// an FP64 residual pass, an FP64 gradient pass (first step: also the low-precision
+// copy Hq and the inner scalars) and the persistent inner-sweep launch.
+enum WgLowKind { WG_LOW_NONE = 0, WG_LOW_C64 = 1, WG_LOW_BF16 = 2 };
+struct BmLaunch {
+    int low;              // WG_LOW_C64 or WG_LOW_BF16: format of Hq
+    int nt;               // threads per workgroup of the inner launch (128, 256, 512)
+    int grid;             // its persistent workgroups
+    int n_max;            // largest n (sizes its LDS)
+    const WgJob* jobs;    // by job id (rpt set for nt)
+    int njobs;
+    const int* order;     // queue slot -> job id
+    uint32_t* queue;      // queue counter (cleared per step)
+    const int64_t* x_off; // device packed x offsets by job id
+    int64_t total_n;
+    const void* H;
+    const void* Y;
+    const void* X0;       // optional warm start
+    void* X;              // iterate / output
+    void* Hq;             // low-precision copy, packed like H
+    void* R;              // FP64 residual, packed like y
+    void* G;              // FP32 inner bias, packed like x
+    void* CF;             // FP32 (m~, n~), packed like x
+    uint32_t* done;       // per job
+    cdm_info* info;
+    double lambda;
+    double tol;
+    int inner_max;
+    double tau;
+};
+hipError_t launch_bm_init(const BmLaunch& L, hipStream_t st);
+hipError_t launch_bm_step(const BmLaunch& L, int step, int last, hipStream_t st);
+hipError_t launch_bm_resid_check(const BmLaunch& L, hipStream_t st);
+size_t bm_lds_bytes(int n_max);
+hipError_t bm_set_lds_limit(int low, int nt, size_t bytes);
+int bm_occupancy(int low, int nt, size_t bytes);
 hipError_t wg_set_lds_limit(bool c128, int nt, size_t bytes);
 int wg_occupancy(bool c128, int nt, size_t bytes);
 

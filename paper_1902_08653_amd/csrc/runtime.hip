@@ -34,6 +34,10 @@ void set_err(const char* where, hipError_t e) {
     } while (0)
 
 constexpr int kWgMaxRows = 8192;      // 1024 threads x 8 rows
+constexpr int kWgMixedMaxRows = 2048; // mixed-precision batched path: 256 threads x 8 rows
+constexpr int kWgMixedInnerMax = 64;  // inner sweeps per outer step at most
+constexpr double kWgMixedTauC64 = 1e-5;   // inner stop ||delta|| <= tau ||d||: complex64 copy
+constexpr double kWgMixedTauBf16 = 3e-2;  // BF16 copy (its rounding bounds the outer gain per step)
 constexpr int kCtrWords = 2048;       // control words: counters, abort/status, arrival flags
 constexpr size_t kLdsMax = 160 * 1024;
 
@@ -61,6 +65,14 @@ struct cdm_plan {
     // WG engine
     int wg_nt = 256, wg_rpt = 1, wg_grid = 1, n_max = 1;   // wg_rpt: rows per thread of the largest job
     size_t wg_lds = 0;
+    int wg_low = WG_LOW_NONE; // batched mixed precision: format of the inner copy
+    void* wg_hq = nullptr;    // the inner copy (packed like H)
+    int wg_inner_max = 0;
+    double wg_tau = 0.0;
+    void* bm_R = nullptr;     // FP64 residuals (packed like y)
+    void* bm_G = nullptr;     // inner biases (packed like x)
+    void* bm_CF = nullptr;    // inner scalars (packed like x)
+    uint32_t* bm_done = nullptr;
     int njobs = 0;
     // PANEL engine
     int kp = 128, rpl = 1, P = 1, npanels = 1, nsplit = 1;
@@ -133,7 +145,7 @@ static int32_t setup_timing(cdm_plan* p) {
 static int32_t validate_common(const cdm_desc* d) {
     if (!d) return CDM_EINVAL;
     if (d->problem != CDM_UPLINK_LMMSE && d->problem != CDM_DOWNLINK_ZF) return CDM_EDTYPE;
-    if (d->precision < CDM_C128 || d->precision > CDM_MIXED_FP8) return CDM_EDTYPE;
+    if (d->precision < CDM_C128 || d->precision > CDM_MIXED_C64) return CDM_EDTYPE;
     if (d->layout != CDM_DENSE && d->layout != CDM_CSR) return CDM_EDTYPE;
     if (d->engine < CDM_ENGINE_AUTO || d->engine > CDM_ENGINE_PANEL) return CDM_EINVAL;
     if (d->T_max < 1 || d->T_max > 100000) return CDM_EINVAL;
@@ -168,9 +180,10 @@ static int32_t alloc_ws(cdm_plan* p, size_t bytes) {
     return CDM_OK;
 }
 
-// rows per thread for an instance of m rows on nt threads (0: too large)
-static int rpt_for(int m, int nt) {
-    for (int r = 1; r <= 8; r *= 2)
+// rows per thread for an instance of m rows on nt threads (0: too large); the
+// mixed-precision kernel takes at most 4
+static int rpt_for(int m, int nt, int cap = 8) {
+    for (int r = 1; r <= cap; r *= 2)
         if ((int64_t)nt * r >= m) return r;
     return 0;
 }
@@ -180,16 +193,20 @@ static int rpt_for(int m, int nt) {
 static int wg_nt_single(int m, bool c128) { return m <= 2048 ? 256 : (c128 ? 512 : 1024); }
 
 static int32_t setup_wg(cdm_plan* p, int m_max, int n_max, int njobs, int nt) {
-    if (rpt_for(m_max, nt) == 0) return CDM_ESHAPE;
+    const int cap = 8;
+    if (rpt_for(m_max, nt, cap) == 0) return CDM_ESHAPE;
     p->wg_nt = nt;
-    p->wg_rpt = rpt_for(m_max, nt);
+    p->wg_rpt = rpt_for(m_max, nt, cap);
     p->n_max = std::max(1, n_max);
-    p->wg_lds = wg_lds_bytes(p->n_max, p->c128);
+    p->wg_lds = p->wg_low ? bm_lds_bytes(p->n_max) : wg_lds_bytes(p->n_max, p->c128);
     if (p->wg_lds + 2048 > kLdsMax) return CDM_ESHAPE;
     if (p->wg_lds > 64 * 1024) {
-        if (wg_set_lds_limit(p->c128, nt, p->wg_lds) != hipSuccess) return CDM_ESHAPE;
+        const hipError_t e = p->wg_low ? bm_set_lds_limit(p->wg_low, nt, p->wg_lds)
+                                       : wg_set_lds_limit(p->c128, nt, p->wg_lds);
+        if (e != hipSuccess) return CDM_ESHAPE;
     }
-    const int occ = std::max(1, wg_occupancy(p->c128, nt, p->wg_lds));
+    const int occ = std::max(1, p->wg_low ? bm_occupancy(p->wg_low, nt, p->wg_lds)
+                                          : wg_occupancy(p->c128, nt, p->wg_lds));
     p->wg_grid = std::max(1, std::min(njobs, occ * p->ncu));
     p->njobs = njobs;
     return CDM_OK;
@@ -435,6 +452,7 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
     if (d.B < 1 || d.U < 1 || d.C < 1 || d.B % d.C) return CDM_ESHAPE;
     const int Bc = d.B / d.C;
     if (d.problem == CDM_DOWNLINK_ZF && Bc < d.U) return CDM_EINFEASIBLE;
+    if (d.precision == CDM_MIXED_C64) return CDM_ENOTIMPL;   // batched plans only
     const bool mixed = d.precision == CDM_MIXED_BF16 || d.precision == CDM_MIXED_FP8;
     if (mixed && (d.problem != CDM_UPLINK_LMMSE || d.layout != CDM_DENSE || d.C != 1)) return CDM_ENOTIMPL;
     if (mixed && !(d.tol > 0.0)) return CDM_EINVAL;
@@ -881,14 +899,17 @@ int32_t cdm_residual(cdm_plan* p, const void* H, int64_t ldh, const void* y, dou
 // Time one persistent launch of the batched engine with nt threads per workgroup
 // on `jobs` (device), 2 fixed sweeps; returns milliseconds (< 0 on failure).
 static double time_batched(cdm_plan* p, int nt, int m_max, int n_max, WgJob* jobs_d, const std::vector<WgJob>& jobs,
-                           int* order_d, void* H, void* Y, void* X, cdm_info* info, uint32_t* ctr) {
+                           int* order_d, void* H, void* Y, void* X, cdm_info* info, uint32_t* ctr, void* Hq,
+                           void* mscratch) {
     const int njobs = (int)jobs.size();
     std::vector<WgJob> jj = jobs;
     for (auto& j : jj) j.rpt = rpt_for(j.m, nt);
     if (hipMemcpy(jobs_d, jj.data(), sizeof(WgJob) * njobs, hipMemcpyHostToDevice) != hipSuccess) return -1.0;
-    const size_t lds = wg_lds_bytes(std::max(1, n_max), p->c128);
-    if (lds > 64 * 1024 && wg_set_lds_limit(p->c128, nt, lds) != hipSuccess) return -1.0;
-    const int occ = std::max(1, wg_occupancy(p->c128, nt, lds));
+    const bool mx = p->wg_low != WG_LOW_NONE;
+    const size_t lds = mx ? bm_lds_bytes(std::max(1, n_max)) : wg_lds_bytes(std::max(1, n_max), p->c128);
+    if (lds > 64 * 1024 && (mx ? bm_set_lds_limit(p->wg_low, nt, lds) : wg_set_lds_limit(p->c128, nt, lds)) != hipSuccess)
+        return -1.0;
+    const int occ = std::max(1, mx ? bm_occupancy(p->wg_low, nt, lds) : wg_occupancy(p->c128, nt, lds));
     WgLaunch L;
     L.c128 = p->c128;
     L.nt = nt;
@@ -910,6 +931,37 @@ static double time_batched(cdm_plan* p, int nt, int m_max, int n_max, WgJob* job
     L.ld = 1;
     L.rho_c = 0.0;
     L.resid = 0;
+    // mixed: one cold outer step with a fixed count of inner sweeps (tol = tau = 0);
+    // its buffers follow the sample's own packing (scratch holds R, G, CF, done)
+    BmLaunch M{};
+    if (mx) {
+        const int64_t sy = jobs.back().y_off + jobs.back().m, sx = jobs.back().x_off + jobs.back().n;
+        char* sc = (char*)mscratch;
+        M.low = p->wg_low;
+        M.nt = nt;
+        M.grid = L.grid;
+        M.n_max = L.n_max;
+        M.jobs = jobs_d;
+        M.njobs = njobs;
+        M.order = order_d;
+        M.queue = ctr + 4;
+        M.x_off = (const int64_t*)sc;
+        M.total_n = sx;
+        M.H = H;
+        M.Y = Y;
+        M.X0 = nullptr;
+        M.X = X;
+        M.Hq = Hq;
+        M.R = sc + align256(8 * (size_t)njobs);
+        M.G = (char*)M.R + align256(16 * (size_t)sy);
+        M.CF = (char*)M.G + align256(8 * (size_t)sx);
+        M.done = (uint32_t*)((char*)M.CF + align256(8 * (size_t)sx));
+        M.info = info;
+        M.lambda = 0.1;
+        M.tol = 0.0;
+        M.inner_max = 8;
+        M.tau = 0.0;
+    }
     (void)m_max;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return -1.0;
@@ -921,7 +973,10 @@ static double time_batched(cdm_plan* p, int nt, int m_max, int n_max, WgJob* job
     for (int rep = 0; rep < 3; ++rep) {
         if (launch_zero_u32(ctr, 16, nullptr) != hipSuccess) break;
         (void)hipEventRecord(e0, nullptr);
-        if (launch_wg(L, nullptr) != hipSuccess) break;
+        const hipError_t le = mx ? (launch_bm_init(M, nullptr) == hipSuccess ? launch_bm_step(M, 1, 0, nullptr)
+                                                                              : hipErrorUnknown)
+                                 : launch_wg(L, nullptr);
+        if (le != hipSuccess) break;
         (void)hipEventRecord(e1, nullptr);
         if (hipEventSynchronize(e1) != hipSuccess) break;
         float ms = 0.f;
@@ -941,20 +996,28 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
     if (st) return st;
     if (batch < 1 || !m || !n) return CDM_EINVAL;
     const cdm_desc& d = *desc;
+    const int low = d.precision == CDM_MIXED_C64 ? WG_LOW_C64 : (d.precision == CDM_MIXED_BF16 ? WG_LOW_BF16 : 0);
     if (d.problem != CDM_UPLINK_LMMSE || d.layout != CDM_DENSE ||
-        (d.precision != CDM_C128 && d.precision != CDM_C64))
+        (d.precision != CDM_C128 && d.precision != CDM_C64 && !low))
         return CDM_ENOTIMPL;
+    if (low && !(d.tol > 0.0)) return CDM_EINVAL;
+    const int rows_cap = low ? kWgMixedMaxRows : kWgMaxRows;
     int m_max = 0, n_max = 0;
+    int64_t total_mn = 0;
     for (int i = 0; i < batch; ++i) {
-        if (m[i] < 1 || n[i] < 1 || m[i] > kWgMaxRows) return CDM_ESHAPE;
+        if (m[i] < 1 || n[i] < 1 || m[i] > rows_cap) return CDM_ESHAPE;
         m_max = std::max(m_max, m[i]);
         n_max = std::max(n_max, n[i]);
+        total_mn += (int64_t)m[i] * n[i];
     }
     cdm_plan* p = new cdm_plan();
     p->d = d;
     p->batched = true;
-    p->c128 = d.precision == CDM_C128;
+    p->c128 = d.precision != CDM_C64;   // mixed plans keep H, y and x in complex128
     p->esz = p->c128 ? 16 : 8;
+    p->wg_low = low;
+    p->wg_inner_max = kWgMixedInnerMax;
+    p->wg_tau = low == WG_LOW_BF16 ? kWgMixedTauBf16 : kWgMixedTauC64;
     st = device_setup(p);
     if (st) {
         delete p;
@@ -996,6 +1059,14 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
     const size_t o_jobs = ar.take(sizeof(WgJob) * batch);
     const size_t o_order = ar.take(sizeof(int) * batch);
     const size_t o_xoff = ar.take(sizeof(int64_t) * batch);
+    const size_t lowsz = low == WG_LOW_C64 ? 8 : 4;
+    const size_t o_hq = low ? ar.take(lowsz * (size_t)total_mn) : 0;
+    int64_t total_m = 0;
+    for (int i = 0; i < batch; ++i) total_m += m[i];
+    const size_t o_R = low ? ar.take(16 * (size_t)total_m) : 0;
+    const size_t o_G = low ? ar.take(8 * (size_t)xo) : 0;
+    const size_t o_CF = low ? ar.take(8 * (size_t)xo) : 0;
+    const size_t o_done = low ? ar.take(4 * (size_t)batch) : 0;
     st = alloc_ws(p, ar.off);
     if (st) {
         delete p;
@@ -1005,6 +1076,13 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
     p->jobs = (WgJob*)(p->ws + o_jobs);
     p->order = (int*)(p->ws + o_order);
     p->xoff_dev = (int64_t*)(p->ws + o_xoff);
+    if (low) {
+        p->wg_hq = p->ws + o_hq;
+        p->bm_R = p->ws + o_R;
+        p->bm_G = p->ws + o_G;
+        p->bm_CF = p->ws + o_CF;
+        p->bm_done = (uint32_t*)(p->ws + o_done);
+    }
     if (hipMemcpy(p->xoff_dev, p->x_off.data(), sizeof(int64_t) * batch, hipMemcpyHostToDevice) != hipSuccess) {
         cdm_destroy(p);
         return CDM_EHIP;
@@ -1013,7 +1091,7 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
     // ---- tile choice: threads per workgroup for the whole launch; rows per
     // thread then follow per job.  With CDM_F_AUTOTUNE each candidate is timed
     // on a spread sample of this batch's shapes (synthetic values).
-    static const int cands[3] = {128, 256, 512};
+    static const int cands[3] = {128, 256, 512};   // the mixed kernel is built for these three
     int nt = 0;
     std::string tune = "null";
     if (d.flags & CDM_F_AUTOTUNE) {
@@ -1039,9 +1117,14 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
             sm_max = std::max(sm_max, j.m);
             sn_max = std::max(sn_max, j.n);
         }
-        void *Hs = nullptr, *Ys = nullptr, *Xs = nullptr, *aux = nullptr;
+        void *Hs = nullptr, *Ys = nullptr, *Xs = nullptr, *aux = nullptr, *Hqs = nullptr, *Ms = nullptr;
+        // mixed: packed x offsets, then R, G, CF and done flags of the sample
+        const size_t ms_bytes = align256(8 * (size_t)S) + align256(16 * (size_t)sy) + 2 * align256(8 * (size_t)sx) +
+                                align256(4 * (size_t)S);
         bool ok = hipMalloc(&Hs, p->esz * (size_t)sh) == hipSuccess && hipMalloc(&Ys, p->esz * (size_t)sy) == hipSuccess &&
                   hipMalloc(&Xs, p->esz * (size_t)sx) == hipSuccess &&
+                  (!low || (hipMalloc(&Hqs, lowsz * (size_t)sh) == hipSuccess &&
+                            hipMalloc(&Ms, ms_bytes) == hipSuccess)) &&
                   hipMalloc(&aux, 64 + sizeof(cdm_info) * S + sizeof(WgJob) * S + sizeof(int) * S) == hipSuccess;
         if (ok) {
             uint32_t* tctr = (uint32_t*)aux;
@@ -1051,12 +1134,18 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
             ok = hipMemcpy(tord, sorder.data(), sizeof(int) * S, hipMemcpyHostToDevice) == hipSuccess &&
                  launch_fill_hash(Hs, (int64_t)sh * 2, p->c128, 0x9e3779b9u, 1.0 / std::sqrt((double)sm_max)) == hipSuccess &&
                  launch_fill_hash(Ys, (int64_t)sy * 2, p->c128, 0x7f4a7c15u, 1.0) == hipSuccess;
+            if (ok && Ms) {
+                std::vector<int64_t> sxo(S);
+                for (int k = 0; k < S; ++k) sxo[k] = sj[k].x_off;
+                ok = hipMemcpy(Ms, sxo.data(), sizeof(int64_t) * S, hipMemcpyHostToDevice) == hipSuccess;
+            }
             double best = -1.0;
             char tb[256];
             int tl = snprintf(tb, sizeof(tb), "{");
             for (int c = 0; ok && c < 3; ++c) {
                 if (rpt_for(m_max, cands[c]) == 0) continue;
-                const double ms = time_batched(p, cands[c], sm_max, sn_max, tjobs, sj, tord, Hs, Ys, Xs, tinfo, tctr);
+                const double ms = time_batched(p, cands[c], sm_max, sn_max, tjobs, sj, tord, Hs, Ys, Xs, tinfo, tctr, Hqs,
+                                               Ms);
                 tl += snprintf(tb + tl, sizeof(tb) - tl, "%s\"%d\": %.3f", tl > 1 ? ", " : "", cands[c], ms);
                 if (ms > 0 && (best < 0 || ms < best)) {
                     best = ms;
@@ -1070,6 +1159,8 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
         if (Ys) (void)hipFree(Ys);
         if (Xs) (void)hipFree(Xs);
         if (aux) (void)hipFree(aux);
+        if (Hqs) (void)hipFree(Hqs);
+        if (Ms) (void)hipFree(Ms);
         (void)hipGetLastError();
     }
     if (nt == 0) nt = rpt_for(m_max, 256) ? 256 : (rpt_for(m_max, 512) ? 512 : 1024);
@@ -1085,11 +1176,16 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
         return CDM_EHIP;
     }
     char buf[768];
+    const char* pname = low == WG_LOW_C64 ? "mixed-c64" : (low == WG_LOW_BF16 ? "mixed-bf16" : (p->c128 ? "c128" : "c64"));
+    char mx[160] = "";
+    if (low)
+        snprintf(mx, sizeof(mx), ", \"inner_max\": %d, \"inner_tau\": %g, \"inner_copy_bytes\": %zu",
+                 p->wg_inner_max, p->wg_tau, lowsz * (size_t)total_mn);
     snprintf(buf, sizeof(buf),
-             "{\"engine\": \"wg-batched\", \"precision\": \"%s\", \"batch\": %d, \"m_max\": %d, \"n_max\": %d, "
-             "\"nt\": %d, \"grid\": %d, \"lds\": %zu, \"workspace\": %zu, \"autotune_ms\": %s}",
-             p->c128 ? "c128" : "c64", batch, m_max, n_max, p->wg_nt, p->wg_grid, p->wg_lds, p->ws_bytes,
-             tune.c_str());
+             "{\"engine\": \"%s\", \"precision\": \"%s\", \"batch\": %d, \"m_max\": %d, \"n_max\": %d, "
+             "\"nt\": %d, \"grid\": %d, \"lds\": %zu, \"workspace\": %zu, \"autotune_ms\": %s%s}",
+             low ? "wg-batched-mixed" : "wg-batched", pname, batch, m_max, n_max, p->wg_nt, p->wg_grid, p->wg_lds,
+             p->ws_bytes, tune.c_str(), mx);
     p->text = buf;
     *plan = p;
     return CDM_OK;
@@ -1131,7 +1227,38 @@ int32_t cdm_solve_batched(cdm_plan* p, const void* H, const void* y, double N0, 
     L.ld = 1;
     L.rho_c = 0.0;
     L.resid = (p->d.flags & CDM_F_RESIDUAL) ? 1 : 0;
-    HIP_TRY(launch_wg(L, st));
+    if (p->wg_low) {
+        BmLaunch M{};
+        M.low = p->wg_low;
+        M.nt = p->wg_nt;
+        M.grid = p->wg_grid;
+        M.n_max = p->n_max;
+        M.jobs = p->jobs;
+        M.njobs = p->njobs;
+        M.order = p->order;
+        M.queue = p->ctr + 4;
+        M.x_off = p->xoff_dev;
+        M.total_n = p->total_n;
+        M.H = H;
+        M.Y = y;
+        M.X0 = x0;
+        M.X = x;
+        M.Hq = p->wg_hq;
+        M.R = p->bm_R;
+        M.G = p->bm_G;
+        M.CF = p->bm_CF;
+        M.done = p->bm_done;
+        M.info = (cdm_info*)info;
+        M.lambda = N0 / Ex;
+        M.tol = p->d.tol;
+        M.inner_max = p->wg_inner_max;
+        M.tau = p->wg_tau;
+        HIP_TRY(launch_bm_init(M, st));
+        for (int s = 1; s <= p->d.T_max; ++s) HIP_TRY(launch_bm_step(M, s, s == p->d.T_max, st));
+        if (L.resid) HIP_TRY(launch_bm_resid_check(M, st));
+    } else {
+        HIP_TRY(launch_wg(L, st));
+    }
     return CDM_OK;
 }
 

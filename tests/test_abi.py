@@ -84,6 +84,26 @@ def test_null_arguments(lib):
                                   C.byref(C.c_void_p())) == -1
 
 
+@pytest.mark.parametrize("kw,status", [
+    (dict(precision=4, tol=0.0), -1),            # mixed refinement needs a tolerance
+    (dict(precision=3, tol=1e-8), -7),           # FP8 inner copy: single solves only
+    (dict(precision=2, tol=1e-8, problem=1), -7),
+])
+def test_create_batched_rejects_on_the_host(lib, kw, status):
+    m = np.array([64, 100], np.int32)
+    n = np.array([32, 50], np.int32)
+    h = C.c_void_p(1)
+    st = lib.cdm_create_batched(C.byref(_desc(**kw)), 2, m.ctypes.data, n.ctypes.data, C.byref(h))
+    assert st == status
+    assert h.value is None
+
+
+def test_mixed_c64_is_batched_only(lib):
+    h = C.c_void_p(1)
+    assert lib.cdm_create(C.byref(_desc(precision=4, tol=1e-8)), C.byref(h)) == -7
+    assert h.value is None
+
+
 def test_info_record_layout():
     from paper_1902_08653_amd import cdm
     assert cdm.INFO_DTYPE.itemsize == 32
