@@ -36,11 +36,25 @@ __device__ __forceinline__ void cd_instance(const WgJob& jb, const cv<T>* __rest
         V* x_s = reinterpret_cast<V*>(smem_raw);
         V* cf_s = x_s + n;   // (m_u, n_u) of Algorithm 1
 
-        V r[RPT];
+        // rows past m load row m - 1 (in bounds) and are zeroed by a select, so that
+        // no load sits behind a branch; column bases stay wave-uniform
+        uint32_t rowc[RPT];
+        bool live[RPT];
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int i = tid + q * NT;
-            r[q] = (i < m) ? Y[jb.y_off + i] : czero<T>();
+            live[q] = i < m;
+            rowc[q] = (uint32_t)(live[q] ? i : m - 1) * (uint32_t)sizeof(V);
+        }
+        auto col = [&](int u, int q) -> V {
+            const V v = *reinterpret_cast<const V*>(reinterpret_cast<const char*>(Hj + (int64_t)u * ld) + rowc[q]);
+            return live[q] ? v : czero<T>();
+        };
+        V r[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const V v = *reinterpret_cast<const V*>(reinterpret_cast<const char*>(Y + jb.y_off) + rowc[q]);
+            r[q] = live[q] ? v : czero<T>();
         }
         for (int u = tid; u < n; u += NT) x_s[u] = X0 ? X0[jb.x0_off + u] : czero<T>();
         __syncthreads();
@@ -48,10 +62,7 @@ __device__ __forceinline__ void cd_instance(const WgJob& jb, const cv<T>* __rest
             for (int u = 0; u < n; ++u) {
                 const V xu = x_s[u];
 #pragma unroll
-                for (int q = 0; q < RPT; ++q) {
-                    const int i = tid + q * NT;
-                    if (i < m) cfms(r[q], Hj[u * ld + i], xu);
-                }
+                for (int q = 0; q < RPT; ++q) cfms(r[q], col(u, q), xu);
             }
         }
 
@@ -62,17 +73,11 @@ __device__ __forceinline__ void cd_instance(const WgJob& jb, const cv<T>* __rest
             Xn = 0.0;
             V hc[RPT], hn[RPT];
 #pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                const int i = tid + q * NT;
-                hc[q] = (i < m) ? Hj[i] : czero<T>();
-            }
+            for (int q = 0; q < RPT; ++q) hc[q] = col(0, q);
             for (int u = 0; u < n; ++u) {
                 if (u + 1 < n) {
 #pragma unroll
-                    for (int q = 0; q < RPT; ++q) {
-                        const int i = tid + q * NT;
-                        hn[q] = (i < m) ? Hj[(int64_t)(u + 1) * ld + i] : czero<T>();
-                    }
+                    for (int q = 0; q < RPT; ++q) hn[q] = col(u + 1, q);
                 }
                 T gr = 0, gi = 0, ee = 0;
 #pragma unroll
@@ -81,14 +86,14 @@ __device__ __forceinline__ void cd_instance(const WgJob& jb, const cv<T>* __rest
                     gi += hc[q].x * r[q].y - hc[q].y * r[q].x;
                     if (t == 1) ee += hc[q].x * hc[q].x + hc[q].y * hc[q].y;
                 }
-                gr = wave_allsum(gr);
-                gi = wave_allsum(gi);
-                if (t == 1) ee = wave_allsum(ee);
+                gr = wave_sum_last(gr);
+                gi = wave_sum_last(gi);
+                if (t == 1) ee = wave_sum_last(ee);
                 // read x_u and the scalars before the barrier: thread 0 overwrites them after it
                 const V xu = x_s[u];
                 V cf = (t > 1) ? cf_s[u] : czero<T>();
                 const int par = u & 1;
-                if (lane == 0) {
+                if (lane == 63) {
                     red_s[par][wid][0] = gr;
                     red_s[par][wid][1] = gi;
                     red_s[par][wid][2] = ee;
@@ -168,7 +173,10 @@ __device__ __forceinline__ void cd_instance(const WgJob& jb, const cv<T>* __rest
         }
 }
 
-template <typename T, int NT>
+// RMAX: the largest rows-per-thread tile the launch needs (4 or 8).  Only tiles up to
+// RMAX are compiled into the instance, so a launch whose instances fit 4 rows per
+// thread is not held to the register footprint of the 8-row tile.
+template <typename T, int NT, int RMAX>
 __global__ __launch_bounds__(NT) void k_cd_wg(const WgJob* __restrict__ jobs, int njobs,
                                               const cv<T>* __restrict__ H, const cv<T>* __restrict__ Y,
                                               const cv<T>* __restrict__ X0, cv<T>* __restrict__ X,
@@ -192,16 +200,19 @@ __global__ __launch_bounds__(NT) void k_cd_wg(const WgJob* __restrict__ jobs, in
             flag_s = 0;
         }
         __syncthreads();
-        const int jslot = job_s;
+        // wave-uniform job index: the job record and the column bases stay scalar
+        const int jslot = __builtin_amdgcn_readfirstlane(job_s);
         if (jslot >= njobs) return;
-        const WgJob jb = jobs[order ? order[jslot] : jslot];
+        const WgJob jb = jobs[order ? __builtin_amdgcn_readfirstlane(order[jslot]) : jslot];
         // row tile of this job, chosen on the host per size bucket
-        switch (jb.rpt) {
-            case 1: cd_instance<T, NT, 1>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s, resid, red64, lambda_d); break;
-            case 2: cd_instance<T, NT, 2>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s, resid, red64, lambda_d); break;
-            case 4: cd_instance<T, NT, 4>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s, resid, red64, lambda_d); break;
-            default: cd_instance<T, NT, 8>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s, resid, red64, lambda_d); break;
-        }
+        if (jb.rpt == 1)
+            cd_instance<T, NT, 1>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s, resid, red64, lambda_d);
+        else if (jb.rpt == 2)
+            cd_instance<T, NT, 2>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s, resid, red64, lambda_d);
+        else if (RMAX == 4 || jb.rpt == 4)
+            cd_instance<T, NT, 4>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s, resid, red64, lambda_d);
+        else
+            cd_instance<T, NT, RMAX>(jb, H, Y, X0, X, info, lambda, T_max, tol, msum, ld_arg, smem_raw, red_s, flag_s, resid, red64, lambda_d);
         __syncthreads();
     }
 }
@@ -382,25 +393,54 @@ template <typename T, int NT> static hipError_t launch_zf_t(const WgLaunch& L, h
     return hipGetLastError();
 }
 
-template <typename T, int NT> static hipError_t launch_wg_t(const WgLaunch& L, hipStream_t st) {
+template <typename T, int NT, int RMAX> static hipError_t launch_wg_t(const WgLaunch& L, hipStream_t st) {
     const size_t shm = (size_t)L.n_max * 2 * sizeof(cv<T>);
-    hipLaunchKernelGGL((k_cd_wg<T, NT>), dim3(L.grid), dim3(NT), shm, st, L.jobs, L.njobs, (const cv<T>*)L.H,
+    hipLaunchKernelGGL((k_cd_wg<T, NT, RMAX>), dim3(L.grid), dim3(NT), shm, st, L.jobs, L.njobs, (const cv<T>*)L.H,
                        (const cv<T>*)L.Y, (const cv<T>*)L.X0, (cv<T>*)L.X, L.info, L.lambda, L.T_max, L.tol,
                        L.order, L.queue, L.msum, L.ld, L.resid);
     return hipGetLastError();
 }
 
-template <typename T, int NT> static hipError_t set_lds_t(size_t bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_cd_wg<T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+template <typename T, int NT, int RMAX> static hipError_t set_lds_t(size_t bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_cd_wg<T, NT, RMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)bytes);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_zf_wg<T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
-template <typename T, int NT> static int occ_t(size_t bytes) {
+template <typename T, int NT, int RMAX> static int occ_t(size_t bytes) {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cd_wg<T, NT>, NT, bytes) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cd_wg<T, NT, RMAX>, NT, bytes) != hipSuccess) return 0;
     return per;
 }
+
+#define CDM_WG_DISPATCH_R(FN, c128, nt, rmax, ...)                                             \
+    do {                                                                                       \
+        if (rmax <= 4) {                                                                       \
+            if (c128) {                                                                        \
+                if (nt == 128) return FN<double, 128, 4>(__VA_ARGS__);                         \
+                if (nt == 256) return FN<double, 256, 4>(__VA_ARGS__);                         \
+                if (nt == 512) return FN<double, 512, 4>(__VA_ARGS__);                         \
+                if (nt == 1024) return FN<double, 1024, 4>(__VA_ARGS__);                       \
+            } else {                                                                           \
+                if (nt == 128) return FN<float, 128, 4>(__VA_ARGS__);                          \
+                if (nt == 256) return FN<float, 256, 4>(__VA_ARGS__);                          \
+                if (nt == 512) return FN<float, 512, 4>(__VA_ARGS__);                          \
+                if (nt == 1024) return FN<float, 1024, 4>(__VA_ARGS__);                        \
+            }                                                                                  \
+        } else {                                                                               \
+            if (c128) {                                                                        \
+                if (nt == 128) return FN<double, 128, 8>(__VA_ARGS__);                         \
+                if (nt == 256) return FN<double, 256, 8>(__VA_ARGS__);                         \
+                if (nt == 512) return FN<double, 512, 8>(__VA_ARGS__);                         \
+                if (nt == 1024) return FN<double, 1024, 8>(__VA_ARGS__);                       \
+            } else {                                                                           \
+                if (nt == 128) return FN<float, 128, 8>(__VA_ARGS__);                          \
+                if (nt == 256) return FN<float, 256, 8>(__VA_ARGS__);                          \
+                if (nt == 512) return FN<float, 512, 8>(__VA_ARGS__);                          \
+                if (nt == 1024) return FN<float, 1024, 8>(__VA_ARGS__);                        \
+            }                                                                                  \
+        }                                                                                      \
+    } while (0)
 
 #define CDM_WG_DISPATCH(FN, c128, nt, ...)                                   \
     do {                                                                     \
@@ -418,19 +458,19 @@ template <typename T, int NT> static int occ_t(size_t bytes) {
     } while (0)
 
 hipError_t launch_wg(const WgLaunch& L, hipStream_t st) {
-    CDM_WG_DISPATCH(launch_wg_t, L.c128, L.nt, L, st);
+    CDM_WG_DISPATCH_R(launch_wg_t, L.c128, L.nt, L.rmax, L, st);
     return hipErrorInvalidValue;
 }
 hipError_t launch_zf(const WgLaunch& L, hipStream_t st) {
     CDM_WG_DISPATCH(launch_zf_t, L.c128, L.nt, L, st);
     return hipErrorInvalidValue;
 }
-hipError_t wg_set_lds_limit(bool c128, int nt, size_t bytes) {
-    CDM_WG_DISPATCH(set_lds_t, c128, nt, bytes);
+hipError_t wg_set_lds_limit(bool c128, int nt, int rmax, size_t bytes) {
+    CDM_WG_DISPATCH_R(set_lds_t, c128, nt, rmax, bytes);
     return hipErrorInvalidValue;
 }
-int wg_occupancy(bool c128, int nt, size_t bytes) {
-    CDM_WG_DISPATCH(occ_t, c128, nt, bytes);
+int wg_occupancy(bool c128, int nt, int rmax, size_t bytes) {
+    CDM_WG_DISPATCH_R(occ_t, c128, nt, rmax, bytes);
     return 0;
 }
 size_t wg_lds_bytes(int n_max, bool c128) { return (size_t)n_max * 2 * (c128 ? 16 : 8); }

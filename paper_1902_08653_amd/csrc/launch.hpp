@@ -43,6 +43,7 @@ struct WgLaunch {
     int64_t ld;       // leading dimension for jobs whose own ld is <= 0
     double rho_c;     // downlink: per-cluster power rho/sqrt(C) (<= 0: no scaling)
     int resid;        // uplink: also write the FP64 normal-equation residual per job
+    int rmax = 8;     // largest rows-per-thread tile among the jobs (<= 4 or 8)
 };
 hipError_t launch_wg(const WgLaunch& L, hipStream_t st);
 // Algorithm 2 (downlink ZF precoding), same job and tile conventions; Y is s (U).
@@ -84,8 +85,9 @@ hipError_t launch_bm_resid_check(const BmLaunch& L, hipStream_t st);
 size_t bm_lds_bytes(int n_max);
 hipError_t bm_set_lds_limit(int low, int nt, size_t bytes);
 int bm_occupancy(int low, int nt, size_t bytes);
-hipError_t wg_set_lds_limit(bool c128, int nt, size_t bytes);
-int wg_occupancy(bool c128, int nt, size_t bytes);
+// rmax: the largest rows-per-thread tile of the launch (<= 4 or 8)
+hipError_t wg_set_lds_limit(bool c128, int nt, int rmax, size_t bytes);
+int wg_occupancy(bool c128, int nt, int rmax, size_t bytes);
 
 // Fusion of C local estimates (Sec. III): x = sum_c lambda_c x_c with
 // lambda_c = sigma_c^-2 / sum_c' sigma_c'^-2 and sigma_c^2 = (N0/U) sum_u m_{u,c}.

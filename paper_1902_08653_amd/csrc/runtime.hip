@@ -202,11 +202,11 @@ static int32_t setup_wg(cdm_plan* p, int m_max, int n_max, int njobs, int nt) {
     if (p->wg_lds + 2048 > kLdsMax) return CDM_ESHAPE;
     if (p->wg_lds > 64 * 1024) {
         const hipError_t e = p->wg_low ? bm_set_lds_limit(p->wg_low, nt, p->wg_lds)
-                                       : wg_set_lds_limit(p->c128, nt, p->wg_lds);
+                                       : wg_set_lds_limit(p->c128, nt, p->wg_rpt, p->wg_lds);
         if (e != hipSuccess) return CDM_ESHAPE;
     }
     const int occ = std::max(1, p->wg_low ? bm_occupancy(p->wg_low, nt, p->wg_lds)
-                                          : wg_occupancy(p->c128, nt, p->wg_lds));
+                                          : wg_occupancy(p->c128, nt, p->wg_rpt, p->wg_lds));
     p->wg_grid = std::max(1, std::min(njobs, occ * p->ncu));
     p->njobs = njobs;
     return CDM_OK;
@@ -714,6 +714,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         WgLaunch L;
         L.c128 = p->c128;
         L.nt = p->wg_nt;
+        L.rmax = p->wg_rpt;
         L.grid = p->wg_grid;
         L.n_max = p->n_max;
         L.jobs = p->jobs;
@@ -758,6 +759,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         WgLaunch L;
         L.c128 = p->c128;
         L.nt = p->wg_nt;
+        L.rmax = p->wg_rpt;
         L.grid = p->wg_grid;
         L.n_max = p->n_max;
         L.jobs = p->jobs;
@@ -907,12 +909,15 @@ static double time_batched(cdm_plan* p, int nt, int m_max, int n_max, WgJob* job
     if (hipMemcpy(jobs_d, jj.data(), sizeof(WgJob) * njobs, hipMemcpyHostToDevice) != hipSuccess) return -1.0;
     const bool mx = p->wg_low != WG_LOW_NONE;
     const size_t lds = mx ? bm_lds_bytes(std::max(1, n_max)) : wg_lds_bytes(std::max(1, n_max), p->c128);
-    if (lds > 64 * 1024 && (mx ? bm_set_lds_limit(p->wg_low, nt, lds) : wg_set_lds_limit(p->c128, nt, lds)) != hipSuccess)
+    const int rmax = rpt_for(m_max, nt);
+    if (lds > 64 * 1024 &&
+        (mx ? bm_set_lds_limit(p->wg_low, nt, lds) : wg_set_lds_limit(p->c128, nt, rmax, lds)) != hipSuccess)
         return -1.0;
-    const int occ = std::max(1, mx ? bm_occupancy(p->wg_low, nt, lds) : wg_occupancy(p->c128, nt, lds));
+    const int occ = std::max(1, mx ? bm_occupancy(p->wg_low, nt, lds) : wg_occupancy(p->c128, nt, rmax, lds));
     WgLaunch L;
     L.c128 = p->c128;
     L.nt = nt;
+    L.rmax = rmax;
     L.grid = std::max(1, std::min(njobs, occ * p->ncu));
     L.n_max = std::max(1, n_max);
     L.jobs = jobs_d;
@@ -1209,6 +1214,7 @@ int32_t cdm_solve_batched(cdm_plan* p, const void* H, const void* y, double N0, 
     WgLaunch L;
     L.c128 = p->c128;
     L.nt = p->wg_nt;
+    L.rmax = p->wg_rpt;
     L.grid = p->wg_grid;
     L.n_max = p->n_max;
     L.jobs = p->jobs;
