@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=0,
                     help="oracle sweeps for the CPU baseline (0 = a full solve)")
     ap.add_argument("--copy-probe", action="store_true", help="also run the library copy kernel")
-    ap.add_argument("--workload", default="dense", choices=["dense", "batched", "warm"],
+    ap.add_argument("--workload", default="dense", choices=["dense", "batched", "warm", "paper"],
                     help="dense: one 16384x8192 instance (default); batched: 4096 uneven instances; "
                          "warm: learned warm start against a cold start on 4096 held-out uneven instances")
     ap.add_argument("--train", type=int, default=50000, help="warm: training instances")
@@ -90,6 +90,8 @@ def main():
         return bench_batched(a)
     if a.workload == "warm":
         return bench_warm(a)
+    if a.workload == "paper":
+        return bench_paper(a)
     import torch
 
     from paper_1902_08653_amd import cdm, inputs
@@ -315,6 +317,82 @@ def bench_batched(a):
         out["copy_probe_gbs"] = _copy_probe(cdm, dev, stream)
     print(json.dumps(out))
     plan.close()
+
+# the paper's Table I (uplink detector, latency ms / throughput Gbit/s on C V100 GPUs
+# including the inter-GPU fusion): context for the paper-shaped workload, not a target
+PAPER_TABLE_I = {("fp32", 4, 2): (0.465, 1.23), ("fp32", 4, 3): (0.540, 1.06), ("fp32", 4, 4): (0.617, 0.93),
+                 ("fp32", 8, 2): (0.502, 1.14), ("fp32", 8, 3): (0.585, 0.98), ("fp32", 8, 4): (0.665, 0.86),
+                 ("fp16", 4, 2): (0.259, 2.21), ("fp16", 4, 3): (0.298, 1.92), ("fp16", 4, 4): (0.341, 1.68),
+                 ("fp16", 8, 2): (0.295, 1.95), ("fp16", 8, 3): (0.331, 1.73), ("fp16", 8, 4): (0.370, 1.55)}
+
+
+def bench_paper(a):
+    """The paper's throughput shape on one GPU: 1200 subcarriers x 15 received vectors,
+    U = 8 users, 16-QAM, Rayleigh channels, C clusters of 32 antennas, T sweeps from
+    x = 0, cluster fusion; one cdm_detect_batch launch per batch (HIP graph replays).
+    The headline line is C = 4, T = 3 in FP16 (the configuration of the paper's
+    per-user throughput comparison); every (C, T, precision) cell is reported."""
+    import torch
+
+    from paper_1902_08653_amd import cdm, inputs
+    dev = torch.device("cuda:0")
+    S, V, U, Bc = 1200, 15, 8, 32
+    bits = S * V * U * 4
+    cells, lines = {}, []
+    for Cn in (4, 8):
+        d = inputs.paper_shaped(Cn, Bc, U, S, V, snr_db=10.0, seed=1)
+        B = Cn * Bc
+        H32 = torch.from_numpy(d["Ht"].astype(np.complex64).reshape(-1)).to(dev)
+        Y32 = torch.from_numpy(d["Y"].astype(np.complex64).reshape(-1)).to(dev)
+        H16 = torch.from_numpy(np.stack([d["Ht"].real, d["Ht"].imag], -1).astype(np.float16).reshape(-1)).to(dev)
+        Y16 = torch.from_numpy(np.stack([d["Y"].real, d["Y"].imag], -1).astype(np.float16).reshape(-1)).to(dev)
+        for prec, (Hd, Yd, esz) in (("fp32", (H32, Y32, 8)), ("fp16", (H16, Y16, 4))):
+            out = torch.empty(S * V * U * (1 if prec == "fp32" else 2), dtype=Yd.dtype, device=dev)
+            for T in (2, 3, 4):
+                g = _graph(lambda: cdm.detect_batch(Hd, Yd, S, V, Cn, Bc, U, T, d["N0"], out=out))
+                ms = _time_graph(g, max(a.steps, 50), max(a.warmup, 5))
+                del g
+                algo = (S * B * U + S * V * B + S * V * U) * esz
+                cells[(prec, Cn, T)] = dict(ms=ms, gbps=bits / (ms * 1e-3) / 1e9, hbm_gbs=algo / (ms * 1e-3) / 1e9,
+                                            bytes=algo)
+                pl, pt = PAPER_TABLE_I[(prec, Cn, T)]
+                lines.append("%s C=%d T=%d: %.4f ms, %.1f Gbit/s (paper on %d V100: %.3f ms, %.2f Gbit/s)"
+                             % (prec, Cn, T, ms, cells[(prec, Cn, T)]["gbps"], Cn, pl, pt))
+                print("[bench] " + lines[-1], file=sys.stderr, flush=True)
+    head = cells[("fp16", 4, 3)]
+    cpu = None
+    if not a.no_oracle:
+        from oracle import oracle
+        oracle.build()
+        d = inputs.paper_shaped(4, Bc, U, 40, V, snr_db=10.0, seed=1)
+        tc = time.perf_counter()
+        n = 0
+        for s_ in range(40):
+            H = d["Ht"][s_].T.astype(np.complex128)
+            for v in range(V):
+                oracle.uplink_cd(H, d["Y"][s_, v].astype(np.complex128), d["N0"], 1.0, T_max=3, C_clusters=4)
+                n += 1
+        cs = time.perf_counter() - tc
+        cpu = {"value": n * U * 4 / cs / 1e9, "unit": "Gbit/s", "cores": 1, "kind": "oracle",
+               "sample": "%d of the batch's received vectors (C = 4, T = 3) through the oracle's Algorithm 1 "
+                         "with fusion on one thread (%.2f s)" % (n, cs)}
+    out = {
+        "metric": "detection throughput of the paper's Table I batch",
+        "value": head["gbps"], "unit": "Gbit/s",
+        "n_gpus": 1, "steps": max(a.steps, 50), "warmup": max(a.warmup, 5), "ms_per_step": head["ms"],
+        "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": head["gbps"] / PAPER_TABLE_I[("fp16", 4, 3)][1],
+        "vs_baseline_note": "paper's Table I on 4 V100 GPUs incl. inter-GPU fusion; context, not the target",
+        "dtype": "f16", "data": "synthetic",
+        "config": {"workload": "paper-shaped uplink: 1200 subcarriers x 15 vectors, U=8, 16-QAM, Rayleigh, "
+                               "C=4 clusters x 32 antennas, T=3, fusion, SNR 10 dB"},
+        "roofline": {"bound": "hbm", "achieved": head["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": head["hbm_gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": "k_detect_small",
+                     "algorithmic_bytes_per_launch": head["bytes"], "avg_launch_ms": head["ms"]},
+        "cpu_baseline": cpu,
+        "cells": {"%s_C%d_T%d" % k: v for k, v in cells.items()},
+    }
+    print(json.dumps(out))
 
 
 def _copy_probe(cdm, dev, stream):

@@ -58,7 +58,8 @@ typedef enum cdm_problem { CDM_UPLINK_LMMSE = 0, CDM_DOWNLINK_ZF = 1 } cdm_probl
  * FP8-e4m3, or the complex64 rounding) with an FP64 residual refinement outside
  * (see cdm_solve and cdm_solve_batched).  CDM_MIXED_C64 is for batched plans only. */
 typedef enum cdm_precision {
-    CDM_C128 = 0, CDM_C64 = 1, CDM_MIXED_BF16 = 2, CDM_MIXED_FP8 = 3, CDM_MIXED_C64 = 4
+    CDM_C128 = 0, CDM_C64 = 1, CDM_MIXED_BF16 = 2, CDM_MIXED_FP8 = 3, CDM_MIXED_C64 = 4,
+    CDM_C16 = 5   /* complex FP16 (two halves, 4 B): cdm_detect_batch only */
 } cdm_precision;
 
 typedef enum cdm_layout { CDM_DENSE = 0, CDM_CSR = 1 } cdm_layout;
@@ -223,6 +224,26 @@ int32_t cdm_quantized_copy(cdm_plan* plan, const void* H, int64_t ldh, void* re_
  * Uses the plan's workspace; same argument conventions as cdm_solve. */
 int32_t cdm_residual(cdm_plan* plan, const void* H, int64_t ldh, const void* y, double N0,
                      double Ex, const void* x, double* out, void* stream);
+
+/* Decentralized detection of a batch of small clustered problems: the shape of the
+ * paper's throughput measurements (Sec. VI, Table I; Algorithm 1 with the fusion of
+ * Sec. III).  S subcarriers; subcarrier s has the channel H_s (B x U, B = C * Bc, rows
+ * = antennas in C clusters of Bc consecutive rows) shared by V received vectors
+ * y_{s,v} (B each).  For every (s, v) each cluster c runs exactly T_max sweeps of
+ * Algorithm 1 from x = 0 on its rows, and the estimates are fused:
+ *   x_hat = sum_c lambda_c x_c,  lambda_c = sigma_c^-2 / sum_c' sigma_c'^-2,
+ *   sigma_c^2 = (N0 / U) sum_u m_{u,c},  m_{u,c} = 1 / (||h_{u,c}||^2 + N0 / Ex).
+ *  H  device, S blocks of B x U column-major (ld = B), block s at element s*B*U
+ *  Y  device, S*V vectors of B, vector (s, v) at element (s*V + v)*B
+ *  X  device output, S*V vectors of U, vector (s, v) at element (s*V + v)*U
+ * Elements are complex in `precision`: CDM_C64 (FP32 arithmetic) or CDM_C16 (FP16
+ * storage; residual updates and dot products in packed FP16, scalar rule in FP32).
+ * Limits: C in {1, 2, 4, 8}, 1 <= Bc <= 32, 1 <= U <= 16; N0 > 0 when C > 1.
+ * Enqueues one kernel; allocates nothing.  Errors: CDM_EINVAL (NULL pointer, N0 < 0,
+ * Ex <= 0, T_max < 1), CDM_EDTYPE, CDM_ESHAPE, CDM_EHIP. */
+int32_t cdm_detect_batch(int32_t S, int32_t V, int32_t C, int32_t Bc, int32_t U, int32_t T_max,
+                         int32_t precision, const void* H, const void* Y, double N0, double Ex,
+                         void* X, void* stream);
 
 /* Per-coordinate features of a batched plan's packed instances, for the
  * learned warm start (one row of 8 floats per user u of instance i, rows in the

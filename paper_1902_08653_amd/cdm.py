@@ -18,7 +18,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcdm.so")
 
 UPLINK_LMMSE, DOWNLINK_ZF = 0, 1
-C128, C64, MIXED_BF16, MIXED_FP8, MIXED_C64 = 0, 1, 2, 3, 4
+C128, C64, MIXED_BF16, MIXED_FP8, MIXED_C64, C16 = 0, 1, 2, 3, 4, 5
 DENSE, CSR = 0, 1
 ENGINE_AUTO, ENGINE_WG, ENGINE_PANEL = 0, 1, 2
 F_RESIDUAL = 1
@@ -55,7 +55,8 @@ EXPORTS = ["cdm_version", "cdm_status_string", "cdm_last_error", "cdm_create", "
            "cdm_create_batched", "cdm_batched_offsets", "cdm_solve_batched", "cdm_residual",
            "cdm_plan_describe", "cdm_plan_timings", "cdm_stream_copy", "cdm_csr_transpose", "cdm_quantized_copy", "cdm_batched_features", "cdm_mlp_create",
            "cdm_mlp_param_count", "cdm_mlp_set_weights", "cdm_mlp_get_weights", "cdm_mlp_forward",
-           "cdm_mlp_gradients", "cdm_mlp_train_step", "cdm_mlp_predict", "cdm_mlp_destroy", "cdm_destroy"]
+           "cdm_mlp_gradients", "cdm_mlp_train_step", "cdm_mlp_predict", "cdm_mlp_destroy", "cdm_destroy",
+           "cdm_detect_batch"]
 
 _lib = None
 
@@ -117,6 +118,8 @@ def lib():
         L.cdm_mlp_destroy.restype = i32
         L.cdm_destroy.argtypes = [P]
         L.cdm_destroy.restype = i32
+        L.cdm_detect_batch.argtypes = [i32, i32, i32, i32, i32, i32, i32, P, P, f64, f64, P, P]
+        L.cdm_detect_batch.restype = i32
         _lib = L
     return _lib
 
@@ -239,6 +242,27 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def detect_batch(H, Y, S, V, C_clusters, Bc, U, T_max, N0, Ex=1.0, out=None, stream=None):
+    """cdm_detect_batch: fused decentralized detection of S subcarriers x V vectors.
+    H, Y (and `out`) are device tensors of complex64, or of complex FP16 held as
+    torch.complex32 / interleaved float16; returns X (S*V*U complex, Y's dtype)."""
+    import torch
+    if Y.dtype == torch.complex64:
+        prec = C64
+    elif Y.dtype in (torch.complex32, torch.float16):
+        prec = C16
+    else:
+        raise TypeError("detect_batch takes complex64 or complex FP16 tensors")
+    if H.dtype != Y.dtype:
+        raise TypeError("H and Y must have the same dtype")
+    per = 2 if Y.dtype == torch.float16 else 1
+    if out is None:
+        out = torch.empty(int(S) * int(V) * int(U) * per, dtype=Y.dtype, device=Y.device)
+    _check(lib().cdm_detect_batch(int(S), int(V), int(C_clusters), int(Bc), int(U), int(T_max), prec, _ptr(H),
+                                  _ptr(Y), float(N0), float(Ex), _ptr(out), _stream(stream)), "cdm_detect_batch")
+    return out
 
 
 def stream_copy(src, dst, stream=None):

@@ -104,6 +104,19 @@ def test_mixed_c64_is_batched_only(lib):
     assert h.value is None
 
 
+@pytest.mark.parametrize("args,status", [
+    (dict(C=3), -2), (dict(Bc=33), -2), (dict(U=17), -2), (dict(U=0), -2), (dict(S=0), -2),
+    (dict(prec=0), -3), (dict(T=0), -1), (dict(N0=0.0), -1), (dict(Ex=0.0), -1),
+])
+def test_detect_batch_rejects_on_the_host(lib, args, status):
+    a = dict(S=4, V=3, C=4, Bc=32, U=8, T=3, prec=1, N0=0.5, Ex=1.0)
+    a.update(args)
+    buf = C.c_void_p(16)   # never dereferenced: validation comes first
+    st = lib.cdm_detect_batch(a["S"], a["V"], a["C"], a["Bc"], a["U"], a["T"], a["prec"], buf, buf,
+                              a["N0"], a["Ex"], buf, None)
+    assert st == status
+
+
 def test_info_record_layout():
     from paper_1902_08653_amd import cdm
     assert cdm.INFO_DTYPE.itemsize == 32
