@@ -27,26 +27,29 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the sweep kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# passes scaled by the copy-kernel calibration (profiles/k_cd_panel_la_c128_16384x8192.md),
-# valid only while the kernel sources hash to the recorded value.
+# HBM bytes per launch (per solve) from rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled by
+# the copy-kernel calibration (profiles/), valid only while the sources that make the
+# kernel hash to the recorded value.
 TRAFFIC = {
-    ("k_cd_panel_la", "c128", 16384, 8192, 1e-11): {"sources_sha256_16": "0e6dc0ce277c9d31", "bytes": 144998758445.0},
+    ("k_cd_panel_la", "c128 16384x8192 tol 1e-11"): {
+        "sources": ['paper_1902_08653_amd/csrc/k_panel_la.hip', 'paper_1902_08653_amd/csrc/panel.hpp', 'paper_1902_08653_amd/csrc/common.hpp'], "sha256_16": "5616b54514c97b1a", "bytes": 144985995137.0},
+    ("k_cd_wg", "c64 batch 4096 tol 1e-06"): {
+        "sources": ['paper_1902_08653_amd/csrc/k_wg.hip', 'paper_1902_08653_amd/csrc/common.hpp', 'paper_1902_08653_amd/csrc/wg.hpp'], "sha256_16": "0250e54ccc4fc8b0", "bytes": 713278845676.0},
+    ("k_bm_resid + k_bm_grad + k_bm_inner", "mixed-c64 batch 4096 tol 1e-08"): {
+        "sources": ['paper_1902_08653_amd/csrc/k_wg_mixed.hip', 'paper_1902_08653_amd/csrc/common.hpp', 'paper_1902_08653_amd/csrc/wg.hpp', 'paper_1902_08653_amd/csrc/quant.hpp'], "sha256_16": "a27fee61a3afae15", "bytes": 1178767779708.0},
 }
-TRAFFIC_SOURCES = ["paper_1902_08653_amd/csrc/k_panel_la.hip", "paper_1902_08653_amd/csrc/panel.hpp",
-                   "paper_1902_08653_amd/csrc/common.hpp"]
 
 
-def measured_traffic(kernel, prec, B, U, tol):
+def measured_traffic(kernel, workload):
     import hashlib
-    rec = TRAFFIC.get((kernel, prec, B, U, tol))
+    rec = TRAFFIC.get((kernel, workload))
     if rec is None:
         return None
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    sha = hashlib.sha256()
+    for f in rec["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return rec["bytes"] if h.hexdigest()[:16] == rec["sources_sha256_16"] else None
+            sha.update(fh.read())
+    return rec["bytes"] if sha.hexdigest()[:16] == rec["sha256_16"] else None
 
 
 def parse():
@@ -57,9 +60,10 @@ def parse():
     ap.add_argument("--B", type=int, default=16384)
     ap.add_argument("--U", type=int, default=8192)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--precision", default="c128", choices=["c128", "c64", "bf16", "fp8"],
-                    help="c128/c64: plain sweeps in that precision; bf16/fp8: mixed-precision "
-                         "refinement (FP64 outer gradient around FP32 inner sweeps on a BF16/FP8 copy)")
+    ap.add_argument("--precision", default=None, choices=["c128", "c64", "bf16", "fp8", "mixed-c64"],
+                    help="dense (default c128): c128/c64 plain sweeps, bf16/fp8 mixed-precision refinement "
+                         "(FP64 outer gradient around FP32 inner sweeps on a BF16/FP8 copy); batched (default "
+                         "c64): c64/c128 plain, mixed-c64/bf16 mixed-precision refinement")
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--eps", type=float, default=None, help="accuracy target vs the oracle")
     ap.add_argument("--lam", type=float, default=0.1)
@@ -96,7 +100,9 @@ def main():
 
     from paper_1902_08653_amd import cdm, inputs
 
-    prec = a.precision
+    prec = a.precision or "c128"
+    if prec == "mixed-c64":
+        sys.exit("dense workload: --precision c128, c64, bf16 or fp8")
     fp64_target = prec in ("c128", "bf16", "fp8")
     tol = a.tol if a.tol is not None else (1e-11 if fp64_target else 1e-6)
     eps = a.eps if a.eps is not None else (1e-10 if fp64_target else 1e-5)
@@ -205,7 +211,7 @@ def main():
                    "engine": json.loads(plan.describe())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(sweep_kernel, prec, a.B, a.U, tol),
+                     "traffic": measured_traffic(sweep_kernel, "%s %dx%d tol %g" % (prec, a.B, a.U, tol)),
                      "kernel": sweep_kernel, "algorithmic_bytes_per_launch": mean_sweeps * h_bytes,
                      "avg_launch_ms": sweep_ms},
         "cpu_baseline": cpu,
@@ -222,59 +228,59 @@ def main():
 
 
 def bench_batched(a):
-    """4096 independent uplink instances, m ~ U{64..2048}, n = m/2, complex64, lambda 0.1,
-    solved to a relative step of 1e-6 (cap 200) in one persistent launch captured in a
-    HIP graph; tiles chosen by the library's autotuner."""
+    """4096 independent uplink instances, m ~ U{64..2048}, n = m/2, lambda 0.1, in one
+    HIP graph.  --precision c64 (the default here): complex64 data, plain sweeps to a
+    relative step of 1e-6 in one persistent launch.  c128: complex128 data, plain sweeps
+    to 1e-8.  mixed-c64 / bf16: complex128 data, the mixed-precision refinement (complex64
+    or BF16 inner copy) to 1e-8.  Tiles from the library's autotuner."""
     import torch
 
     from paper_1902_08653_amd import cdm, inputs
     dev = torch.device("cuda:0")
-    tol, eps = 1e-6, 1e-5
+    prec = a.precision or "c64"
+    if prec not in ("c64", "c128", "mixed-c64", "bf16"):
+        sys.exit("batched workload: --precision c64, c128, mixed-c64 or bf16")
+    c64 = prec == "c64"
+    mixed = prec in ("mixed-c64", "bf16")
+    tol, eps = (1e-6, 1e-5) if c64 else (1e-8, 1e-6)
+    dt = torch.complex64 if c64 else torch.complex128
+    esz = 8 if c64 else 16
     t0 = time.time()
-    H, y, m, n = inputs.batch_uneven_device(a.batch, seed0=0, device=dev)
+    H, y, m, n = inputs.batch_uneven_device(a.batch, seed0=0, dtype=dt, device=dev)
     torch.cuda.synchronize()
-    print("[bench] batch of %d ready in %.1fs (%.2f GB)" % (a.batch, time.time() - t0, H.numel() * 8 / 1e9),
+    print("[bench] batch of %d ready in %.1fs (%.2f GB)" % (a.batch, time.time() - t0, H.numel() * esz / 1e9),
           file=sys.stderr, flush=True)
-    plan = cdm.BatchedPlan(m, n, precision="c64", T_max=200, tol=tol, autotune=True)
-    x = torch.empty(int(n.astype(np.int64).sum()), dtype=torch.complex64, device=dev)
+    plan = cdm.BatchedPlan(m, n, precision=prec, T_max=(8 if prec == "mixed-c64" else 16) if mixed else 200,
+                           tol=tol, autotune=True)
+    x = torch.empty(int(n.astype(np.int64).sum()), dtype=dt, device=dev)
     info = torch.empty(32 * a.batch, dtype=torch.uint8, device=dev)
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        plan.solve(H, y, N0=a.lam, x=x, info=info)      # eager warm-up on the capture stream
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        plan.solve(H, y, N0=a.lam, x=x, info=info)
-    for _ in range(a.warmup):
-        g.replay()
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(a.steps):
-        g.replay()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / a.steps
+    g = _graph(lambda: plan.solve(H, y, N0=a.lam, x=x, info=info))
+    ms = _time_graph(g, a.steps, a.warmup)
     rec = cdm.parse_info(info)
     sweeps = rec["sweeps"].astype(np.int64)
-    hbytes = (m.astype(np.int64) * n.astype(np.int64)) * 8
-    alg_bytes = float((sweeps * hbytes).sum())
+    mn = m.astype(np.int64) * n.astype(np.int64)
+    if mixed:
+        lowsz = 8 if prec == "mixed-c64" else 4
+        inner = rec["reserved"].astype(np.int64)
+        # FP64 passes (a cold first step needs only g), inner sweeps over the copy, its write
+        alg_bytes = float((mn * (16 * (2 * sweeps - 1) + lowsz * inner + lowsz)).sum())
+        kernel = "k_bm_resid + k_bm_grad + k_bm_inner"
+        acc = {"outer_mean": float(sweeps.mean()), "inner_sweeps_mean": float(inner.mean())}
+    else:
+        alg_bytes = float((sweeps * mn * esz).sum())
+        kernel = "k_cd_wg"
+        acc = {"sweeps_mean": float(sweeps.mean()), "sweeps_max": int(sweeps.max())}
     achieved = alg_bytes / (ms * 1e-3) / 1e9
-    print("[bench] %.3f ms per batch solve, sweeps min/mean/max %d/%.1f/%d, flags %d" % (
-        ms, sweeps.min(), sweeps.mean(), sweeps.max(), int(np.bitwise_or.reduce(rec["flags"]))),
-        file=sys.stderr, flush=True)
+    print("[bench] %.3f ms per batch solve, %s, flags %d" % (ms, acc, int(np.bitwise_or.reduce(rec["flags"]))),
+          file=sys.stderr, flush=True)
     cpu = None
     errs = []
     if not a.no_oracle:
         from oracle import oracle
         oracle.build()
-        order = np.argsort(-(m.astype(np.int64) * n))
+        order = np.argsort(-mn)
         pick = order[np.linspace(0, a.batch - 1, a.sample).astype(int)]
-        ho = np.concatenate([[0], np.cumsum(m.astype(np.int64) * n)[:-1]])
+        ho = np.concatenate([[0], np.cumsum(mn)[:-1]])
         yo = np.concatenate([[0], np.cumsum(m.astype(np.int64))[:-1]])
         xo = np.concatenate([[0], np.cumsum(n.astype(np.int64))[:-1]])
         xg = x.cpu().numpy()
@@ -284,39 +290,43 @@ def bench_batched(a):
             Hi = H[ho[i]:ho[i] + m[i] * n[i]].cpu().numpy().reshape(n[i], m[i]).T.astype(np.complex128)
             yi = y[yo[i]:yo[i] + m[i]].cpu().numpy().astype(np.complex128)
             tc = time.perf_counter()
-            ref = oracle.local_cd(Hi, yi, a.lam, T_max=200, tol=1e-12)
+            ref = oracle.local_cd(Hi, yi, a.lam, T_max=200, tol=tol)
             cpu_s += time.perf_counter() - tc
-            cpu_bytes += ref["sweeps"] * float(hbytes[i]) * 2
-            errs.append(float(np.linalg.norm(xg[xo[i]:xo[i] + n[i]] - ref["x"]) / np.linalg.norm(ref["x"])))
-        # oracle cost per byte of one complex128 sweep, scaled to this batch's sweeps (same counts)
-        full = float((sweeps * hbytes * 2).sum())
+            cpu_bytes += ref["sweeps"] * float(mn[i]) * 16
+            exact = ref["x"] if c64 else oracle.local_cd(Hi, yi, a.lam, T_max=2000, tol=1e-13)["x"]
+            errs.append(float(np.linalg.norm(xg[xo[i]:xo[i] + n[i]] - exact) / np.linalg.norm(exact)))
+        # oracle cost per byte of one complex128 sweep, scaled to the plain sweep count of
+        # this batch (the mixed forms: the oracle's own sweeps on the sample)
+        full = float((sweeps * mn * 16).sum()) if not mixed else cpu_bytes * a.batch / len(pick)
         cpu = {"value": a.batch / (cpu_s * full / cpu_bytes), "unit": "instance solves/s", "cores": 1,
                "kind": "oracle",
-               "sample": "%d instances spread over the size range, oracle to rel. step 1e-12 on one thread "
-                         "(%.1f s), scaled by the batch's sweep-weighted H bytes" % (len(pick), cpu_s)}
+               "sample": "%d instances spread over the size range, oracle to rel. step %g on one thread "
+                         "(%.1f s), scaled by the batch's sweep-weighted H bytes" % (len(pick), tol, cpu_s)}
     out = {
         "metric": "solves/sec to fixed rel. tolerance vs FP64 oracle",
         "value": a.batch * 1000.0 / ms,
         "unit": "instance solves/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"c64": "f32", "c128": "f64", "mixed-c64": "f32+f64", "bf16": "bf16+f32+f64"}[prec],
         "data": "synthetic",
-        "config": {"workload": "%d uneven uplink instances, m~U{64..2048}, n=m/2, complex64, CN(0,1/m), "
-                               "lambda=%g, rel-step tol %g, one persistent launch in a HIP graph"
-                               % (a.batch, a.lam, tol), "engine": json.loads(plan.describe())},
+        "config": {"workload": "%d uneven uplink instances, m~U{64..2048}, n=m/2, %s, CN(0,1/m), lambda=%g, "
+                               "rel-step tol %g, HIP graph" % (a.batch, prec, a.lam, tol),
+                   "engine": json.loads(plan.describe())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_cd_wg",
-                     "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": ms},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(kernel, "%s batch %d tol %g" % (prec, a.batch, tol)),
+                     "kernel": kernel, "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": ms},
         "cpu_baseline": cpu,
-        "accuracy": {"sweeps_mean": float(sweeps.mean()), "sweeps_max": int(sweeps.max()),
-                     "flags_or": int(np.bitwise_or.reduce(rec["flags"])),
-                     "max_rel_err_vs_oracle_sample": max(errs) if errs else None,
-                     "within_eps": bool(max(errs) <= eps) if errs else None},
+        "accuracy": dict(acc, flags_or=int(np.bitwise_or.reduce(rec["flags"])),
+                         max_rel_err_vs_oracle_sample=max(errs) if errs else None,
+                         within_eps=bool(max(errs) <= eps) if errs else None),
     }
     if a.copy_probe:
-        out["copy_probe_gbs"] = _copy_probe(cdm, dev, stream)
+        out["copy_probe_gbs"] = _copy_probe(cdm, dev, torch.cuda.current_stream())
     print(json.dumps(out))
     plan.close()
+
 
 # the paper's Table I (uplink detector, latency ms / throughput Gbit/s on C V100 GPUs
 # including the inter-GPU fusion): context for the paper-shaped workload, not a target
