@@ -33,7 +33,15 @@ constexpr int GK = 16;
 __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, int64_t sam, int64_t sak,
                                                    const float* __restrict__ Bm, int64_t sbk, int64_t sbn,
                                                    float* __restrict__ C, int64_t ldc, int M, int N, int K,
-                                                   const float* __restrict__ bias, int beta) {
+                                                   const float* __restrict__ bias, int beta, int kc, int64_t zc) {
+    // split along K: workgroup z takes K range [z kc, z kc + kc) into C + z zc
+    {
+        const int z = blockIdx.z;
+        A += (int64_t)z * kc * sak;
+        Bm += (int64_t)z * kc * sbk;
+        C += (int64_t)z * zc;
+        K = min(kc, K - z * kc);
+    }
     __shared__ unsigned short As[GT][GK + 4];
     __shared__ unsigned short Bs[GK][GT + 4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -90,10 +98,209 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, 
             }
 }
 
+// Large products (the training GEMMs): 128 x 128 tile per workgroup of 4 waves (each a
+// 64 x 64 block of 4 x 4 MFMA tiles), K in chunks of 32 staged as BF16 in LDS with the next
+// chunk's FP32 loads in flight during the current chunk's MFMAs.  Operands are read with
+// 16-B loads along their contiguous dimension: AK = A contiguous in k (else in m), BN = B
+// contiguous in n (else in k).  LDS keeps both tiles k-fastest, so an MFMA fragment (4
+// consecutive k) is one 8-B read.
+constexpr int G2T = 128, G2K = 32, G2P = G2K + 8;   // tile, K chunk, padded LDS row
+template <bool AK, bool BN>
+__global__ __launch_bounds__(256) void k_gemm2_bf16(const float* __restrict__ A, int64_t lda,
+                                                    const float* __restrict__ Bm, int64_t ldb,
+                                                    float* __restrict__ C, int64_t ldc, int M, int N, int K,
+                                                    const float* __restrict__ bias, int beta, int kc, int64_t zc) {
+    // split along K: workgroup z takes K range [z kc, z kc + kc) into C + z zc
+    {
+        const int z = blockIdx.z;
+        A += (int64_t)z * kc * (AK ? 1 : lda);
+        Bm += (int64_t)z * kc * (BN ? ldb : 1);
+        C += (int64_t)z * zc;
+        K = min(kc, K - z * kc);
+    }
+    __shared__ __align__(16) unsigned short As[G2T][G2P];
+    __shared__ __align__(16) unsigned short Bs[G2T][G2P];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int m0 = blockIdx.y * G2T, n0 = blockIdx.x * G2T;
+    const int wm = (wid >> 1) * 64, wn = (wid & 1) * 64;
+    // each thread moves 16 floats of A and 16 of B per chunk, as four 16-B loads along
+    // the operand's contiguous dimension
+    //   contiguous in k: row = tid / 2, k offset = (tid % 2) * 16
+    //   contiguous in m or n: k = tid / 8, row offset = (tid % 8) * 16
+    float4 ra[4], rb[4];
+    auto load = [&](int k0) {
+        if (AK) {
+            const int r = tid >> 1, kk = k0 + (tid & 1) * 16;
+            const int gm = m0 + r;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                ra[q] = (gm < M && kk + 4 * q < K) ? *reinterpret_cast<const float4*>(A + (int64_t)gm * lda + kk + 4 * q)
+                                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            const int kk = k0 + (tid >> 3), mm = m0 + (tid & 7) * 16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                ra[q] = (kk < K && mm + 4 * q < M) ? *reinterpret_cast<const float4*>(A + (int64_t)kk * lda + mm + 4 * q)
+                                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        if (BN) {
+            const int kk = k0 + (tid >> 3), nn = n0 + (tid & 7) * 16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                rb[q] = (kk < K && nn + 4 * q < N) ? *reinterpret_cast<const float4*>(Bm + (int64_t)kk * ldb + nn + 4 * q)
+                                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            const int r = tid >> 1, kk = k0 + (tid & 1) * 16;
+            const int gn = n0 + r;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                rb[q] = (gn < N && kk + 4 * q < K) ? *reinterpret_cast<const float4*>(Bm + (int64_t)gn * ldb + kk + 4 * q)
+                                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto store = [&]() {
+        if (AK) {
+            const int r = tid >> 1, kk = (tid & 1) * 16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                As[r][kk + 4 * q + 0] = f32_to_bf16(ra[q].x);
+                As[r][kk + 4 * q + 1] = f32_to_bf16(ra[q].y);
+                As[r][kk + 4 * q + 2] = f32_to_bf16(ra[q].z);
+                As[r][kk + 4 * q + 3] = f32_to_bf16(ra[q].w);
+            }
+        } else {
+            const int kk = tid >> 3, mm = (tid & 7) * 16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                As[mm + 4 * q + 0][kk] = f32_to_bf16(ra[q].x);
+                As[mm + 4 * q + 1][kk] = f32_to_bf16(ra[q].y);
+                As[mm + 4 * q + 2][kk] = f32_to_bf16(ra[q].z);
+                As[mm + 4 * q + 3][kk] = f32_to_bf16(ra[q].w);
+            }
+        }
+        if (BN) {
+            const int kk = tid >> 3, nn = (tid & 7) * 16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                Bs[nn + 4 * q + 0][kk] = f32_to_bf16(rb[q].x);
+                Bs[nn + 4 * q + 1][kk] = f32_to_bf16(rb[q].y);
+                Bs[nn + 4 * q + 2][kk] = f32_to_bf16(rb[q].z);
+                Bs[nn + 4 * q + 3][kk] = f32_to_bf16(rb[q].w);
+            }
+        } else {
+            const int r = tid >> 1, kk = (tid & 1) * 16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                Bs[r][kk + 4 * q + 0] = f32_to_bf16(rb[q].x);
+                Bs[r][kk + 4 * q + 1] = f32_to_bf16(rb[q].y);
+                Bs[r][kk + 4 * q + 2] = f32_to_bf16(rb[q].z);
+                Bs[r][kk + 4 * q + 3] = f32_to_bf16(rb[q].w);
+            }
+        }
+    };
+    f32x4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    const int kq = 4 * (lane >> 4);
+    load(0);
+    for (int k0 = 0; k0 < K; k0 += G2K) {
+        __syncthreads();   // the previous chunk's MFMAs are done with the tiles
+        store();
+        __syncthreads();
+        if (k0 + G2K < K) load(k0 + G2K);
+#pragma unroll
+        for (int ks = 0; ks < G2K; ks += 16) {
+            bf16x4_t a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = *reinterpret_cast<const bf16x4_t*>(&As[wm + 16 * i + (lane & 15)][ks + kq]);
+                b[i] = *reinterpret_cast<const bf16x4_t*>(&Bs[wn + 16 * i + (lane & 15)][ks + kq]);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // D layout: lane -> column (lane & 15), rows 4 * (lane >> 4) + r
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                const int gn = n0 + wn + 16 * j + (lane & 15);
+                if (gm < M && gn < N) {
+                    float v = acc[i][j][r];
+                    if (bias) v += bias[gn];
+                    float* cp = &C[(int64_t)gm * ldc + gn];
+                    *cp = beta ? (*cp + v) : v;
+                }
+            }
+}
+
+// S > 1: S splits of K (chunks of kc, a multiple of 32) side by side, split z writing C + z zc
+static hipError_t gemm_bf16_one(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk, int64_t sbn,
+                                float* C, int64_t ldc, int M, int N, int K, const float* bias, int beta, hipStream_t st,
+                                int S = 1, int kc = 0, int64_t zc = 0) {
+    if (S == 1) kc = K;
+    // the tiled kernel: large products whose operands are contiguous along one dimension,
+    // with 16-B aligned rows (K, M, N multiples of 4 where they are contiguous)
+    const bool big = M >= G2T && N >= G2T && kc >= G2K;
+    const bool ak = sak == 1, am = sam == 1, bn = sbn == 1, bk = sbk == 1;
+    auto al = [](const void* p, int64_t ld) { return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0); };
+    if (big && (ak || am) && (bn || bk) && (K % 4 == 0) && (M % 4 == 0) && (N % 4 == 0)) {
+        const int64_t lda = ak ? sam : sak, ldb = bn ? sbk : sbn;
+        if (al(A, lda) && al(B, ldb)) {
+            const dim3 g((N + G2T - 1) / G2T, (M + G2T - 1) / G2T, S);
+            if (ak && bn) hipLaunchKernelGGL((k_gemm2_bf16<true, true>), g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias, beta, kc, zc);
+            else if (ak) hipLaunchKernelGGL((k_gemm2_bf16<true, false>), g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias, beta, kc, zc);
+            else if (bn) hipLaunchKernelGGL((k_gemm2_bf16<false, true>), g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias, beta, kc, zc);
+            else hipLaunchKernelGGL((k_gemm2_bf16<false, false>), g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias, beta, kc, zc);
+            return hipGetLastError();
+        }
+    }
+    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, S);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, beta, kc, zc);
+    return hipGetLastError();
+}
+
+// split-K finish: C = sum_s part[s] (fixed order) (+ bias) (+ C if beta)
+__global__ void k_splitk_sum(const float* __restrict__ part, int S, int M, int N, float* __restrict__ C, int64_t ldc,
+                             const float* __restrict__ bias, int beta) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)M * N) return;
+    const int m = (int)(e / N), n = (int)(e % N);
+    float v = 0.f;
+    for (int k = 0; k < S; ++k) v += part[(int64_t)k * M * N + e];
+    if (bias) v += bias[n];
+    float* cp = &C[(int64_t)m * ldc + n];
+    *cp = beta ? (*cp + v) : v;
+}
+
+// C = A B (+ bias) (+ C): products with a long K and few output tiles (the weight
+// gradients, K = rows) are split along K into S chunks computed side by side into
+// `splitk` (S * M * N floats), then summed in chunk order.
 hipError_t launch_gemm_bf16(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk, int64_t sbn, float* C,
-                            int64_t ldc, int M, int N, int K, const float* bias, int beta, hipStream_t st) {
-    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
-    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, beta);
+                            int64_t ldc, int M, int N, int K, const float* bias, int beta, hipStream_t st,
+                            float* splitk, int64_t splitk_floats) {
+    const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+    int S = 1;
+    if (splitk && K >= 4096 && tiles < 256) {
+        S = (int)std::min<int64_t>(std::min<int64_t>(64, K / 256), splitk_floats / ((int64_t)M * N));
+        S = std::max(S, 1);
+    }
+    if (S == 1) return gemm_bf16_one(A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, beta, st);
+    const int chunk = ((K + S - 1) / S + 31) / 32 * 32;   // multiple of the tiled kernel's K chunk
+    const int s = (K + chunk - 1) / chunk;
+    hipError_t e = gemm_bf16_one(A, sam, sak, B, sbk, sbn, splitk, N, M, N, K, nullptr, 0, st, s, chunk, (int64_t)M * N);
+    if (e != hipSuccess) return e;
+    const int64_t mn = (int64_t)M * N;
+    hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, (const float*)splitk, s, M,
+                       N, C, ldc, bias, beta);
     return hipGetLastError();
 }
 
@@ -126,13 +333,30 @@ __global__ void k_mse(const float* __restrict__ O, const float* __restrict__ Tg,
     }
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
-// column sums of an M x N row-major matrix (bias gradients), fixed order per column
-__global__ void k_colsum(const float* __restrict__ X, int M, int N, float* __restrict__ out) {
+// Column sums of an M x N row-major matrix (bias gradients) in two fixed-order stages:
+// workgroup (bx, by) sums rows [by R, (by + 1) R) of columns 64 bx .. 64 bx + 63 (four row
+// lanes per column, combined in order) into part[by][n]; k_colsum_fin adds the CS_SPLIT
+// partials of each column in order.
+constexpr int CS_SPLIT = 64;
+__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ X, int M, int N, float* __restrict__ part) {
+    __shared__ float s[4][64];
+    const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + c;
+    const int R = (M + CS_SPLIT - 1) / CS_SPLIT;
+    const int m0 = blockIdx.y * R, m1 = min(M, m0 + R);
+    float acc = 0.f;
+    if (n < N)
+        for (int m = m0 + q; m < m1; m += 4) acc += X[(int64_t)m * N + n];
+    s[q][c] = acc;
+    __syncthreads();
+    if (q == 0 && n < N) part[(int64_t)blockIdx.y * N + n] = ((s[0][c] + s[1][c]) + s[2][c]) + s[3][c];
+}
+__global__ void k_colsum_fin(const float* __restrict__ part, int N, float* __restrict__ out) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
-    float s = 0.f;
-    for (int m = 0; m < M; ++m) s += X[(int64_t)m * N + n];
-    out[n] = s;
+    float acc = 0.f;
+    for (int k = 0; k < CS_SPLIT; ++k) acc += part[(int64_t)k * N + n];
+    out[n] = acc;
 }
 // Adam (bias-corrected), FP32 master weights
 __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m1, float* __restrict__ m2,
@@ -159,8 +383,10 @@ hipError_t launch_mse(const float* O, const float* T, float* dO, int64_t n, floa
     hipLaunchKernelGGL(k_mse, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, O, T, dO, n, scale, part);
     return hipGetLastError();
 }
-hipError_t launch_colsum(const float* X, int M, int N, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, st, X, M, N, out);
+// part: CS_SPLIT * N floats of scratch
+hipError_t launch_colsum(const float* X, int M, int N, float* out, float* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64, CS_SPLIT), dim3(256), 0, st, X, M, N, part);
+    hipLaunchKernelGGL(k_colsum_fin, dim3((N + 255) / 256), dim3(256), 0, st, (const float*)part, N, out);
     return hipGetLastError();
 }
 hipError_t launch_adam(float* w, const float* g, float* m1, float* m2, int64_t n, float lr, float b1, float b2,
@@ -335,15 +561,30 @@ __global__ __launch_bounds__(MI_NT) void k_mlp_infer(const float* __restrict__ X
         f32x4_t acc[MI_R / 16];
 #pragma unroll
         for (int i = 0; i < MI_R / 16; ++i) acc[i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-        bf16x4_t bn = *reinterpret_cast<const bf16x4_t*>(bsrc);
-        for (int k0 = 0; k0 < HID; k0 += 16) {
-            const bf16x4_t b = bn;
-            if (k0 + 16 < HID) bn = *reinterpret_cast<const bf16x4_t*>(bsrc + k0 + 16);
+        // B fragments in groups of 8 sixteen-steps of K: the next group's 8 loads are in
+        // flight while the current group's MFMAs run (one L2 round trip per group)
+        constexpr int GRP = 8;
+        bf16x4_t cur[GRP], nxt[GRP];
 #pragma unroll
-            for (int i = 0; i < MI_R / 16; ++i) {
-                const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(&A1[(16 * i + (lane & 15)) * LDA + k0 + kq]);
-                acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i], 0, 0, 0);
+        for (int k = 0; k < GRP; ++k) cur[k] = *reinterpret_cast<const bf16x4_t*>(bsrc + 16 * k);
+#pragma unroll 1
+        for (int k0 = 0; k0 < HID; k0 += 16 * GRP) {
+            if (k0 + 16 * GRP < HID) {
+#pragma unroll
+                for (int k = 0; k < GRP; ++k)
+                    nxt[k] = *reinterpret_cast<const bf16x4_t*>(bsrc + k0 + 16 * GRP + 16 * k);
             }
+#pragma unroll
+            for (int k = 0; k < GRP; ++k) {
+#pragma unroll
+                for (int i = 0; i < MI_R / 16; ++i) {
+                    const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(
+                        &A1[(16 * i + (lane & 15)) * LDA + k0 + 16 * k + kq]);
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, cur[k], acc[i], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < GRP; ++k) cur[k] = nxt[k];
         }
         // epilogue: lane holds Z2[16 i + 4 (lane >> 4) + r][col]
         const float bz = b2[col];
@@ -434,6 +675,9 @@ struct Mlp {
     int64_t nparam;
     float *w = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;
     float *Z1, *A1, *Z2, *A2, *O, *dO, *dA2, *dZ2, *dA1, *dZ1, *part;
+    float* cpart = nullptr;                   // column-sum partials (CS_SPLIT x widest layer)
+    float* splitk = nullptr;                  // split-K partial products of the weight gradients
+    int64_t splitk_floats = 0;
     float *w1r = nullptr, *w3r = nullptr;     // fused inference: BF16-rounded W1, W3
     unsigned short* w2t = nullptr;            // and W2 transposed as BF16
     bool fused = false;                       // shape served by k_mlp_infer
@@ -461,14 +705,14 @@ using namespace cdm;
 static hipError_t mlp_forward(cdm_mlp* n, const float* X, int rows, hipStream_t st) {
     hipError_t e;
     float* w = n->w;
-    if ((e = launch_gemm_bf16(X, n->nin, 1, w + n->oW1, n->h1, 1, n->Z1, n->h1, rows, n->h1, n->nin, w + n->ob1, 0, st)))
+    if ((e = launch_gemm_bf16(X, n->nin, 1, w + n->oW1, n->h1, 1, n->Z1, n->h1, rows, n->h1, n->nin, w + n->ob1, 0, st, n->splitk, n->splitk_floats)))
         return e;
     if ((e = launch_relu(n->Z1, n->A1, (int64_t)rows * n->h1, st))) return e;
-    if ((e = launch_gemm_bf16(n->A1, n->h1, 1, w + n->oW2, n->h2, 1, n->Z2, n->h2, rows, n->h2, n->h1, w + n->ob2, 0, st)))
+    if ((e = launch_gemm_bf16(n->A1, n->h1, 1, w + n->oW2, n->h2, 1, n->Z2, n->h2, rows, n->h2, n->h1, w + n->ob2, 0, st, n->splitk, n->splitk_floats)))
         return e;
     if ((e = launch_relu(n->Z2, n->A2, (int64_t)rows * n->h2, st))) return e;
     return launch_gemm_bf16(n->A2, n->h2, 1, w + n->oW3, n->nout, 1, n->O, n->nout, rows, n->nout, n->h2, w + n->ob3,
-                            0, st);
+                            0, st, n->splitk, n->splitk_floats);
 }
 
 // gradients of the mean squared error (1 / (rows * nout)) sum (O - T)^2 into n->g
@@ -479,23 +723,23 @@ static hipError_t mlp_backward(cdm_mlp* n, const float* X, const float* T, int r
     const int64_t no = (int64_t)rows * n->nout;
     if ((e = launch_mse(n->O, T, n->dO, no, 1.f / (float)no, n->part, st))) return e;
     // layer 3
-    if ((e = launch_gemm_bf16(n->A2, 1, n->h2, n->dO, n->nout, 1, g + n->oW3, n->nout, n->h2, n->nout, rows, nullptr, 0, st)))
+    if ((e = launch_gemm_bf16(n->A2, 1, n->h2, n->dO, n->nout, 1, g + n->oW3, n->nout, n->h2, n->nout, rows, nullptr, 0, st, n->splitk, n->splitk_floats)))
         return e;
-    if ((e = launch_colsum(n->dO, rows, n->nout, g + n->ob3, st))) return e;
-    if ((e = launch_gemm_bf16(n->dO, n->nout, 1, w + n->oW3, 1, n->nout, n->dA2, n->h2, rows, n->h2, n->nout, nullptr, 0, st)))
+    if ((e = launch_colsum(n->dO, rows, n->nout, g + n->ob3, n->cpart, st))) return e;
+    if ((e = launch_gemm_bf16(n->dO, n->nout, 1, w + n->oW3, 1, n->nout, n->dA2, n->h2, rows, n->h2, n->nout, nullptr, 0, st, n->splitk, n->splitk_floats)))
         return e;
     if ((e = launch_relu_bwd(n->Z2, n->dA2, n->dZ2, (int64_t)rows * n->h2, st))) return e;
     // layer 2
-    if ((e = launch_gemm_bf16(n->A1, 1, n->h1, n->dZ2, n->h2, 1, g + n->oW2, n->h2, n->h1, n->h2, rows, nullptr, 0, st)))
+    if ((e = launch_gemm_bf16(n->A1, 1, n->h1, n->dZ2, n->h2, 1, g + n->oW2, n->h2, n->h1, n->h2, rows, nullptr, 0, st, n->splitk, n->splitk_floats)))
         return e;
-    if ((e = launch_colsum(n->dZ2, rows, n->h2, g + n->ob2, st))) return e;
-    if ((e = launch_gemm_bf16(n->dZ2, n->h2, 1, w + n->oW2, 1, n->h2, n->dA1, n->h1, rows, n->h1, n->h2, nullptr, 0, st)))
+    if ((e = launch_colsum(n->dZ2, rows, n->h2, g + n->ob2, n->cpart, st))) return e;
+    if ((e = launch_gemm_bf16(n->dZ2, n->h2, 1, w + n->oW2, 1, n->h2, n->dA1, n->h1, rows, n->h1, n->h2, nullptr, 0, st, n->splitk, n->splitk_floats)))
         return e;
     if ((e = launch_relu_bwd(n->Z1, n->dA1, n->dZ1, (int64_t)rows * n->h1, st))) return e;
     // layer 1
-    if ((e = launch_gemm_bf16(X, 1, n->nin, n->dZ1, n->h1, 1, g + n->oW1, n->h1, n->nin, n->h1, rows, nullptr, 0, st)))
+    if ((e = launch_gemm_bf16(X, 1, n->nin, n->dZ1, n->h1, 1, g + n->oW1, n->h1, n->nin, n->h1, rows, nullptr, 0, st, n->splitk, n->splitk_floats)))
         return e;
-    return launch_colsum(n->dZ1, rows, n->h1, g + n->ob1, st);
+    return launch_colsum(n->dZ1, rows, n->h1, g + n->ob1, n->cpart, st);
 }
 
 extern "C" {
@@ -521,7 +765,12 @@ int32_t cdm_mlp_create(int32_t nin, int32_t h1, int32_t h2, int32_t nout, int32_
     n->fused = nin <= 16 && h1 == h2 && (h1 == 256 || h1 == 512) && nout == 2;
     // fused inference weights: nin*h1 + 2*h2 floats and h1*h2 BF16 (as floats: half of it)
     const int64_t fw = n->fused ? (int64_t)nin * h1 + 2 * (int64_t)h2 + ((int64_t)h1 * h2 + 1) / 2 + 64 : 0;
-    const int64_t fl = 4 * n->nparam + R * (4 * (int64_t)h1 + 4 * (int64_t)h2 + 2 * nout) + (R * nout + 255) / 256 + 64 + fw;
+    const int64_t wmax = std::max<int64_t>(std::max(h1, h2), nout);
+    // split-K scratch: up to 64 partial copies of the largest weight block
+    const int64_t wblk = std::max<int64_t>(std::max<int64_t>((int64_t)nin * h1, (int64_t)h1 * h2), (int64_t)h2 * nout);
+    const int64_t skf = (R >= 4096) ? std::min<int64_t>(64, R / 256) * wblk : 0;
+    const int64_t fl = 4 * n->nparam + R * (4 * (int64_t)h1 + 4 * (int64_t)h2 + 2 * nout) + (R * nout + 255) / 256 + 64 + fw +
+                       CS_SPLIT * wmax + skf + 64;
     if (hipMalloc(&n->ws, sizeof(float) * fl) != hipSuccess) {
         delete n;
         return CDM_ENOMEM;
@@ -542,6 +791,10 @@ int32_t cdm_mlp_create(int32_t nin, int32_t h1, int32_t h2, int32_t nout, int32_
     n->O = p; p += R * nout;
     n->dO = p; p += R * nout;
     n->part = p; p += (R * nout + 255) / 256 + 64;
+    n->cpart = p; p += CS_SPLIT * wmax;
+    n->splitk = skf ? p : nullptr;
+    n->splitk_floats = skf;
+    p += skf;
     if (n->fused) {
         n->w1r = p; p += (int64_t)nin * h1;
         n->w3r = p; p += 2 * (int64_t)h2 + 64;

@@ -84,6 +84,30 @@ def test_gradients_vs_oracle(dev, mo, rows):
     net.close()
 
 
+@pytest.mark.parametrize("rows", [300, 512, 130, 8192])
+def test_gradients_vs_oracle_wide(dev, mo, rows):
+    """Widths 256 take the 128 x 128 tiled GEMM for the products with M, N >= 128 (the
+    layer-2 forward, dW2 when the row count is a multiple of 4, dA1): same bars as the
+    narrow network; 300 and 130 rows leave ragged tiles (130 also sends dW2 back to the
+    generic kernel); 8192 rows split the weight gradients along K (8 chunks summed in
+    order)."""
+    shape = (8, 256, 256, 2)
+    from paper_1902_08653_amd import cdm
+    net = cdm.Mlp(*shape, max_rows=max(rows, 512))
+    w = (np.random.default_rng(3).standard_normal(net.nparam) * 0.3).astype(np.float32)
+    net.set_weights(w)
+    X, T = data(rows, shape[0], shape[3], 300 + rows)
+    g, parts = net.gradients(torch.from_numpy(X).to(dev), torch.from_numpy(T).to(dev))
+    Y = net.forward(torch.from_numpy(X).to(dev))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    want = mo.gradients(w.astype(np.float64), shape, X, T, bf16=True)
+    for got_b, want_b in zip(mo.split(g, shape), mo.split(want, shape)):
+        assert relerr(got_b, want_b) <= 2e-3
+    assert relerr(Y.cpu().numpy().astype(np.float64), mo.forward(w.astype(np.float64), shape, X, bf16=True)["Y"]) <= 1e-4
+    net.close()
+
+
 def test_train_steps_match_adam(dev, mo):
     net, w = make_net(seed=2)
     lr = 1e-3
