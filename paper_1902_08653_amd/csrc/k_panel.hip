@@ -588,7 +588,10 @@ hipError_t launch_gram(const GramLaunch& L, hipStream_t st) {
 
 // X[i] = sum over splits of part[s][i], fixed order
 template <typename V>
-__global__ void k_sum_splits(const V* __restrict__ part, int nsplit, int64_t n, V* __restrict__ X) {
+// X (one kp x kp block per panel) = sum of the split partials, written transposed:
+// element (j, v) of block K lands at (K, v, j), so that a product X_K delta reads
+// consecutive j for consecutive lanes
+__global__ void k_sum_splits(const V* __restrict__ part, int nsplit, int64_t n, int kp, V* __restrict__ X) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     V s = part[i];
@@ -597,7 +600,10 @@ __global__ void k_sum_splits(const V* __restrict__ part, int nsplit, int64_t n, 
         s.x += p.x;
         s.y += p.y;
     }
-    X[i] = s;
+    const int64_t kk = (int64_t)kp * kp;
+    const int64_t blk = i / kk, rem = i % kk;
+    const int j = (int)(rem / kp), v = (int)(rem % kp);
+    X[blk * kk + (int64_t)v * kp + j] = s;
 }
 
 template <typename T> static hipError_t launch_gram_cross_t(const GramLaunch& L, void* X, hipStream_t st) {
@@ -623,7 +629,7 @@ template <typename T> static hipError_t launch_gram_cross_t(const GramLaunch& L,
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)L.npanels * L.kp * L.kp;
     hipLaunchKernelGGL(k_sum_splits<cv<T>>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       (const cv<T>*)L.gpart, L.nsplit, n, (cv<T>*)X);
+                       (const cv<T>*)L.gpart, L.nsplit, n, L.kp, (cv<T>*)X);
     return hipGetLastError();
 }
 

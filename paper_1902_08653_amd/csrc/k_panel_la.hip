@@ -8,6 +8,12 @@
 //     X_{K+1} = H_{K+1}^H H_K  (formed once per solve, next to M).
 // The exchange of panel K+1's partials thereby overlaps the wait for panel K's
 // reduced b.  In exact arithmetic every delta equals the sequential sweep's.
+// Where X_K fits the LDS next to M (complex128, 64-column panels) the reducers publish
+// q_K = H_K^H r - lambda x_K as soon as the partials are in, and every workgroup forms
+// b_K = q_K - X_K delta_{K-1} itself from X_K staged in LDS: the chain from one panel's
+// delta to the next panel's then stays inside the workgroup, and the cross-workgroup
+// exchange runs a panel ahead of it.  Otherwise (64 KB of X_K would not fit) the
+// reducers apply the correction and publish b_K.
 //
 // Workgroup: 8 tile waves and one control wave, decoupled.
 //  * Tile waves own the rows (lane = row) and NC panel columns each.  They keep
@@ -109,6 +115,7 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
     constexpr int NE = KP * (KP + 1) / 2;       // packed lower triangle of M_K
     constexpr int NS = 64 * LA_NWT / KP;        // matvec slices per row (tile threads)
     constexpr int KL = (KP + 63) / 64;          // panel entries per control lane
+    constexpr bool LOCALB = (int)sizeof(V) * KP * KP <= 64 * 1024;   // X_K in LDS, b formed locally
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -132,6 +139,8 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
     __shared__ V xsh[2][KP];                    // x of the step's panel before its update
     __shared__ V dsh[2][KP];                    // delta of the step's panel
     __shared__ V dpart[NS][KP];
+    // X_K (transposed: column v at v * KP) for the local correction of b
+    __shared__ __attribute__((aligned(16))) V Xs[LOCALB ? KP * KP : 1];
     __shared__ V axs[LA_NWT][RPL][64];
     // LDS words: b_ready = (last step whose b, x and M are in LDS) + 1; d_ready = (last
     // step whose delta is in dsh) + 1; p_done[k] = partial panels written by tile wave
@@ -252,6 +261,32 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
 #define CDM_LA_TSTEP(cur, nn)                                                                         \
     {                                                                                                 \
         if (!wait_b(q)) goto tdone;                                                                   \
+        if constexpr (LOCALB) {                                                                       \
+            if (q > 0) { /* b = q_K - X_K delta_{K-1} (the first panel of the solve has no correction) */ \
+                constexpr int SX = KP / NS;                                                           \
+                const V* dp = dsh[(q - 1) & 1];                                                       \
+                const int j = tid % KP, v0 = (tid / KP) * SX;                                         \
+                V c0 = czero<T>(), c1 = czero<T>();                                                   \
+                for (int v = v0; v < v0 + SX; v += 2) {                                               \
+                    cfma(c0, Xs[v * KP + j], dp[v]);                                                  \
+                    cfma(c1, Xs[(v + 1) * KP + j], dp[v + 1]);                                        \
+                }                                                                                     \
+                dpart[tid / KP][j] = cmake<T>(c0.x + c1.x, c0.y + c1.y);                              \
+                tbar();                                                                               \
+                if (bad) goto tdone;                                                                  \
+                if (tid < KP) {                                                                       \
+                    V s_ = dpart[0][tid];                                                             \
+                    for (int k = 1; k < NS; ++k) {                                                    \
+                        s_.x += dpart[k][tid].x;                                                      \
+                        s_.y += dpart[k][tid].y;                                                      \
+                    }                                                                                 \
+                    bsh[q & 1][tid].x -= s_.x;                                                        \
+                    bsh[q & 1][tid].y -= s_.y;                                                        \
+                }                                                                                     \
+                tbar();                                                                               \
+                if (bad) goto tdone;                                                                  \
+            }                                                                                         \
+        }                                                                                             \
         {   /* delta = M_K b; column v of the packed M holds rows v..KP-1 at offset v*KP - v(v-1)/2 */ \
             constexpr int SV = KP / NS;                                                               \
             const V* Mq = Ms[q & 1];                                                                  \
@@ -477,6 +512,20 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
             __builtin_amdgcn_global_load_lds(src + off, (__attribute__((address_space(3))) void*)(dst + off), 16, 0, 0);
     };
 
+    auto stage_X = [&](int K) {
+        if constexpr (LOCALB) {
+            const char* src = reinterpret_cast<const char*>(a.X + (int64_t)K * KP * KP) + lane * 16;
+            char* dst = reinterpret_cast<char*>(Xs);
+#pragma unroll 4
+            for (int off = 0; off < KP * KP * (int)sizeof(V); off += 1024)
+                __builtin_amdgcn_global_load_lds(src + off, (__attribute__((address_space(3))) void*)(dst + off), 16, 0,
+                                                 0);
+        }
+    };
+    // LOCALB: the reducers publish q of the next panel before this step's delta unless the
+    // next panel is this one (a single panel), whose x this step still changes
+    const bool early = LOCALB && np > 1;
+
     int state = 0;   // 0 running, 1 stopped (converged or T_max), 2 abandoned
     if (a.T_max >= 1) {
         // prologue: partials of panels 0 and 1 (both from r0); b of panel 0 (no correction)
@@ -496,17 +545,25 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
             // finished step q - 2, whose delta this wave has already seen)
             stage_M(K, q & 1);
             V xr[KL];
-            if (reducer) {
+            if (!LOCALB && reducer) {   // row w of X_{K+1} (stored transposed)
 #pragma unroll
                 for (int i = 0; i < KL; ++i) {
                     const int v = lane + 64 * i;
-                    xr[i] = (v < KP) ? a.X[((int64_t)K1 * KP + w) * KP + v] : czero<T>();
+                    xr[i] = (v < KP) ? a.X[((int64_t)K1 * KP + v) * KP + w] : czero<T>();
                 }
             }
             ok = gather_b(q);
             if (!ok) break;
-            wave_drain_vmem();   // the LDS-direct loads of M_K have landed
+            wave_drain_vmem();   // the LDS-direct loads of M_K (and X_K) have landed
             if (lane == 0) lds_set(&b_ready, q + 1);
+            // LOCALB reducer: q of panel K+1 from its look-ahead partials (published one
+            // step ago), while this workgroup's tile waves work on panel K
+            if (early && reducer) {
+                V g;
+                ok = gather_partials(q + 1, g);
+                if (!ok) break;
+                publish_b(K1, q + 1, g);
+            }
             // statistics and x of panel K once the tile waves have delta
             ok = wait_delta(q);
             if (!ok) break;
@@ -547,8 +604,9 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
                 }
             }
             // reducer: b of panel K+1 = (sum of its look-ahead partials) - X_{K+1} delta_K
-            // - lambda x (the partials were published one step ago)
-            if (reducer) {
+            // - lambda x (the partials were published one step ago); with LOCALB and a
+            // single panel, q of the next sweep's panel once this step's x is written
+            if (!LOCALB && reducer) {
                 V g;
                 ok = gather_partials(q + 1, g);
                 if (!ok) break;
@@ -561,7 +619,14 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
                 c.x = wave_allsum(c.x);
                 c.y = wave_allsum(c.y);
                 publish_b(K1, q + 1, cmake<T>(g.x - c.x, g.y - c.y));
+            } else if (LOCALB && !early && reducer) {
+                V g;
+                ok = gather_partials(q + 1, g);
+                if (!ok) break;
+                publish_b(K1, q + 1, g);
             }
+            // X of panel K+1 into LDS: this step's delta, its last use of X_K, is done
+            stage_X(K1);
             // the tile waves' partials of panel K+2 (sequence q + 2)
             ok = wait_parts(q + 3);
             if (!ok) break;

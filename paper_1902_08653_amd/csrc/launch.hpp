@@ -117,7 +117,8 @@ struct PanelLaunch {
     const void* r0;      // initial residual (B)
     void* x;             // in: x^(0) (U), out: x^(T)
     const void* M;       // [npanels][kp*(kp+1)/2] packed lower (D + L)^-1 per panel, column by column
-    const void* X = nullptr;  // look-ahead: [npanels][kp][kp] X_K = H_K^H H_{K-1 mod npanels}, row-major
+    const void* X = nullptr;  // look-ahead: [npanels][kp][kp] X_K = H_K^H H_{K-1 mod npanels}, transposed
+                              // (element (j, v) of X_K at (K, v, j))
     void* part;          // [2][kp][P] partial dot products
     void* gbuf;          // [2][kp][2] reduced right-hand sides and old x
     uint32_t* ctr;       // [2] abort, [3] status word, [16..) arrival flags
@@ -155,7 +156,7 @@ struct GramLaunch {
     double lambda;
 };
 hipError_t launch_gram(const GramLaunch& L, hipStream_t st);
-// Cross blocks X_K = H_K^H H_{K-1 mod npanels} (full kp x kp, row-major) into X,
+// Cross blocks X_K = H_K^H H_{K-1 mod npanels} (full kp x kp, transposed) into X,
 // using gpart as split scratch (call after launch_gram: its contents are consumed).
 hipError_t launch_gram_cross(const GramLaunch& L, void* X, hipStream_t st);
 
