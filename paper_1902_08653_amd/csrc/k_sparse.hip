@@ -5,13 +5,14 @@
 // (an integer step: counts, prefix sum, atomic fill, then a per-column sort by
 // row, which makes the result unique and independent of the fill order).
 //
-// The sweep runs in ONE workgroup (the whole operator is a few tens of MB and the
-// dependent chain is the bottleneck, not bandwidth).  Columns are taken in panels
-// of 64 whose mutual coupling is resolved exactly with the panel Gram blocks of
-// the sparse columns (row-list intersections) -- the same block form of the
-// cyclic sweep as the dense panel engine: delta_K = (D + L)^-1 (g_K - lambda x_K).
-// The residual r lives in global memory and is updated with atomic adds, since
-// the columns of one panel may share rows.
+// Columns are taken in panels of 64 whose mutual coupling is resolved exactly with
+// the panel Gram blocks of the sparse columns (row-list intersections) -- the same
+// block form of the cyclic sweep as the dense panel engine:
+// delta_K = (D + L)^-1 (g_K - lambda x_K).  The sweep is spread over row slices, one
+// workgroup each, that hold their part of the residual in LDS; a panel costs each
+// workgroup a few hundred stored entries and one exchange of 64 partial sums.
+#include <algorithm>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -165,156 +166,513 @@ __global__ __launch_bounds__(256) void k_sparse_gram(const int32_t* __restrict__
     }
 }
 
-// ---- the sweep ---------------------------------------------------------------
-constexpr int SP_NT = 1024;
-constexpr int SP_KP = 64;
-constexpr int SP_NW = SP_NT / 64;            // 16 waves
-constexpr int SP_CPW = SP_KP / SP_NW;        // 4 columns per wave
+// ---- row slices of the column-compressed form --------------------------------
+// spt[s * U + u] = first entry of column u whose row is >= s * R (s = 0..P), so the
+// entries of column u inside row slice s are [spt[s*U+u], spt[(s+1)*U+u]).
+__global__ void k_sparse_slices(const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx, int B,
+                                int U, int P, int R, int32_t* __restrict__ spt) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)(P + 1) * U) return;
+    const int s = (int)(k / U), u = (int)(k % U);
+    const int64_t bound = min((int64_t)s * R, (int64_t)B);
+    int32_t lo = colptr[u], hi = colptr[u + 1];
+    while (lo < hi) {                       // lower bound of `bound` in the sorted rows
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (rowidx[mid] < bound) lo = mid + 1; else hi = mid;
+    }
+    spt[k] = lo;
+}
 
-// The residual is changed only by this workgroup's device-scope atomic adds; it is
-// read back with device-coherent loads (ld_dev), so no stale cached copy is used.
-template <typename T>
-__global__ __launch_bounds__(SP_NT) void k_cd_sparse(const int32_t* __restrict__ colptr,
-                                                     const int32_t* __restrict__ rowidx,
-                                                     const cv<T>* __restrict__ cval, cv<T>* __restrict__ r,
-                                                     cv<T>* __restrict__ x, const cv<T>* __restrict__ M, int U,
-                                                     int npanels, double lambda_d, int T_max, double tol,
-                                                     cdm_info* __restrict__ info) {
+// ---- the sweep ---------------------------------------------------------------
+// P workgroups, one per slice of R consecutive rows (antennas).  Each keeps its slice
+// of r in LDS for the whole solve and walks the panels of 64 columns in order:
+//   1. partial  p_s = H_{K,s}^H r_s  (its rows only; entries prefetched a panel ahead)
+//   2. exchange: every workgroup publishes p_s and reads all P partials (tagged words,
+//      one memory round trip), summing them in slice order, so every workgroup holds
+//      the same b_K = sum_s p_s - lambda x_K bit for bit;
+//   3. delta_K = (D + L)^-1 b_K and x_K += delta_K, computed redundantly everywhere;
+//   4. r_s -= H_{K,s} delta_K through the row-ordered input (one thread per row: no
+//      two threads touch one r entry, no atomics).
+// The stopping sums are formed from the identical deltas, so all workgroups stop
+// after the same sweep.  Each workgroup keeps a private copy of x (xp).
+namespace {
+
+// Tagged words: a 32-bit payload and a 32-bit tag (panel sequence + 1) in one 64-bit
+// word, stored and loaded single-copy atomically at agent scope; a value whose words
+// all carry the expected tag has arrived.  The buffer is cleared before each launch.
+__device__ __forceinline__ void sp_st(uint64_t* p, uint32_t payload, uint32_t tag) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), ((unsigned long long)tag << 32) | payload,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t sp_ld(const uint64_t* p) {
+    return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T> struct SpTag;
+template <> struct SpTag<double> {
+    static constexpr int NW = 4;
+    __device__ static void put(uint64_t* p, double2 v, uint32_t tag) {
+        const unsigned long long a = __double_as_longlong(v.x), b = __double_as_longlong(v.y);
+        sp_st(p + 0, (uint32_t)a, tag);
+        sp_st(p + 1, (uint32_t)(a >> 32), tag);
+        sp_st(p + 2, (uint32_t)b, tag);
+        sp_st(p + 3, (uint32_t)(b >> 32), tag);
+    }
+    __device__ static bool decode(const uint64_t (&wd)[4], uint32_t tag, double2& v) {
+        const uint64_t w0 = wd[0], w1 = wd[1], w2 = wd[2], w3 = wd[3];
+        const bool ok = ((uint32_t)(w0 >> 32) == tag) & ((uint32_t)(w1 >> 32) == tag) &
+                        ((uint32_t)(w2 >> 32) == tag) & ((uint32_t)(w3 >> 32) == tag);
+        v.x = __longlong_as_double((long long)(((w1 & 0xffffffffull) << 32) | (w0 & 0xffffffffull)));
+        v.y = __longlong_as_double((long long)(((w3 & 0xffffffffull) << 32) | (w2 & 0xffffffffull)));
+        return ok;
+    }
+};
+template <> struct SpTag<float> {
+    static constexpr int NW = 2;
+    __device__ static void put(uint64_t* p, float2 v, uint32_t tag) {
+        sp_st(p + 0, __float_as_uint(v.x), tag);
+        sp_st(p + 1, __float_as_uint(v.y), tag);
+    }
+    __device__ static bool decode(const uint64_t (&wd)[2], uint32_t tag, float2& v) {
+        const uint64_t w0 = wd[0], w1 = wd[1];
+        const bool ok = ((uint32_t)(w0 >> 32) == tag) & ((uint32_t)(w1 >> 32) == tag);
+        v.x = __uint_as_float((uint32_t)w0);
+        v.y = __uint_as_float((uint32_t)w1);
+        return ok;
+    }
+};
+
+template <typename T> __device__ __forceinline__ T sp_quad_sum(T v) {
+    v += dpp_take<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v += dpp_take<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+    return v;
+}
+
+}  // namespace
+
+constexpr int SR_NT = 256;                // 4 waves
+constexpr int SR_KP = 64;                 // panel width
+constexpr int SR_G = SR_NT / SR_KP;       // threads per column in the partial (a quad)
+constexpr int SR_EG = 4;                  // block entries per thread held in registers
+constexpr int SR_SC = 4;                  // slices read per exchange attempt (per thread)
+constexpr int SR_CAP = 1024;              // scatter staging (block entries per pass)
+constexpr int SR_RMAX = SR_NT * 16;       // largest slice
+
+// ---- row order inside each (slice, panel) block --------------------------------
+// The entries of block (s, K) -- rows of slice s, columns of panel K -- are held by the
+// sweep in column order.  pi[e] is entry e's position in the block's (row, column)
+// order, so that the update r -= H delta can add each row's terms in a fixed order.
+// Stored with the entry's row inside the slice: pk[e] = pi << 12 | (row - s * R)
+// (R <= 4096, and a block holds at most 64 R entries).  bcnt[s * npanels + K] is the
+// block's entry count.  One workgroup per block: count
+// the entries per row, prefix-sum, then place the columns one after another (the rows
+// of one column are distinct, so each row's next slot is taken at most once per step).
+__global__ __launch_bounds__(256) void k_sparse_rank(const int32_t* __restrict__ rowidx,
+                                                     const int32_t* __restrict__ spt, int U, int npanels,
+                                                     int R, int32_t* __restrict__ pk, int32_t* __restrict__ bcnt) {
+    __shared__ int32_t cnt[SR_RMAX], fill[SR_RMAX];
+    __shared__ int32_t wsum[256 / 64];
+    const int s = blockIdx.x / npanels, K = blockIdx.x % npanels;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int row0 = s * R;
+    for (int i = tid; i < R; i += 256) cnt[i] = 0;
+    __syncthreads();
+    const int ncol = min(SR_KP, U - K * SR_KP);
+    for (int c = 0; c < ncol; ++c) {
+        const int u = K * SR_KP + c;
+        const int32_t lo = spt[(int64_t)s * U + u], hi = spt[(int64_t)(s + 1) * U + u];
+        for (int32_t e = lo + tid; e < hi; e += 256) atomicAdd(&cnt[rowidx[e] - row0], 1);
+    }
+    __syncthreads();
+    // exclusive prefix sum of cnt[0..R) into fill (each thread a contiguous run)
+    const int per = (R + 255) / 256;
+    const int i0 = min(R, tid * per), i1 = min(R, i0 + per);
+    int32_t run = 0;
+    for (int i = i0; i < i1; ++i) run += cnt[i];
+    int32_t incl = run;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const int32_t o = __shfl_up(incl, m, 64);
+        if (lane >= m) incl += o;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int32_t base = incl - run;
+    for (int k = 0; k < w; ++k) base += wsum[k];
+    for (int i = i0; i < i1; ++i) {
+        fill[i] = base;
+        base += cnt[i];
+    }
+    if (tid == 255) bcnt[(int64_t)s * npanels + K] = base;
+    __syncthreads();
+    for (int c = 0; c < ncol; ++c) {
+        const int u = K * SR_KP + c;
+        const int32_t lo = spt[(int64_t)s * U + u], hi = spt[(int64_t)(s + 1) * U + u];
+        for (int32_t e = lo + tid; e < hi; e += 256) {
+            const int r = rowidx[e] - row0;
+            pk[e] = (fill[r] << 12) | r;
+            fill[r] += 1;
+        }
+        __syncthreads();
+    }
+}
+
+struct SparseRsArgs {
+    const void* cval;        // column-compressed values (rows ascending per column)
+    const int32_t* pk;       // row-order position in the block << 12 | row in the slice
+    const int32_t* spt;      // [P+1][U] slice pointers
+    const int32_t* bcnt;     // [P][npanels] block entry counts
+    const void* M;           // [npanels] packed (D + L)^-1, column-major lower
+    const void* r0;          // r = y - H x0 (B)
+    void* x;                 // in: x0 (U); out: x
+    void* xp;                // [P][U] private copies of x
+    uint64_t* xbuf;          // [2][P][64][NW] tagged partials
+    uint32_t* abort_flag;
+    cdm_info* info;
+    int64_t nnz;
+    int B, U, npanels, R, T_max;
+    double lambda, tol;
+    uint64_t tmo;
+};
+
+// Every prefetch below is an unconditional load from a clamped (in-bounds) index whose
+// validity is decided where the value is used, so no load waits for another.
+template <typename T, int RPT>
+__global__ __launch_bounds__(SR_NT) void k_cd_sparse(const SparseRsArgs a) {
     using V = cv<T>;
-    constexpr int NE = SP_KP * (SP_KP + 1) / 2;
-    constexpr int NS = SP_NT / SP_KP;       // matvec slices per row
-    constexpr int SV = SP_KP / NS;
+    using TG = SpTag<T>;
+    constexpr int NT = SR_NT, KP = SR_KP, NE = KP * (KP + 1) / 2, NWV = NT / 64, NW = TG::NW;
+    constexpr int MPT = (NE + NT - 1) / NT;
+    constexpr int VPW = KP / NWV;          // matvec columns per wave
+    __shared__ V rs[NT * RPT];
     __shared__ V Ms[NE];
-    __shared__ V bsh[SP_KP], xsh[SP_KP], dsh[SP_KP];
-    __shared__ V dpart[NS][SP_KP];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const T lambda = (T)lambda_d;
+    __shared__ V part[NWV][KP];
+    __shared__ V bsh[KP], dsh[KP];
+    __shared__ V cbuf[SR_CAP];
+    __shared__ int32_t rbuf[SR_CAP];
+    __shared__ double stop_s[2];
+    __shared__ int fail_s;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int s = blockIdx.x, P = gridDim.x;
+    const int U = a.U, np = a.npanels;
+    const int row0 = s * a.R;
+    const int nrow = max(0, min(a.R, a.B - row0));
+    const int32_t ncsc = (int32_t)max(a.nnz, (int64_t)1) - 1;   // last valid internal entry
+    const int32_t* __restrict__ pkg = a.pk;
+    const int32_t* __restrict__ spt = a.spt;
+    const V* __restrict__ cval = (const V*)a.cval;
+    const V* __restrict__ Mg = (const V*)a.M;
+    V* xp = (V*)a.xp + (int64_t)s * U;
+    const T lambda = (T)a.lambda;
+
+    for (int i = tid; i < nrow; i += NT) rs[i] = ((const V*)a.r0)[row0 + i];
+    for (int u = tid; u < U; u += NT) xp[u] = ((const V*)a.x)[u];
+    if (tid == 0) fail_s = 0;
+
+    // block mapping: column jl = tid / 4, quad member gq.  An empty range stands for a
+    // padding column (u >= U).
+    const int jl = tid >> 2, gq = tid & 3;
+    auto ptrs = [&](int K, int32_t& lo, int32_t& hi) {
+        const int u = min(K * KP + jl, U - 1);
+        lo = spt[(int64_t)s * U + u];
+        hi = spt[(int64_t)(s + 1) * U + u];
+    };
+    auto live = [&](int K, int32_t lo, int32_t hi) { return K * KP + jl < U ? hi : lo; };
+    // entries of the current panel (ek, ev) and of the next one (nk, nv)
+    int32_t ek[SR_EG], nk[SR_EG];
+    V ev[SR_EG], nv[SR_EG];
+    auto fetch_entries = [&](int32_t lo) {
+#pragma unroll
+        for (int k = 0; k < SR_EG; ++k) {
+            const int32_t e = min(lo + gq + SR_G * k, ncsc);
+            nk[k] = pkg[e];
+            nv[k] = cval[e];
+        }
+    };
+    // pointers run two panels ahead of the entries, the entries one panel ahead of use
+    int32_t glo, ghi, nlo, nhi, lo1, hi1, lo2, hi2;
+    ptrs(0, nlo, nhi);
+    nhi = live(0, nlo, nhi);
+    fetch_entries(nlo);
+    ptrs(1 % np, lo1, hi1);
+    ptrs(2 % np, lo2, hi2);
+    int32_t nb_next = a.bcnt[(int64_t)s * np];
+    // M_{K+1}, loaded during panel K into registers (scalar arrays: kept in registers);
+    // x_{K+1} likewise (wave 0)
+    T mre[MPT], mim[MPT];
+    auto fetch_M = [&](int K) {
+        const V* Mk = Mg + (int64_t)K * NE;
+#pragma unroll
+        for (int k = 0; k < MPT; ++k) {
+            const V m = Mk[min(tid + k * NT, NE - 1)];
+            mre[k] = m.x;
+            mim[k] = m.y;
+        }
+    };
+    for (int e = tid; e < NE; e += NT) Ms[e] = Mg[e];
+    V xN = czero<T>();
+    __syncthreads();
+    if (w == 0) xN = xp[min(lane, U - 1)];
+
+    double S = 0.0, Xn = 0.0;     // stopping sums (wave 0)
     int sweeps = 0;
-    double S = 0.0, Xn = 0.0;
-    for (int t = 1; t <= T_max; ++t) {
+    bool failed = false;
+    uint32_t seq = 0;
+    for (int t = 1; t <= a.T_max && !failed; ++t) {
         S = 0.0;
         Xn = 0.0;
-        for (int K = 0; K < npanels; ++K) {
-            // stage the packed (D + L)^-1 of this panel
-            const V* Mk = M + (int64_t)K * NE;
-            for (int e = tid; e < NE; e += SP_NT) Ms[e] = Mk[e];
-            // g_u = h_u^H r over the stored entries, one wave per column
+        for (int K = 0; K < np; ++K, ++seq) {
+            const int K1 = (K + 1) % np, K3 = (K + 3) % np;
+            const uint32_t tag = seq + 1;
+            const int par = (int)(seq & 1);
+            // the prefetched block becomes the current one
+            glo = nlo;
+            ghi = nhi;
+            const int32_t nb = nb_next;
 #pragma unroll
-            for (int c = 0; c < SP_CPW; ++c) {
-                const int jl = wid * SP_CPW + c;
-                const int u = K * SP_KP + jl;
-                T gr = 0, gi = 0;
-                if (u < U) {
-                    const int32_t e0 = colptr[u], e1 = colptr[u + 1];
-                    for (int32_t e = e0 + lane; e < e1; e += 64) {
-                        const V h = cval[e];
-                        const V rv = ld_dev(&r[rowidx[e]]);
-                        gr += h.x * rv.x + h.y * rv.y;
-                        gi += h.x * rv.y - h.y * rv.x;
+            for (int k = 0; k < SR_EG; ++k) {
+                ek[k] = nk[k];
+                ev[k] = nv[k];
+            }
+            // 1. partial of this slice (reads from clamped indices, products masked: no
+            //    branch between the LDS reads; entries past the register window: direct loads)
+            {
+                V p = czero<T>();
+#pragma unroll
+                for (int k = 0; k < SR_EG; ++k) {
+                    const bool ok = glo + gq + SR_G * k < ghi;
+                    const V rv = rs[ok ? (ek[k] & 4095) : 0];
+                    V h = ev[k];
+                    h.x = ok ? h.x : T(0);
+                    h.y = ok ? h.y : T(0);
+                    cfma_conj(p, h, rv);
+                }
+                for (int32_t e = glo + gq + SR_G * SR_EG; e < ghi; e += SR_G)
+                    cfma_conj(p, cval[e], rs[pkg[e] & 4095]);
+                p.x = sp_quad_sum(p.x);
+                p.y = sp_quad_sum(p.y);
+                if (gq == 0) TG::put(a.xbuf + (((int64_t)par * P + s) * KP + jl) * NW, p, tag);
+            }
+            // 2. prefetch: the next panel's block, the pointers after that, M_{K+1}
+            fetch_entries(lo1);
+            nlo = lo1;
+            nhi = live(K1, lo1, hi1);
+            lo1 = lo2;
+            hi1 = hi2;
+            ptrs(K3, lo2, hi2);
+            nb_next = a.bcnt[(int64_t)s * np + K1];
+            fetch_M(K1);
+            const int uK = K * KP + lane;
+            V xK = xN;
+            // 3. exchange: wave w sums slices w, w + 4, ... of column `lane`, fixed order.
+            //    Each attempt issues all of its loads before testing any tag.
+            {
+                V acc = czero<T>();
+                for (int s0 = w; s0 < P && !failed; s0 += NWV * SR_SC) {
+                    V v[SR_SC];
+                    bool have[SR_SC];
+#pragma unroll
+                    for (int k = 0; k < SR_SC; ++k) {
+                        v[k] = czero<T>();
+                        have[k] = s0 + NWV * k >= P;
+                    }
+                    uint64_t t0 = 0;
+                    bool started = false;
+                    for (;;) {
+                        // slices the whole wave already holds are not read again
+                        uint64_t wd[SR_SC][NW];
+#pragma unroll
+                        for (int k = 0; k < SR_SC; ++k) {
+                            const uint64_t* src =
+                                a.xbuf + (((int64_t)par * P + min(s0 + NWV * k, P - 1)) * KP + lane) * NW;
+                            const bool want = __any(!have[k]);
+#pragma unroll
+                            for (int i = 0; i < NW; ++i) wd[k][i] = want ? sp_ld(src + i) : 0;
+                        }
+                        bool miss = false;
+#pragma unroll
+                        for (int k = 0; k < SR_SC; ++k) {
+                            V got;
+                            const bool ok = TG::decode(wd[k], tag, got);
+                            if (!have[k] && ok) {
+                                v[k] = got;
+                                have[k] = true;
+                            }
+                            miss |= !have[k];
+                        }
+                        if (!__any(miss)) break;
+                        if (!started) {
+                            t0 = wall_clock64();
+                            started = true;
+                        }
+                        if (ld_relaxed(a.abort_flag) || wall_clock64() - t0 > a.tmo) {
+                            if (lane == 0) st_relaxed(a.abort_flag, 1u);
+                            failed = true;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+#pragma unroll
+                    for (int k = 0; k < SR_SC; ++k) {
+                        acc.x += v[k].x;
+                        acc.y += v[k].y;
                     }
                 }
-                gr = wave_allsum(gr);
-                gi = wave_allsum(gi);
-                if (lane == 0) {
-                    const V xo = (u < U) ? ld_dev(&x[u]) : czero<T>();
-                    bsh[jl] = cmake<T>(gr - lambda * xo.x, gi - lambda * xo.y);
-                    xsh[jl] = xo;
-                }
+                part[w][lane] = acc;
+                if (failed && lane == 0) fail_s = 1;
             }
             __syncthreads();
+            if (fail_s) {
+                failed = true;
+                break;
+            }
+            if (w == 0) {
+                V b = part[0][lane];
+#pragma unroll
+                for (int k = 1; k < NWV; ++k) {
+                    b.x += part[k][lane].x;
+                    b.y += part[k][lane].y;
+                }
+                if (uK >= U) xK = czero<T>();
+                b.x -= lambda * xK.x;
+                b.y -= lambda * xK.y;
+                bsh[lane] = b;
+            }
+            __syncthreads();
+            // 4. delta = (D + L)^-1 b: thread (j, wave w) sums v in [16 w, 16 w + 16), v <= j
+            //    (every read index stays inside the packed triangle; v > j is masked)
             {
-                const int j = tid % SP_KP, sl = tid / SP_KP;
-                const int v0 = sl * SV, v1 = min(v0 + SV - 1, j);
+                const int j = lane, v0 = w * VPW;
                 V d = czero<T>();
-                int off = v0 * SP_KP - (v0 * (v0 - 1)) / 2 + (j - v0);
-                for (int v = v0; v <= v1; ++v) {
-                    cfma(d, Ms[off], bsh[v]);
-                    off += SP_KP - v - 1;
-                }
-                dpart[sl][j] = d;
-            }
-            __syncthreads();
-            if (tid < SP_KP) {
-                V s = dpart[0][tid];
 #pragma unroll
-                for (int k = 1; k < NS; ++k) {
-                    s.x += dpart[k][tid].x;
-                    s.y += dpart[k][tid].y;
+                for (int k = 0; k < VPW; ++k) {
+                    const int v = v0 + k;
+                    V m = Ms[v * KP - (v * (v - 1)) / 2 + (j - v)];
+                    const V bb = bsh[v];
+                    m.x = v <= j ? m.x : T(0);
+                    m.y = v <= j ? m.y : T(0);
+                    cfma(d, m, bb);
                 }
-                dsh[tid] = s;
-                const int u = K * SP_KP + tid;
-                if (u < U) st_dev(&x[u], cmake<T>(xsh[tid].x + s.x, xsh[tid].y + s.y));
+                part[w][j] = d;
             }
             __syncthreads();
+            // stage M_{K+1} (its loads were issued before the exchange)
+#pragma unroll
+            for (int k = 0; k < MPT; ++k) {
+                const int e = tid + k * NT;
+                if (e < NE) Ms[e] = cmake<T>(mre[k], mim[k]);
+            }
+            if (w == 0) {
+                V d = part[0][lane];
+#pragma unroll
+                for (int k = 1; k < NWV; ++k) {
+                    d.x += part[k][lane].x;
+                    d.y += part[k][lane].y;
+                }
+                dsh[lane] = d;
+                xK = cmake<T>(xK.x + d.x, xK.y + d.y);
+                if (uK < U) {
+                    S += cabs2d(d);
+                    Xn += cabs2d(xK);
+                    xp[uK] = xK;
+                }
+                xN = xp[min(K1 * KP + lane, U - 1)];
+            }
+            __syncthreads();
+            // 5. r_s -= H_{K,s} delta: every entry's term goes to its row-order slot of the
+            //    block, then the first slot of each row adds the row's terms in order
+            //    (blocks larger than the staging area take several passes)
             {
-                double s1 = 0.0, s2 = 0.0;
-                for (int j = lane; j < SP_KP; j += 64) {
-                    const V d = dsh[j];
-                    s1 += cabs2d(d);
-                    s2 += cabs2d(cmake<T>(xsh[j].x + d.x, xsh[j].y + d.y));
-                }
-                S += wave_allsum(s1);
-                Xn += wave_allsum(s2);
-            }
-            // r -= h_u delta_u for every stored entry of the panel (rows may repeat
-            // across the panel's columns: atomic adds)
+                const V dj = dsh[jl];
+                for (int c0 = 0; c0 < nb; c0 += SR_CAP) {
 #pragma unroll
-            for (int c = 0; c < SP_CPW; ++c) {
-                const int jl = wid * SP_CPW + c;
-                const int u = K * SP_KP + jl;
-                if (u < U) {
-                    const V d = dsh[jl];
-                    const int32_t e0 = colptr[u], e1 = colptr[u + 1];
-                    for (int32_t e = e0 + lane; e < e1; e += 64) {
-                        const V h = cval[e];
-                        V* rp = &r[rowidx[e]];
-                        atomicAdd(&rp->x, -(h.x * d.x - h.y * d.y));
-                        atomicAdd(&rp->y, -(h.x * d.y + h.y * d.x));
+                    for (int k = 0; k < SR_EG; ++k) {
+                        const int q = (ek[k] >> 12) - c0;
+                        if (glo + gq + SR_G * k < ghi && q >= 0 && q < SR_CAP) {
+                            cbuf[q] = cmul(ev[k], dj);
+                            rbuf[q] = ek[k] & 4095;
+                        }
                     }
+                    for (int32_t e = glo + gq + SR_G * SR_EG; e < ghi; e += SR_G) {
+                        const int32_t pe = pkg[e];
+                        const int q = (pe >> 12) - c0;
+                        if (q >= 0 && q < SR_CAP) {
+                            cbuf[q] = cmul(cval[e], dj);
+                            rbuf[q] = pe & 4095;
+                        }
+                    }
+                    __syncthreads();
+                    const int lim = min(SR_CAP, nb - c0);
+                    for (int q = tid; q < lim; q += NT) {
+                        const int r = rbuf[q];
+                        if (q > 0 && rbuf[q - 1] == r) continue;
+                        V acc = cbuf[q];
+                        for (int q2 = q + 1; q2 < lim && rbuf[q2] == r; ++q2) {
+                            acc.x += cbuf[q2].x;
+                            acc.y += cbuf[q2].y;
+                        }
+                        const int rr = min((unsigned)r, (unsigned)(NT * RPT - 1));   // (always r)
+                        V rv = rs[rr];
+                        rv.x -= acc.x;
+                        rv.y -= acc.y;
+                        rs[rr] = rv;
+                    }
+                    __syncthreads();
                 }
             }
-            wave_drain_vmem();
-            __syncthreads();
         }
+        if (failed) break;
         sweeps = t;
-        if (tol > 0.0 && sqrt(S) <= tol * sqrt(Xn)) break;
+        if (w == 0) {
+            const double s1 = wave_allsum(S), s2 = wave_allsum(Xn);
+            if (lane == 0) {
+                stop_s[0] = s1;
+                stop_s[1] = s2;
+            }
+        }
+        __syncthreads();
+        S = stop_s[0];
+        Xn = stop_s[1];
+        __syncthreads();
+        if (a.tol > 0.0 && sqrt(S) <= a.tol * sqrt(Xn)) break;
     }
-    if (tid == 0) {
-        const double rel = (Xn > 0.0) ? sqrt(S / Xn) : (S > 0.0 ? INFINITY : 0.0);
-        int fl = 0;
-        if (tol > 0.0 && !(rel <= tol)) fl |= CDM_INFO_NOT_CONVERGED;
-        cdm_info o;
-        o.sweeps = sweeps;
-        o.flags = fl;
-        o.rel_step = rel;
-        o.resid = -1.0;
-        o.reserved = 0.0;
-        info[0] = o;
+    if (s == 0) {
+        for (int u = tid; u < U; u += NT) ((V*)a.x)[u] = xp[u];
+        if (tid == 0) {
+            const double rel = (Xn > 0.0) ? sqrt(S / Xn) : (S > 0.0 ? INFINITY : 0.0);
+            int fl = 0;
+            if (a.tol > 0.0 && !(rel <= a.tol)) fl |= CDM_INFO_NOT_CONVERGED;
+            cdm_info o;
+            o.sweeps = sweeps;
+            o.flags = fl;
+            o.rel_step = rel;
+            o.resid = -1.0;
+            o.reserved = 0.0;
+            a.info[0] = o;
+        }
     }
 }
 
-// r = y, x = x0 (or 0); warm start: r -= H x0 through the column-compressed form
+// r = y - H x0 (one thread per row, through the row-ordered input: fixed order, no
+// atomics) and x = x0 (or 0)
 template <typename T>
-__global__ void k_sparse_init(const cv<T>* __restrict__ y, int B, const cv<T>* __restrict__ x0, int U,
-                              cv<T>* __restrict__ r, cv<T>* __restrict__ x) {
+__global__ void k_sparse_init(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                              const cv<T>* __restrict__ val, const cv<T>* __restrict__ y, int B,
+                              const cv<T>* __restrict__ x0, int U, cv<T>* __restrict__ r, cv<T>* __restrict__ x) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < B) r[i] = y[i];
+    if (i < B) {
+        cv<T> ri = y[i];
+        if (x0)
+            for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) cfms(ri, val[e], x0[colidx[e]]);
+        r[i] = ri;
+    }
     if (i < U) x[i] = x0 ? x0[i] : czero<T>();
 }
-template <typename T>
-__global__ void k_sparse_warm(const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
-                              const cv<T>* __restrict__ cval, const cv<T>* __restrict__ x0, int U,
-                              cv<T>* __restrict__ r) {
-    const int u = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (u >= U) return;
-    const cv<T> xv = x0[u];
-    for (int32_t e = colptr[u] + lane; e < colptr[u + 1]; e += 64) {
-        const cv<T> h = cval[e];
-        cv<T>* rp = &r[rowidx[e]];
-        atomicAdd(&rp->x, -(h.x * xv.x - h.y * xv.y));
-        atomicAdd(&rp->y, -(h.x * xv.y + h.y * xv.x));
-    }
+
+template <typename T, int RPT> static hipError_t launch_sweep_t(const SparseRsArgs& A, int P, hipStream_t st) {
+    void* args[] = {(void*)&A};
+    return hipLaunchCooperativeKernel((const void*)k_cd_sparse<T, RPT>, dim3(P), dim3(SR_NT), args, 0, st);
 }
 
 template <typename T> static hipError_t launch_sparse_t(const SparseLaunch& L, hipStream_t st) {
@@ -335,23 +693,69 @@ template <typename T> static hipError_t launch_sparse_t(const SparseLaunch& L, h
     if (e != hipSuccess || L.transpose_only) return e;
     // 2. panel Gram blocks and (D + L)^-1
     hipLaunchKernelGGL((k_sparse_gram<T>), dim3(L.npanels), dim3(256), 0, st, L.colptr, L.rowidx, (const V*)L.cval,
-                       L.U, SP_KP, (V*)L.gpart);
+                       L.U, SR_KP, (V*)L.gpart);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_gram_invert(L.c128, L.gpart, 1, L.npanels, SP_KP, L.U, L.lambda, L.M, L.e, L.status, st);
+    e = launch_gram_invert(L.c128, L.gpart, 1, L.npanels, SR_KP, L.U, L.lambda, L.M, L.e, L.status, st);
     if (e != hipSuccess) return e;
-    // 3. init and sweeps
+    // 3. row slices, init, sweeps
+    const int64_t nsp = (int64_t)(L.P + 1) * L.U;
+    hipLaunchKernelGGL(k_sparse_slices, dim3((unsigned)((nsp + 255) / 256)), dim3(256), 0, st, L.colptr, L.rowidx,
+                       L.B, L.U, L.P, L.R, L.spt);
+    hipLaunchKernelGGL(k_sparse_rank, dim3((unsigned)(L.P * L.npanels)), dim3(256), 0, st, L.rowidx, L.spt, L.U,
+                       L.npanels, L.R, L.pi, L.bcnt);
     const int n = L.B > L.U ? L.B : L.U;
-    hipLaunchKernelGGL((k_sparse_init<T>), dim3((n + 255) / 256), dim3(256), 0, st, (const V*)L.y, L.B,
-                       (const V*)L.x0, L.U, (V*)L.r, (V*)L.x);
-    if (L.x0)
-        hipLaunchKernelGGL((k_sparse_warm<T>), dim3((L.U + 3) / 4), dim3(256), 0, st, L.colptr, L.rowidx,
-                           (const V*)L.cval, (const V*)L.x0, L.U, (V*)L.r);
+    hipLaunchKernelGGL((k_sparse_init<T>), dim3((n + 255) / 256), dim3(256), 0, st, L.rowptr, L.colidx,
+                       (const V*)L.val, (const V*)L.y, L.B, (const V*)L.x0, L.U, (V*)L.r, (V*)L.x);
+    e = launch_zero_u32((uint32_t*)L.xbuf, (int64_t)2 * L.P * SR_KP * SpTag<T>::NW * 2, st);
+    if (e != hipSuccess) return e;
+    SparseRsArgs A;
+    A.cval = L.cval;
+    A.pk = L.pi;
+    A.spt = L.spt;
+    A.bcnt = L.bcnt;
+    A.M = L.M;
+    A.r0 = L.r;
+    A.x = L.x;
+    A.xp = L.xp;
+    A.xbuf = L.xbuf;
+    A.abort_flag = L.abort_flag;
+    A.info = L.info;
+    A.nnz = L.nnz;
+    A.B = L.B;
+    A.U = L.U;
+    A.npanels = L.npanels;
+    A.R = L.R;
+    A.T_max = L.T_max;
+    A.lambda = L.lambda;
+    A.tol = L.tol;
+    A.tmo = L.timeout_ticks;
     if (L.ev_sweep0) (void)hipEventRecord(L.ev_sweep0, st);
-    hipLaunchKernelGGL((k_cd_sparse<T>), dim3(1), dim3(SP_NT), 0, st, L.colptr, L.rowidx, (const V*)L.cval, (V*)L.r,
-                       (V*)L.x, (const V*)L.M, L.U, L.npanels, L.lambda, L.T_max, L.tol, L.info);
+    const int rpt = sparse_rows_per_thread(L.R);
+    switch (rpt) {
+        case 1: e = launch_sweep_t<T, 1>(A, L.P, st); break;
+        case 2: e = launch_sweep_t<T, 2>(A, L.P, st); break;
+        case 4: e = launch_sweep_t<T, 4>(A, L.P, st); break;
+        case 8: e = launch_sweep_t<T, 8>(A, L.P, st); break;
+        case 16: e = launch_sweep_t<T, 16>(A, L.P, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
     if (L.ev_sweep1) (void)hipEventRecord(L.ev_sweep1, st);
     return hipGetLastError();
+}
+
+// rows per thread of the sweep for slices of R rows: the power of two >= R / 256
+int sparse_rows_per_thread(int R) {
+    int rpt = 1;
+    while (rpt * SR_NT < R) rpt *= 2;
+    return rpt * SR_NT <= SR_RMAX ? rpt : 0;
+}
+
+void sparse_slices(int B, int ncu, int& P, int& R) {
+    P = (B + CDM_SPARSE_SLICE_ROWS - 1) / CDM_SPARSE_SLICE_ROWS;
+    P = std::max(1, std::min(P, std::min(64, ncu)));
+    R = (B + P - 1) / P;
 }
 
 hipError_t launch_sparse(const SparseLaunch& L, hipStream_t st) {

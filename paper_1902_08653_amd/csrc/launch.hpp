@@ -189,9 +189,23 @@ struct SparseLaunch {
     int T_max;
     double tol;
     bool transpose_only;
+    int P, R;                // row slices (one workgroup each) of R rows
+    int32_t* spt;            // [P+1][U] slice pointers into the column-compressed form
+    int32_t* pi;             // [nnz] row-order position of each entry inside its block
+    int32_t* bcnt;           // [P][npanels] block entry counts
+    void* xp;                // [P][U] per-workgroup copies of x
+    uint64_t* xbuf;          // [2][P][64][4] tagged partials
+    uint32_t* abort_flag;
+    uint64_t timeout_ticks;
     hipEvent_t ev_sweep0, ev_sweep1;   // optional events around the sweep kernel
 };
 hipError_t launch_sparse(const SparseLaunch& L, hipStream_t st);
+// Rows per slice the sparse sweep aims for (slices = ceil(B / rows), 1..64).
+#ifndef CDM_SPARSE_SLICE_ROWS
+#define CDM_SPARSE_SLICE_ROWS 512
+#endif
+void sparse_slices(int B, int ncu, int& P, int& R);
+int sparse_rows_per_thread(int R);   // 0: R too large for the sweep's LDS slice
 
 // Mixed-precision refinement (outer FP64 steps around the FP32 panel engine).
 struct MixedLaunch {

@@ -120,6 +120,12 @@ struct cdm_plan {
     int32_t* sp_rowidx = nullptr;
     void* sp_cval = nullptr;
     void* sp_r = nullptr;
+    int32_t* sp_spt = nullptr;
+    int32_t* sp_pi = nullptr;
+    int32_t* sp_bcnt = nullptr;
+    void* sp_xp = nullptr;
+    uint64_t* sp_xbuf = nullptr;
+    int sp_P = 1, sp_R = 1;
     // batched layout
     std::vector<int64_t> H_off, y_off, x_off;
     int64_t* xoff_dev = nullptr;
@@ -235,6 +241,16 @@ static int32_t create_sparse(cdm_plan* p, cdm_plan** plan) {
     const size_t o_M = ar.take(p->esz * ne * p->npanels);
     const size_t o_gpart = ar.take(p->esz * 2 * (size_t)kSpKp * kSpKp * p->npanels);
     const size_t o_e = ar.take(8 * (size_t)d.U);
+    sparse_slices(d.B, p->ncu, p->sp_P, p->sp_R);
+    if (sparse_rows_per_thread(p->sp_R) == 0) {
+        delete p;
+        return CDM_ESHAPE;
+    }
+    const size_t o_spt = ar.take(4 * (size_t)(p->sp_P + 1) * d.U);
+    const size_t o_pi = ar.take(4 * nnz);
+    const size_t o_bcnt = ar.take(4 * (size_t)p->sp_P * p->npanels);
+    const size_t o_xp = ar.take(p->esz * (size_t)p->sp_P * d.U);
+    const size_t o_xbuf = ar.take(8 * (size_t)2 * p->sp_P * kSpKp * 4);
     int32_t st = alloc_ws(p, ar.off);
     if (st) {
         delete p;
@@ -250,11 +266,16 @@ static int32_t create_sparse(cdm_plan* p, cdm_plan** plan) {
     p->M = b + o_M;
     p->gpart = b + o_gpart;
     p->e = (double*)(b + o_e);
+    p->sp_spt = (int32_t*)(b + o_spt);
+    p->sp_pi = (int32_t*)(b + o_pi);
+    p->sp_bcnt = (int32_t*)(b + o_bcnt);
+    p->sp_xp = b + o_xp;
+    p->sp_xbuf = (uint64_t*)(b + o_xbuf);
     char buf[512];
     snprintf(buf, sizeof(buf),
              "{\"engine\": \"sparse\", \"precision\": \"%s\", \"B\": %d, \"U\": %d, \"nnz\": %lld, \"panel\": %d, "
-             "\"npanels\": %d, \"workgroups\": 1, \"workspace\": %zu}",
-             p->c128 ? "c128" : "c64", d.B, d.U, (long long)d.nnz, kSpKp, p->npanels, p->ws_bytes);
+             "\"npanels\": %d, \"workgroups\": %d, \"slice_rows\": %d, \"workspace\": %zu}",
+             p->c128 ? "c128" : "c64", d.B, d.U, (long long)d.nnz, kSpKp, p->npanels, p->sp_P, p->sp_R, p->ws_bytes);
     p->text = buf;
     st = setup_timing(p);
     if (st) {
@@ -295,6 +316,15 @@ static int32_t run_sparse(cdm_plan* p, const void* val, const int32_t* rowptr, c
     L.T_max = d.T_max;
     L.tol = d.tol;
     L.transpose_only = transpose_only;
+    L.P = p->sp_P;
+    L.R = p->sp_R;
+    L.spt = p->sp_spt;
+    L.pi = p->sp_pi;
+    L.bcnt = p->sp_bcnt;
+    L.xp = p->sp_xp;
+    L.xbuf = p->sp_xbuf;
+    L.abort_flag = p->ctr + 2;
+    L.timeout_ticks = p->timeout_ticks;
     L.ev_sweep0 = p->timed ? p->ev[2] : nullptr;
     L.ev_sweep1 = p->timed ? p->ev[3] : nullptr;
     HIP_TRY(launch_zero_u32(p->ctr, 16, st));
