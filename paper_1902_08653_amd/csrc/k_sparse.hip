@@ -253,7 +253,10 @@ template <typename T> __device__ __forceinline__ T sp_quad_sum(T v) {
 constexpr int SR_NT = 256;                // 4 waves
 constexpr int SR_KP = 64;                 // panel width
 constexpr int SR_G = SR_NT / SR_KP;       // threads per column in the partial (a quad)
-constexpr int SR_EG = 4;                  // block entries per thread held in registers
+#ifndef CDM_SPARSE_EG
+#define CDM_SPARSE_EG 4
+#endif
+constexpr int SR_EG = CDM_SPARSE_EG;      // block entries per thread held in registers
 constexpr int SR_SC = 4;                  // slices read per exchange attempt (per thread)
 constexpr int SR_CAP = 1024;              // scatter staging (block entries per pass)
 constexpr int SR_RMAX = SR_NT * 16;       // largest slice
