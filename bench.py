@@ -450,19 +450,27 @@ PAPER_TABLE_I = {("fp32", 4, 2): (0.465, 1.23), ("fp32", 4, 3): (0.540, 1.06), (
                  ("fp16", 8, 2): (0.295, 1.95), ("fp16", 8, 3): (0.331, 1.73), ("fp16", 8, 4): (0.370, 1.55)}
 
 
+# the downlink half of Table I (precoding, same shapes; latency ms / throughput Gbit/s)
+PAPER_TABLE_I_DL = {("fp32", 4, 2): (0.414, 1.38), ("fp32", 4, 3): (0.499, 1.15), ("fp32", 4, 4): (0.577, 0.99),
+                    ("fp32", 8, 2): (0.440, 1.30), ("fp32", 8, 3): (0.525, 1.09), ("fp32", 8, 4): (0.601, 0.95),
+                    ("fp16", 4, 2): (0.228, 2.52), ("fp16", 4, 3): (0.267, 2.15), ("fp16", 4, 4): (0.305, 1.88),
+                    ("fp16", 8, 2): (0.233, 2.46), ("fp16", 8, 3): (0.275, 2.09), ("fp16", 8, 4): (0.311, 1.84)}
+
+
 def bench_paper(a):
     """The paper's throughput shape on one GPU: 1200 subcarriers x 15 received vectors,
     U = 8 users, 16-QAM, Rayleigh channels, C clusters of 32 antennas, T sweeps from
     x = 0, cluster fusion; one cdm_detect_batch launch per batch (HIP graph replays).
     The headline line is C = 4, T = 3 in FP16 (the configuration of the paper's
-    per-user throughput comparison); every (C, T, precision) cell is reported."""
+    per-user throughput comparison); every (C, T, precision) cell is reported, and the
+    downlink half of the table (cdm_precode_batch on the same shape) beside it."""
     import torch
 
     from paper_1902_08653_amd import cdm, inputs
     dev = torch.device("cuda:0")
     S, V, U, Bc = 1200, 15, 8, 32
     bits = S * V * U * 4
-    cells, lines = {}, []
+    cells, lines, dl = {}, [], {}
     for Cn in (4, 8):
         d = inputs.paper_shaped(Cn, Bc, U, S, V, snr_db=10.0, seed=1)
         B = Cn * Bc
@@ -470,9 +478,21 @@ def bench_paper(a):
         Y32 = torch.from_numpy(d["Y"].astype(np.complex64).reshape(-1)).to(dev)
         H16 = torch.from_numpy(np.stack([d["Ht"].real, d["Ht"].imag], -1).astype(np.float16).reshape(-1)).to(dev)
         Y16 = torch.from_numpy(np.stack([d["Y"].real, d["Y"].imag], -1).astype(np.float16).reshape(-1)).to(dev)
-        for prec, (Hd, Yd, esz) in (("fp32", (H32, Y32, 8)), ("fp16", (H16, Y16, 4))):
+        X32 = torch.from_numpy(d["X"].astype(np.complex64).reshape(-1)).to(dev)
+        X16 = torch.from_numpy(np.stack([d["X"].real, d["X"].imag], -1).astype(np.float16).reshape(-1)).to(dev)
+        for prec, (Hd, Yd, Xd, esz) in (("fp32", (H32, Y32, X32, 8)), ("fp16", (H16, Y16, X16, 4))):
             out = torch.empty(S * V * U * (1 if prec == "fp32" else 2), dtype=Yd.dtype, device=dev)
+            pre = torch.empty(S * V * B * (1 if prec == "fp32" else 2), dtype=Yd.dtype, device=dev)
             for T in (2, 3, 4):
+                g = _graph(lambda: cdm.precode_batch(Hd, Xd, S, V, Cn, Bc, U, T, 1.0, out=pre))
+                ms = _time_graph(g, max(a.steps, 50), max(a.warmup, 5))
+                del g
+                algo = (S * B * U + S * V * U + S * V * B) * esz
+                dl[(prec, Cn, T)] = dict(ms=ms, gbps=bits / (ms * 1e-3) / 1e9, hbm_gbs=algo / (ms * 1e-3) / 1e9,
+                                         bytes=algo)
+                pl, pt = PAPER_TABLE_I_DL[(prec, Cn, T)]
+                print("[bench] downlink %s C=%d T=%d: %.4f ms, %.1f Gbit/s (paper on %d V100: %.3f ms, %.2f Gbit/s)"
+                      % (prec, Cn, T, ms, dl[(prec, Cn, T)]["gbps"], Cn, pl, pt), file=sys.stderr, flush=True)
                 g = _graph(lambda: cdm.detect_batch(Hd, Yd, S, V, Cn, Bc, U, T, d["N0"], out=out))
                 ms = _time_graph(g, max(a.steps, 50), max(a.warmup, 5))
                 del g
@@ -515,6 +535,10 @@ def bench_paper(a):
                      "algorithmic_bytes_per_launch": head["bytes"], "avg_launch_ms": head["ms"]},
         "cpu_baseline": cpu,
         "cells": {"%s_C%d_T%d" % k: v for k, v in cells.items()},
+        "downlink_cells": {"%s_C%d_T%d" % k: v for k, v in dl.items()},
+        "downlink_note": "cdm_precode_batch (Algorithm 2, power scaling to rho/sqrt(C), rho = 1) on the same "
+                         "channels, one 16-QAM symbol vector per (subcarrier, vector); paper's downlink Table I "
+                         "cells for context",
     }
     print(json.dumps(out))
 

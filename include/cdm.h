@@ -59,7 +59,7 @@ typedef enum cdm_problem { CDM_UPLINK_LMMSE = 0, CDM_DOWNLINK_ZF = 1 } cdm_probl
  * (see cdm_solve and cdm_solve_batched).  CDM_MIXED_C64 is for batched plans only. */
 typedef enum cdm_precision {
     CDM_C128 = 0, CDM_C64 = 1, CDM_MIXED_BF16 = 2, CDM_MIXED_FP8 = 3, CDM_MIXED_C64 = 4,
-    CDM_C16 = 5   /* complex FP16 (two halves, 4 B): cdm_detect_batch only */
+    CDM_C16 = 5   /* complex FP16 (two halves, 4 B): cdm_detect_batch and cdm_precode_batch only */
 } cdm_precision;
 
 typedef enum cdm_layout { CDM_DENSE = 0, CDM_CSR = 1 } cdm_layout;
@@ -244,6 +244,22 @@ int32_t cdm_residual(cdm_plan* plan, const void* H, int64_t ldh, const void* y, 
 int32_t cdm_detect_batch(int32_t S, int32_t V, int32_t C, int32_t Bc, int32_t U, int32_t T_max,
                          int32_t precision, const void* H, const void* Y, double N0, double Ex,
                          void* X, void* stream);
+
+/* Decentralized ZF precoding of the same batch shape (Algorithm 2, Sec. IV; the
+ * downlink half of Table I).  For every (s, v) the symbols s_{s,v} (U) are broadcast
+ * to the C clusters; cluster c runs exactly T_max sweeps of eq. (4) from x_c = 0 on
+ * its rows of H_s (p_u = 1/||h_{u,c}||, a zero column stays inactive), then scales
+ * x_c to norm rho_c = rho / sqrt(C) (rho <= 0: no scaling; x_c = 0 stays 0).
+ *  H    device, as in cdm_detect_batch (uplink orientation; the downlink channel of
+ *       cluster c is its block's conjugate transpose)
+ *  Sym  device, S*V symbol vectors of U, vector (s, v) at element (s*V + v)*U
+ *  X    device output, S*V stacked vectors [x_1; ...; x_C] of B, at element (s*V + v)*B
+ * Precisions and limits as cdm_detect_batch; Bc >= U.  Enqueues one kernel; allocates
+ * nothing.  Errors: CDM_EINVAL (NULL pointer, non-finite rho, T_max < 1), CDM_EDTYPE,
+ * CDM_ESHAPE, CDM_EINFEASIBLE (Bc < U), CDM_EHIP. */
+int32_t cdm_precode_batch(int32_t S, int32_t V, int32_t C, int32_t Bc, int32_t U, int32_t T_max,
+                          int32_t precision, const void* H, const void* Sym, double rho, void* X,
+                          void* stream);
 
 /* Per-coordinate features of a batched plan's packed instances, for the
  * learned warm start (one row of 8 floats per user u of instance i, rows in the

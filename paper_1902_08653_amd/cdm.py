@@ -56,7 +56,7 @@ EXPORTS = ["cdm_version", "cdm_status_string", "cdm_last_error", "cdm_create", "
            "cdm_plan_describe", "cdm_plan_timings", "cdm_stream_copy", "cdm_csr_transpose", "cdm_quantized_copy", "cdm_batched_features", "cdm_mlp_create",
            "cdm_mlp_param_count", "cdm_mlp_set_weights", "cdm_mlp_get_weights", "cdm_mlp_forward",
            "cdm_mlp_gradients", "cdm_mlp_train_step", "cdm_mlp_predict", "cdm_mlp_destroy", "cdm_destroy",
-           "cdm_detect_batch"]
+           "cdm_detect_batch", "cdm_precode_batch"]
 
 _lib = None
 
@@ -120,6 +120,8 @@ def lib():
         L.cdm_destroy.restype = i32
         L.cdm_detect_batch.argtypes = [i32, i32, i32, i32, i32, i32, i32, P, P, f64, f64, P, P]
         L.cdm_detect_batch.restype = i32
+        L.cdm_precode_batch.argtypes = [i32, i32, i32, i32, i32, i32, i32, P, P, f64, P, P]
+        L.cdm_precode_batch.restype = i32
         _lib = L
     return _lib
 
@@ -262,6 +264,28 @@ def detect_batch(H, Y, S, V, C_clusters, Bc, U, T_max, N0, Ex=1.0, out=None, str
         out = torch.empty(int(S) * int(V) * int(U) * per, dtype=Y.dtype, device=Y.device)
     _check(lib().cdm_detect_batch(int(S), int(V), int(C_clusters), int(Bc), int(U), int(T_max), prec, _ptr(H),
                                   _ptr(Y), float(N0), float(Ex), _ptr(out), _stream(stream)), "cdm_detect_batch")
+    return out
+
+
+def precode_batch(H, Sym, S, V, C_clusters, Bc, U, T_max, rho, out=None, stream=None):
+    """cdm_precode_batch: decentralized ZF precoding of S subcarriers x V symbol
+    vectors (Algorithm 2).  H, Sym (and `out`) are device tensors of complex64, or of
+    complex FP16 held as torch.complex32 / interleaved float16; returns the stacked
+    precoded vectors (S*V*B complex, B = C*Bc, Sym's dtype)."""
+    import torch
+    if Sym.dtype == torch.complex64:
+        prec = C64
+    elif Sym.dtype in (torch.complex32, torch.float16):
+        prec = C16
+    else:
+        raise TypeError("precode_batch takes complex64 or complex FP16 tensors")
+    if H.dtype != Sym.dtype:
+        raise TypeError("H and Sym must have the same dtype")
+    per = 2 if Sym.dtype == torch.float16 else 1
+    if out is None:
+        out = torch.empty(int(S) * int(V) * int(C_clusters) * int(Bc) * per, dtype=Sym.dtype, device=Sym.device)
+    _check(lib().cdm_precode_batch(int(S), int(V), int(C_clusters), int(Bc), int(U), int(T_max), prec, _ptr(H),
+                                   _ptr(Sym), float(rho), _ptr(out), _stream(stream)), "cdm_precode_batch")
     return out
 
 

@@ -1,4 +1,4 @@
-// k_small.hip -- decentralized detection of many small clustered problems.
+// k_small.hip -- decentralized detection and precoding of many small clustered problems.
 //
 // The shape of the paper's throughput measurements (Sec. VI): S subcarriers, each with a
 // channel H_s (B x U, B = C * B_c antennas in C clusters) shared by V received vectors.
@@ -213,9 +213,146 @@ static hipError_t launch_small(const void* H, const void* Y, void* X, int S, int
     return hipGetLastError();
 }
 
+// ---- downlink: Algorithm 2 on the same shape ---------------------------------------
+// For every (s, v) each cluster c runs T sweeps of eq. (4) on its rows from x_c = 0
+// with the broadcast symbols s_{s,v}: with p_u = 1/||h_{u,c}|| and sbar_u = p_u s_u,
+//   e = p_u h_{u,c}^H x_c - sbar_u,   x_c <- x_c - e p_u h_{u,c},
+// then scales x_c to norm rho_c = rho / sqrt(C) (Sec. IV-B; rho <= 0: no scaling).
+// The output of (s, v) is the stacked [x_1; ...; x_C] (B entries).  Same mapping as the
+// detector (a quad per task, lane j holding rows j, j + 4, ... of x_c), no fusion step.
+template <int UMAX> static size_t sm_pre_lds_bytes(int NS, int C, bool f16) {
+    return (size_t)NS * C * sm_block<UMAX>(f16) * (f16 ? 4 : 8);
+}
+
+template <bool F16, int UMAX>
+__global__ __launch_bounds__(SM_NT) void k_precode_small(const typename SmNum<F16>::E* __restrict__ H,
+                                                         const typename SmNum<F16>::E* __restrict__ Sym,
+                                                         typename SmNum<F16>::E* __restrict__ X, int S, int V, int C,
+                                                         int Bc, int U, int T, float rho_c, int NS) {
+    using N = SmNum<F16>;
+    using E = typename N::E;
+    constexpr int BLK = sm_block<UMAX>(F16);
+    extern __shared__ __align__(16) unsigned char smem[];
+    E* Hl = reinterpret_cast<E*>(smem);
+    const int tid = threadIdx.x;
+    const int s0 = blockIdx.x * NS;
+    const int ns = min(NS, S - s0);
+    const int B = C * Bc;
+    for (int e = tid; e < ns * C * UMAX * SM_BMAX; e += SM_NT) {
+        const int i = e % SM_BMAX, u = (e / SM_BMAX) % UMAX, k = e / (SM_BMAX * UMAX);
+        const int sub = k / C, c = k % C;
+        E v = N::zero();
+        if (i < Bc && u < U) v = H[(int64_t)(s0 + sub) * B * U + (int64_t)u * B + c * Bc + i];
+        Hl[k * BLK + u * SM_BMAX + i] = v;
+    }
+    __syncthreads();
+    const int tasks = ns * C * V;
+    const int j = tid % SM_LPT;
+    for (int t = tid / SM_LPT; t < tasks; t += SM_NT / SM_LPT) {
+        const int sub = t / (C * V), rem = t % (C * V);
+        const int c = rem / V, v = rem % V;
+        const E* hb = Hl + (sub * C + c) * BLK + j;
+        const E* sv = Sym + ((int64_t)(s0 + sub) * V + v) * U;
+        // preprocessing (FP32): p_u = 1/||h_u|| (a zero column stays inactive), sbar_u
+        float pu[UMAX];
+        float2 sb[UMAX];
+#pragma unroll
+        for (int u = 0; u < UMAX; ++u) {
+            float e = 0.f;
+#pragma unroll
+            for (int k = 0; k < SM_RPL; ++k) {
+                const float2 hf = N::to_f(hb[u * SM_BMAX + SM_LPT * k]);
+                e += hf.x * hf.x + hf.y * hf.y;
+            }
+            e = quad_sum(e);
+            pu[u] = (u < U && e > 0.f) ? 1.f / sqrtf(e) : 0.f;
+            const float2 su = u < U ? N::to_f(sv[u]) : make_float2(0.f, 0.f);
+            sb[u] = make_float2(pu[u] * su.x, pu[u] * su.y);
+        }
+        E x[SM_RPL];
+#pragma unroll
+        for (int k = 0; k < SM_RPL; ++k) x[k] = N::zero();
+        for (int it = 0; it < T; ++it) {
+#pragma unroll
+            for (int u = 0; u < UMAX; ++u) {
+                if (pu[u] != 0.f) {   // equal in the four lanes of the quad
+                    float2 g = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int k = 0; k < SM_RPL; ++k) N::dot_acc(g, hb[u * SM_BMAX + SM_LPT * k], x[k]);
+                    g.x = quad_sum(g.x);
+                    g.y = quad_sum(g.y);
+                    const float2 d = make_float2(pu[u] * (pu[u] * g.x - sb[u].x), pu[u] * (pu[u] * g.y - sb[u].y));
+#pragma unroll
+                    for (int k = 0; k < SM_RPL; ++k) N::axpy(x[k], hb[u * SM_BMAX + SM_LPT * k], d);
+                }
+            }
+        }
+        if (rho_c > 0.f) {
+            float nn = 0.f;
+#pragma unroll
+            for (int k = 0; k < SM_RPL; ++k) {
+                const float2 xf = N::to_f(x[k]);
+                nn += xf.x * xf.x + xf.y * xf.y;
+            }
+            nn = quad_sum(nn);
+            if (nn > 0.f) {
+                const float sc = rho_c / sqrtf(nn);
+#pragma unroll
+                for (int k = 0; k < SM_RPL; ++k) {
+                    const float2 xf = N::to_f(x[k]);
+                    x[k] = N::from_f(make_float2(sc * xf.x, sc * xf.y));
+                }
+            }
+        }
+        E* xo = X + ((int64_t)(s0 + sub) * V + v) * B + c * Bc;
+#pragma unroll
+        for (int k = 0; k < SM_RPL; ++k) {
+            const int i = j + SM_LPT * k;
+            if (i < Bc) xo[i] = x[k];
+        }
+    }
+}
+
+template <bool F16, int UMAX>
+static hipError_t launch_precode(const void* H, const void* Sym, void* X, int S, int V, int C, int Bc, int U, int T,
+                                 float rho_c, hipStream_t st) {
+    using E = typename SmNum<F16>::E;
+    int NS = std::max(1, SM_NT / SM_LPT / (C * V));
+    while (NS > 1 && sm_pre_lds_bytes<UMAX>(NS, C, F16) > SM_LDS) --NS;
+    const size_t lds = sm_pre_lds_bytes<UMAX>(NS, C, F16);
+    if (lds > SM_LDS) return hipErrorInvalidValue;
+    const int blocks = (S + NS - 1) / NS;
+    hipLaunchKernelGGL((k_precode_small<F16, UMAX>), dim3(blocks), dim3(SM_NT), lds, st, (const E*)H, (const E*)Sym,
+                       (E*)X, S, V, C, Bc, U, T, rho_c, NS);
+    return hipGetLastError();
+}
+
 }  // namespace cdm
 
 using namespace cdm;
+
+extern "C" int32_t cdm_precode_batch(int32_t S, int32_t V, int32_t C, int32_t Bc, int32_t U, int32_t T_max,
+                                     int32_t precision, const void* H, const void* Sym, double rho, void* X,
+                                     void* stream) {
+    if (!H || !Sym || !X) return CDM_EINVAL;
+    if (!std::isfinite(rho)) return CDM_EINVAL;
+    if (T_max < 1 || T_max > 100000) return CDM_EINVAL;
+    if (precision != CDM_C64 && precision != CDM_C16) return CDM_EDTYPE;
+    if (S < 1 || V < 1 || U < 1 || U > SM_UMAX || Bc < 1 || Bc > SM_BMAX) return CDM_ESHAPE;
+    if (C != 1 && C != 2 && C != 4 && C != 8) return CDM_ESHAPE;
+    if (Bc < U) return CDM_EINFEASIBLE;   // local zero-forcing needs Bc >= U
+    const bool f16 = precision == CDM_C16;
+    const float rho_c = rho > 0.0 ? (float)(rho / std::sqrt((double)C)) : 0.f;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (f16)
+        e = U <= 8 ? launch_precode<true, 8>(H, Sym, X, S, V, C, Bc, U, T_max, rho_c, st)
+                   : launch_precode<true, 16>(H, Sym, X, S, V, C, Bc, U, T_max, rho_c, st);
+    else
+        e = U <= 8 ? launch_precode<false, 8>(H, Sym, X, S, V, C, Bc, U, T_max, rho_c, st)
+                   : launch_precode<false, 16>(H, Sym, X, S, V, C, Bc, U, T_max, rho_c, st);
+    return e == hipSuccess ? CDM_OK : CDM_EHIP;
+}
 
 extern "C" int32_t cdm_detect_batch(int32_t S, int32_t V, int32_t C, int32_t Bc, int32_t U, int32_t T_max,
                                     int32_t precision, const void* H, const void* Y, double N0, double Ex, void* X,

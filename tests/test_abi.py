@@ -117,6 +117,19 @@ def test_detect_batch_rejects_on_the_host(lib, args, status):
     assert st == status
 
 
+@pytest.mark.parametrize("args,status", [
+    (dict(C=3), -2), (dict(Bc=33), -2), (dict(U=17), -2), (dict(U=0), -2), (dict(S=0), -2),
+    (dict(prec=0), -3), (dict(T=0), -1), (dict(rho=float("inf")), -1), (dict(Bc=4, U=8), -6),
+])
+def test_precode_batch_rejects_on_the_host(lib, args, status):
+    a = dict(S=4, V=3, C=4, Bc=32, U=8, T=3, prec=1, rho=1.0)
+    a.update(args)
+    buf = C.c_void_p(16)   # never dereferenced: validation comes first
+    st = lib.cdm_precode_batch(a["S"], a["V"], a["C"], a["Bc"], a["U"], a["T"], a["prec"], buf, buf,
+                               a["rho"], buf, None)
+    assert st == status
+
+
 def test_info_record_layout():
     from paper_1902_08653_amd import cdm
     assert cdm.INFO_DTYPE.itemsize == 32
