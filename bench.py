@@ -35,6 +35,8 @@ TRAFFIC = {
         "sources": ['paper_1902_08653_amd/csrc/k_panel_la.hip', 'paper_1902_08653_amd/csrc/panel.hpp', 'paper_1902_08653_amd/csrc/common.hpp'], "sha256_16": "cf01b307eb696dcf", "bytes": 148282019566.0},
     ("k_cd_wg", "c64 batch 4096 tol 1e-06"): {
         "sources": ['paper_1902_08653_amd/csrc/k_wg.hip', 'paper_1902_08653_amd/csrc/common.hpp', 'paper_1902_08653_amd/csrc/wg.hpp'], "sha256_16": "0250e54ccc4fc8b0", "bytes": 713278845676.0},
+    ("k_cd_sparse", "c128 16384x8192 0.01 tol 1e-11"): {
+        "sources": ['paper_1902_08653_amd/csrc/k_sparse.hip', 'paper_1902_08653_amd/csrc/common.hpp'], "sha256_16": "f2bdf3b945d580cd", "bytes": 15913280590.0},
     ("k_bm_resid + k_bm_grad + k_bm_inner", "mixed-c64 batch 4096 tol 1e-08"): {
         "sources": ['paper_1902_08653_amd/csrc/k_wg_mixed.hip', 'paper_1902_08653_amd/csrc/common.hpp', 'paper_1902_08653_amd/csrc/wg.hpp', 'paper_1902_08653_amd/csrc/quant.hpp'], "sha256_16": "a27fee61a3afae15", "bytes": 1178767779708.0},
 }
@@ -426,18 +428,22 @@ def bench_sparse(a):
                                % (a.B, a.U, density, prec, density, a.seed, a.lam, tol),
                    "B": a.B, "U": a.U, "nnz": nnz, "precision": prec, "tol": tol, "eps": eps,
                    "engine": json.loads(plan.describe())},
-        # frac against HBM is reported as measured; the sweep is one workgroup walking a
-        # dependent gather -> reduce -> panel product -> scatter chain over a MALL-resident
-        # operator, so its limiter is that chain's latency
+        # frac against HBM is reported as measured; the sweep is a
+        # chain of panel steps (partial, exchange across the slice workgroups, panel product,
+        # scatter) over a MALL-resident operator, so its limiter is that chain's latency
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_cd_sparse",
-                     "limiter": "dependent chain (one workgroup), not HBM",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("k_cd_sparse", "%s %dx%d %g tol %g" % (prec, a.B, a.U, density, tol)),
+                     "kernel": "k_cd_sparse",
+                     "limiter": "per-panel exchange latency across the slice workgroups, not HBM",
                      "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": sweep_ms},
         "cpu_baseline": cpu,
         "accuracy": {"sweeps": sweeps, "rel_step": float(rec["rel_step"]), "flags": int(rec["flags"]),
                      "rel_err_vs_oracle": err, "within_eps": (err is not None and err <= eps)},
         "stages_ms_per_solve": {k: v / a.steps for k, v in stage.items()},
     }
+    if a.copy_probe:
+        out["copy_probe_gbs"] = _copy_probe(cdm, dev, stream)
     print(json.dumps(out))
     plan.close()
 
