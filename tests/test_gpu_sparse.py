@@ -96,3 +96,48 @@ def test_sparse_fullsize_two_sweeps(dev, orc, prec):
     err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
     print(prec, desc, err)
     assert info["sweeps"] == 2 and err <= TOL[prec]
+
+
+def _csr_from_dense(H, y, seed):
+    B, U = H.shape
+    rows, cols = np.nonzero(H)
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    rowptr = np.zeros(B + 1, np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    return inputs.CsrInstance(B=B, U=U, rowptr=np.cumsum(rowptr).astype(np.int32),
+                              colidx=cols.astype(np.int32), val=H[rows, cols].astype(np.complex128),
+                              y=y.astype(np.complex128), seed=seed)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_sparse_large_blocks_heavy_rows_and_empty_lines(dev, orc, prec):
+    """Blocks of a (row slice, 64-column panel) larger than the scatter's staging area,
+    columns with more entries inside one slice than the per-thread register window,
+    three fully dense rows, empty rows and an empty column (with lambda > 0 its coordinate
+    is exactly 0 and no flag is raised, as in the oracle), a ragged last panel."""
+    rng = np.random.default_rng(41)
+    B, U = 1100, 300
+    mask = rng.random((B, U)) < 0.1
+    mask[[5, 600, 1099], :] = True      # dense rows
+    mask[[7, 8, 900], :] = False        # empty rows
+    mask[:, 123] = False                # empty column
+    H = np.where(mask, (rng.standard_normal((B, U)) + 1j * rng.standard_normal((B, U))) / np.sqrt(2 * 0.1 * B), 0)
+    y = (rng.standard_normal(B) + 1j * rng.standard_normal(B)) / np.sqrt(2)
+    ins = _csr_from_dense(H, y, 41)
+    x, info, desc = run_sparse(dev, ins, prec, 3)
+    ref = oracle_sparse(orc, ins, prec, 3)
+    err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+    print(prec, desc, err)
+    assert info["sweeps"] == 3 and err <= TOL[prec]
+    assert info["flags"] == ref["flags"] == 0
+    assert x[123] == 0
+
+
+def test_sparse_results_repeat_bit_for_bit(dev):
+    """The scatter adds each row's terms in a fixed order (no atomics): two solves of the
+    same input give identical bits."""
+    ins = inputs.sparse_uplink(3000, 900, 0.02, seed=5)
+    a, _, _ = run_sparse(dev, ins, "c128", 5)
+    b, _, _ = run_sparse(dev, ins, "c128", 5)
+    assert np.array_equal(a, b)
