@@ -210,20 +210,29 @@ __device__ __forceinline__ uint64_t sp_ld(const uint64_t* p) {
 }
 template <typename T> struct SpTag;
 template <> struct SpTag<double> {
-    static constexpr int NW = 4;
-    __device__ static void put(uint64_t* p, double2 v, uint32_t tag) {
-        const unsigned long long a = __double_as_longlong(v.x), b = __double_as_longlong(v.y);
-        sp_st(p + 0, (uint32_t)a, tag);
-        sp_st(p + 1, (uint32_t)(a >> 32), tag);
-        sp_st(p + 2, (uint32_t)b, tag);
-        sp_st(p + 3, (uint32_t)(b >> 32), tag);
+    // complex128: the 128 payload bits in three words of 48 bits, each with a 16-bit tag
+    // (tag = sequence + 1 modulo 2^16; a slot is rewritten every second sequence, so the
+    // value it held before carries a different tag)
+    static constexpr int NW = 3;
+    __device__ static void st48(uint64_t* p, uint64_t payload, uint32_t tag) {
+        __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                           (unsigned long long)((payload & 0xffffffffffffull) | ((uint64_t)(tag & 0xffffu) << 48)),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __device__ static bool decode(const uint64_t (&wd)[4], uint32_t tag, double2& v) {
-        const uint64_t w0 = wd[0], w1 = wd[1], w2 = wd[2], w3 = wd[3];
-        const bool ok = ((uint32_t)(w0 >> 32) == tag) & ((uint32_t)(w1 >> 32) == tag) &
-                        ((uint32_t)(w2 >> 32) == tag) & ((uint32_t)(w3 >> 32) == tag);
-        v.x = __longlong_as_double((long long)(((w1 & 0xffffffffull) << 32) | (w0 & 0xffffffffull)));
-        v.y = __longlong_as_double((long long)(((w3 & 0xffffffffull) << 32) | (w2 & 0xffffffffull)));
+    __device__ static void put(uint64_t* p, double2 v, uint32_t tag) {
+        const uint64_t a = (uint64_t)__double_as_longlong(v.x), b = (uint64_t)__double_as_longlong(v.y);
+        st48(p + 0, a, tag);
+        st48(p + 1, (a >> 48) | (b << 16), tag);
+        st48(p + 2, b >> 32, tag);
+    }
+    __device__ static bool decode(const uint64_t (&wd)[3], uint32_t tag, double2& v) {
+        const uint64_t t = (uint64_t)(tag & 0xffffu);
+        const bool ok = ((wd[0] >> 48) == t) & ((wd[1] >> 48) == t) & ((wd[2] >> 48) == t);
+        const uint64_t m = 0xffffffffffffull;
+        const uint64_t a = (wd[0] & m) | ((wd[1] & 0xffffull) << 48);
+        const uint64_t b = ((wd[1] & m) >> 16) | ((wd[2] & 0xffffffffull) << 32);
+        v.x = __longlong_as_double((long long)a);
+        v.y = __longlong_as_double((long long)b);
         return ok;
     }
 };
@@ -267,12 +276,14 @@ constexpr int SR_RMAX = SR_NT * 16;       // largest slice
 // order, so that the update r -= H delta can add each row's terms in a fixed order.
 // Stored with the entry's row inside the slice: pk[e] = pi << 12 | (row - s * R)
 // (R <= 4096, and a block holds at most 64 R entries).  bcnt[s * npanels + K] is the
-// block's entry count.  One workgroup per block: count
+// block's entry count, and roff[(s * npanels + K) * (R + 1) + i] the first position of
+// the slice's row i in that order (i = R: the count).  One workgroup per block: count
 // the entries per row, prefix-sum, then place the columns one after another (the rows
 // of one column are distinct, so each row's next slot is taken at most once per step).
 __global__ __launch_bounds__(256) void k_sparse_rank(const int32_t* __restrict__ rowidx,
                                                      const int32_t* __restrict__ spt, int U, int npanels,
-                                                     int R, int32_t* __restrict__ pk, int32_t* __restrict__ bcnt) {
+                                                     int R, int32_t* __restrict__ pk, int32_t* __restrict__ bcnt,
+                                                     int32_t* __restrict__ roff) {
     __shared__ int32_t cnt[SR_RMAX], fill[SR_RMAX];
     __shared__ int32_t wsum[256 / 64];
     const int s = blockIdx.x / npanels, K = blockIdx.x % npanels;
@@ -302,11 +313,16 @@ __global__ __launch_bounds__(256) void k_sparse_rank(const int32_t* __restrict__
     __syncthreads();
     int32_t base = incl - run;
     for (int k = 0; k < w; ++k) base += wsum[k];
+    int32_t* ro = roff + ((int64_t)s * npanels + K) * (R + 1);
     for (int i = i0; i < i1; ++i) {
         fill[i] = base;
+        ro[i] = base;
         base += cnt[i];
     }
-    if (tid == 255) bcnt[(int64_t)s * npanels + K] = base;
+    if (tid == 255) {
+        bcnt[(int64_t)s * npanels + K] = base;
+        ro[R] = base;
+    }
     __syncthreads();
     for (int c = 0; c < ncol; ++c) {
         const int u = K * SR_KP + c;
@@ -325,6 +341,7 @@ struct SparseRsArgs {
     const int32_t* pk;       // row-order position in the block << 12 | row in the slice
     const int32_t* spt;      // [P+1][U] slice pointers
     const int32_t* bcnt;     // [P][npanels] block entry counts
+    const int32_t* roff;     // [P][npanels][R+1] row starts inside each block (row order)
     const void* M;           // [npanels] packed (D + L)^-1, column-major lower
     const void* r0;          // r = y - H x0 (B)
     void* x;                 // in: x0 (U); out: x
@@ -349,11 +366,9 @@ __global__ __launch_bounds__(SR_NT) void k_cd_sparse(const SparseRsArgs a) {
     constexpr int VPW = KP / NWV;          // matvec columns per wave
     __shared__ V rs[NT * RPT];
     __shared__ V Ms[NE];
-    __shared__ V part[NWV][KP];
     __shared__ V bsh[KP], dsh[KP];
     __shared__ V cbuf[SR_CAP];
-    __shared__ int32_t rbuf[SR_CAP];
-    __shared__ double stop_s[2];
+    __shared__ double stop_s[NWV][2];
     __shared__ int fail_s;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -401,8 +416,19 @@ __global__ __launch_bounds__(SR_NT) void k_cd_sparse(const SparseRsArgs a) {
     ptrs(1 % np, lo1, hi1);
     ptrs(2 % np, lo2, hi2);
     int32_t nb_next = a.bcnt[(int64_t)s * np];
-    // M_{K+1}, loaded during panel K into registers (scalar arrays: kept in registers);
-    // x_{K+1} likewise (wave 0)
+    // the owned rows' slot ranges in the current block (ro*) and the next one (rn*)
+    int32_t ro0[RPT], ro1[RPT], rn0[RPT], rn1[RPT];
+    auto fetch_roff = [&](int K) {
+        const int32_t* ro = a.roff + ((int64_t)s * np + K) * (a.R + 1);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = min(tid + q * NT, a.R);
+            rn0[q] = ro[i];
+            rn1[q] = ro[min(i + 1, a.R)];
+        }
+    };
+    fetch_roff(0);
+    // M_{K+1}, loaded during panel K into registers (scalar arrays: kept in registers)
     T mre[MPT], mim[MPT];
     auto fetch_M = [&](int K) {
         const V* Mk = Mg + (int64_t)K * NE;
@@ -414,11 +440,10 @@ __global__ __launch_bounds__(SR_NT) void k_cd_sparse(const SparseRsArgs a) {
         }
     };
     for (int e = tid; e < NE; e += NT) Ms[e] = Mg[e];
-    V xN = czero<T>();
+    const int cl = w * 16 + (lane & 15), grp = lane >> 4;
     __syncthreads();
-    if (w == 0) xN = xp[min(lane, U - 1)];
 
-    double S = 0.0, Xn = 0.0;     // stopping sums (wave 0)
+    double S = 0.0, Xn = 0.0;     // stopping sums (group-0 lanes of each wave)
     int sweeps = 0;
     bool failed = false;
     uint32_t seq = 0;
@@ -437,6 +462,11 @@ __global__ __launch_bounds__(SR_NT) void k_cd_sparse(const SparseRsArgs a) {
             for (int k = 0; k < SR_EG; ++k) {
                 ek[k] = nk[k];
                 ev[k] = nv[k];
+            }
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                ro0[q] = rn0[q];
+                ro1[q] = rn1[q];
             }
             // 1. partial of this slice (reads from clamped indices, products masked: no
             //    branch between the LDS reads; entries past the register window: direct loads)
@@ -465,20 +495,24 @@ __global__ __launch_bounds__(SR_NT) void k_cd_sparse(const SparseRsArgs a) {
             hi1 = hi2;
             ptrs(K3, lo2, hi2);
             nb_next = a.bcnt[(int64_t)s * np + K1];
+            fetch_roff(K1);
             fetch_M(K1);
-            const int uK = K * KP + lane;
-            V xK = xN;
-            // 3. exchange: wave w sums slices w, w + 4, ... of column `lane`, fixed order.
-            //    Each attempt issues all of its loads before testing any tag.
+            // exchange and panel product: wave w owns columns [16 w, 16 w + 16); lane l
+            // takes column cl = 16 w + (l & 15) and group l >> 4 of the slices (exchange)
+            // or of the v range (panel product), the four groups meeting in a butterfly
+            const int uK = K * KP + cl;
+            V xK = xp[min(uK, U - 1)];   // used after the exchange
+            // 3. exchange: group g sums slices g, g + 4, ... of column cl in order; each
+            //    attempt issues all of its loads before testing any tag
             {
                 V acc = czero<T>();
-                for (int s0 = w; s0 < P && !failed; s0 += NWV * SR_SC) {
+                for (int s0 = 0; s0 < P && !failed; s0 += NWV * SR_SC) {
                     V v[SR_SC];
                     bool have[SR_SC];
 #pragma unroll
                     for (int k = 0; k < SR_SC; ++k) {
                         v[k] = czero<T>();
-                        have[k] = s0 + NWV * k >= P;
+                        have[k] = s0 + NWV * k + grp >= P;
                     }
                     uint64_t t0 = 0;
                     bool started = false;
@@ -488,7 +522,7 @@ __global__ __launch_bounds__(SR_NT) void k_cd_sparse(const SparseRsArgs a) {
 #pragma unroll
                         for (int k = 0; k < SR_SC; ++k) {
                             const uint64_t* src =
-                                a.xbuf + (((int64_t)par * P + min(s0 + NWV * k, P - 1)) * KP + lane) * NW;
+                                a.xbuf + (((int64_t)par * P + min(s0 + NWV * k + grp, P - 1)) * KP + cl) * NW;
                             const bool want = __any(!have[k]);
 #pragma unroll
                             for (int i = 0; i < NW; ++i) wd[k][i] = want ? sp_ld(src + i) : 0;
@@ -522,7 +556,12 @@ __global__ __launch_bounds__(SR_NT) void k_cd_sparse(const SparseRsArgs a) {
                         acc.y += v[k].y;
                     }
                 }
-                part[w][lane] = acc;
+                acc.x += __shfl_xor(acc.x, 16, 64);
+                acc.y += __shfl_xor(acc.y, 16, 64);
+                acc.x += __shfl_xor(acc.x, 32, 64);
+                acc.y += __shfl_xor(acc.y, 32, 64);
+                if (uK >= U) xK = czero<T>();
+                if (grp == 0) bsh[cl] = cmake<T>(acc.x - lambda * xK.x, acc.y - lambda * xK.y);
                 if (failed && lane == 0) fail_s = 1;
             }
             __syncthreads();
@@ -530,23 +569,10 @@ __global__ __launch_bounds__(SR_NT) void k_cd_sparse(const SparseRsArgs a) {
                 failed = true;
                 break;
             }
-            if (w == 0) {
-                V b = part[0][lane];
-#pragma unroll
-                for (int k = 1; k < NWV; ++k) {
-                    b.x += part[k][lane].x;
-                    b.y += part[k][lane].y;
-                }
-                if (uK >= U) xK = czero<T>();
-                b.x -= lambda * xK.x;
-                b.y -= lambda * xK.y;
-                bsh[lane] = b;
-            }
-            __syncthreads();
-            // 4. delta = (D + L)^-1 b: thread (j, wave w) sums v in [16 w, 16 w + 16), v <= j
-            //    (every read index stays inside the packed triangle; v > j is masked)
+            // 4. delta = (D + L)^-1 b: lane (j = cl, group g) sums v in [16 g, 16 g + 16),
+            //    v <= j (every read index stays inside the packed triangle; v > j is masked)
             {
-                const int j = lane, v0 = w * VPW;
+                const int j = cl, v0 = grp * VPW;
                 V d = czero<T>();
 #pragma unroll
                 for (int k = 0; k < VPW; ++k) {
@@ -557,69 +583,65 @@ __global__ __launch_bounds__(SR_NT) void k_cd_sparse(const SparseRsArgs a) {
                     m.y = v <= j ? m.y : T(0);
                     cfma(d, m, bb);
                 }
-                part[w][j] = d;
+                d.x += __shfl_xor(d.x, 16, 64);
+                d.y += __shfl_xor(d.y, 16, 64);
+                d.x += __shfl_xor(d.x, 32, 64);
+                d.y += __shfl_xor(d.y, 32, 64);
+                xK = cmake<T>(xK.x + d.x, xK.y + d.y);
+                if (grp == 0) {
+                    dsh[cl] = d;
+                    if (uK < U) {
+                        S += cabs2d(d);
+                        Xn += cabs2d(xK);
+                        xp[uK] = xK;
+                    }
+                }
             }
             __syncthreads();
-            // stage M_{K+1} (its loads were issued before the exchange)
+            // stage M_{K+1} (its loads were issued before the exchange; the panel product
+            // that read M_K is done)
 #pragma unroll
             for (int k = 0; k < MPT; ++k) {
                 const int e = tid + k * NT;
                 if (e < NE) Ms[e] = cmake<T>(mre[k], mim[k]);
             }
-            if (w == 0) {
-                V d = part[0][lane];
-#pragma unroll
-                for (int k = 1; k < NWV; ++k) {
-                    d.x += part[k][lane].x;
-                    d.y += part[k][lane].y;
-                }
-                dsh[lane] = d;
-                xK = cmake<T>(xK.x + d.x, xK.y + d.y);
-                if (uK < U) {
-                    S += cabs2d(d);
-                    Xn += cabs2d(xK);
-                    xp[uK] = xK;
-                }
-                xN = xp[min(K1 * KP + lane, U - 1)];
-            }
-            __syncthreads();
             // 5. r_s -= H_{K,s} delta: every entry's term goes to its row-order slot of the
-            //    block, then the first slot of each row adds the row's terms in order
-            //    (blocks larger than the staging area take several passes)
+            //    block, then each thread adds its own rows' slots in order (blocks larger
+            //    than the staging area take several passes)
             {
                 const V dj = dsh[jl];
                 for (int c0 = 0; c0 < nb; c0 += SR_CAP) {
 #pragma unroll
                     for (int k = 0; k < SR_EG; ++k) {
                         const int q = (ek[k] >> 12) - c0;
-                        if (glo + gq + SR_G * k < ghi && q >= 0 && q < SR_CAP) {
-                            cbuf[q] = cmul(ev[k], dj);
-                            rbuf[q] = ek[k] & 4095;
-                        }
+                        if (glo + gq + SR_G * k < ghi && q >= 0 && q < SR_CAP) cbuf[q] = cmul(ev[k], dj);
                     }
                     for (int32_t e = glo + gq + SR_G * SR_EG; e < ghi; e += SR_G) {
-                        const int32_t pe = pkg[e];
-                        const int q = (pe >> 12) - c0;
-                        if (q >= 0 && q < SR_CAP) {
-                            cbuf[q] = cmul(cval[e], dj);
-                            rbuf[q] = pe & 4095;
-                        }
+                        const int q = (pkg[e] >> 12) - c0;
+                        if (q >= 0 && q < SR_CAP) cbuf[q] = cmul(cval[e], dj);
                     }
                     __syncthreads();
                     const int lim = min(SR_CAP, nb - c0);
-                    for (int q = tid; q < lim; q += NT) {
-                        const int r = rbuf[q];
-                        if (q > 0 && rbuf[q - 1] == r) continue;
-                        V acc = cbuf[q];
-                        for (int q2 = q + 1; q2 < lim && rbuf[q2] == r; ++q2) {
-                            acc.x += cbuf[q2].x;
-                            acc.y += cbuf[q2].y;
+                    int qa[RPT], qb[RPT];
+                    V acc[RPT], rv[RPT];
+#pragma unroll
+                    for (int q = 0; q < RPT; ++q) {
+                        const bool own = tid + q * NT < nrow;
+                        qa[q] = max(ro0[q] - c0, 0);
+                        qb[q] = own ? min(ro1[q] - c0, lim) : 0;
+                        acc[q] = cbuf[qa[q] < qb[q] ? qa[q] : 0];
+                        rv[q] = rs[own ? tid + q * NT : 0];
+                    }
+#pragma unroll
+                    for (int q = 0; q < RPT; ++q) {
+                        if (qa[q] >= qb[q]) continue;
+                        for (int j = qa[q] + 1; j < qb[q]; ++j) {
+                            acc[q].x += cbuf[j].x;
+                            acc[q].y += cbuf[j].y;
                         }
-                        const int rr = min((unsigned)r, (unsigned)(NT * RPT - 1));   // (always r)
-                        V rv = rs[rr];
-                        rv.x -= acc.x;
-                        rv.y -= acc.y;
-                        rs[rr] = rv;
+                        rv[q].x -= acc[q].x;
+                        rv[q].y -= acc[q].y;
+                        rs[tid + q * NT] = rv[q];
                     }
                     __syncthreads();
                 }
@@ -627,16 +649,21 @@ __global__ __launch_bounds__(SR_NT) void k_cd_sparse(const SparseRsArgs a) {
         }
         if (failed) break;
         sweeps = t;
-        if (w == 0) {
+        {
             const double s1 = wave_allsum(S), s2 = wave_allsum(Xn);
             if (lane == 0) {
-                stop_s[0] = s1;
-                stop_s[1] = s2;
+                stop_s[w][0] = s1;
+                stop_s[w][1] = s2;
             }
         }
         __syncthreads();
-        S = stop_s[0];
-        Xn = stop_s[1];
+        S = stop_s[0][0];
+        Xn = stop_s[0][1];
+#pragma unroll
+        for (int k = 1; k < NWV; ++k) {
+            S += stop_s[k][0];
+            Xn += stop_s[k][1];
+        }
         __syncthreads();
         if (a.tol > 0.0 && sqrt(S) <= a.tol * sqrt(Xn)) break;
     }
@@ -706,7 +733,7 @@ template <typename T> static hipError_t launch_sparse_t(const SparseLaunch& L, h
     hipLaunchKernelGGL(k_sparse_slices, dim3((unsigned)((nsp + 255) / 256)), dim3(256), 0, st, L.colptr, L.rowidx,
                        L.B, L.U, L.P, L.R, L.spt);
     hipLaunchKernelGGL(k_sparse_rank, dim3((unsigned)(L.P * L.npanels)), dim3(256), 0, st, L.rowidx, L.spt, L.U,
-                       L.npanels, L.R, L.pi, L.bcnt);
+                       L.npanels, L.R, L.pi, L.bcnt, L.roff);
     const int n = L.B > L.U ? L.B : L.U;
     hipLaunchKernelGGL((k_sparse_init<T>), dim3((n + 255) / 256), dim3(256), 0, st, L.rowptr, L.colidx,
                        (const V*)L.val, (const V*)L.y, L.B, (const V*)L.x0, L.U, (V*)L.r, (V*)L.x);
@@ -717,6 +744,7 @@ template <typename T> static hipError_t launch_sparse_t(const SparseLaunch& L, h
     A.pk = L.pi;
     A.spt = L.spt;
     A.bcnt = L.bcnt;
+    A.roff = L.roff;
     A.M = L.M;
     A.r0 = L.r;
     A.x = L.x;

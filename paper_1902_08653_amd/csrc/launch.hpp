@@ -193,6 +193,7 @@ struct SparseLaunch {
     int32_t* spt;            // [P+1][U] slice pointers into the column-compressed form
     int32_t* pi;             // [nnz] row-order position of each entry inside its block
     int32_t* bcnt;           // [P][npanels] block entry counts
+    int32_t* roff;           // [P][npanels][R+1] row starts inside each block
     void* xp;                // [P][U] per-workgroup copies of x
     uint64_t* xbuf;          // [2][P][64][4] tagged partials
     uint32_t* abort_flag;

@@ -123,6 +123,7 @@ struct cdm_plan {
     int32_t* sp_spt = nullptr;
     int32_t* sp_pi = nullptr;
     int32_t* sp_bcnt = nullptr;
+    int32_t* sp_roff = nullptr;
     void* sp_xp = nullptr;
     uint64_t* sp_xbuf = nullptr;
     int sp_P = 1, sp_R = 1;
@@ -249,6 +250,7 @@ static int32_t create_sparse(cdm_plan* p, cdm_plan** plan) {
     const size_t o_spt = ar.take(4 * (size_t)(p->sp_P + 1) * d.U);
     const size_t o_pi = ar.take(4 * nnz);
     const size_t o_bcnt = ar.take(4 * (size_t)p->sp_P * p->npanels);
+    const size_t o_roff = ar.take(4 * (size_t)p->sp_P * p->npanels * (p->sp_R + 1));
     const size_t o_xp = ar.take(p->esz * (size_t)p->sp_P * d.U);
     const size_t o_xbuf = ar.take(8 * (size_t)2 * p->sp_P * kSpKp * 4);
     int32_t st = alloc_ws(p, ar.off);
@@ -269,6 +271,7 @@ static int32_t create_sparse(cdm_plan* p, cdm_plan** plan) {
     p->sp_spt = (int32_t*)(b + o_spt);
     p->sp_pi = (int32_t*)(b + o_pi);
     p->sp_bcnt = (int32_t*)(b + o_bcnt);
+    p->sp_roff = (int32_t*)(b + o_roff);
     p->sp_xp = b + o_xp;
     p->sp_xbuf = (uint64_t*)(b + o_xbuf);
     char buf[512];
@@ -321,6 +324,7 @@ static int32_t run_sparse(cdm_plan* p, const void* val, const int32_t* rowptr, c
     L.spt = p->sp_spt;
     L.pi = p->sp_pi;
     L.bcnt = p->sp_bcnt;
+    L.roff = p->sp_roff;
     L.xp = p->sp_xp;
     L.xbuf = p->sp_xbuf;
     L.abort_flag = p->ctr + 2;
