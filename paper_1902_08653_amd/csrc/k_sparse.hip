@@ -263,7 +263,7 @@ constexpr int SR_NT = 256;                // 4 waves
 constexpr int SR_KP = 64;                 // panel width
 constexpr int SR_G = SR_NT / SR_KP;       // threads per column in the partial (a quad)
 #ifndef CDM_SPARSE_EG
-#define CDM_SPARSE_EG 4
+#define CDM_SPARSE_EG 6
 #endif
 constexpr int SR_EG = CDM_SPARSE_EG;      // block entries per thread held in registers
 constexpr int SR_SC = 4;                  // slices read per exchange attempt (per thread)

@@ -203,7 +203,7 @@ struct SparseLaunch {
 hipError_t launch_sparse(const SparseLaunch& L, hipStream_t st);
 // Rows per slice the sparse sweep aims for (slices = ceil(B / rows), 1..64).
 #ifndef CDM_SPARSE_SLICE_ROWS
-#define CDM_SPARSE_SLICE_ROWS 512
+#define CDM_SPARSE_SLICE_ROWS 1024
 #endif
 void sparse_slices(int B, int ncu, int& P, int& R);
 int sparse_rows_per_thread(int R);   // 0: R too large for the sweep's LDS slice
