@@ -129,7 +129,7 @@ const char* cdm_last_error(void);
  * Validates the descriptor, picks the engine and tiles, and allocates the whole
  * device workspace, so that cdm_solve itself never allocates.
  * CDM_CSR plans (uplink, C = 1, CDM_C128 or CDM_C64): the sweep cuts the rows into
- * slices of about 512 (at most 128 slices, one workgroup each, at most 2048 rows per
+ * slices of about 1024 (at most 64 slices, one workgroup each, at most 4096 rows per
  * slice), so B <= 262144; the workspace holds the column-compressed copy and about
  * 4 B per stored entry more.
  * Errors: CDM_EINVAL, CDM_ESHAPE, CDM_EDTYPE, CDM_EINFEASIBLE (downlink with

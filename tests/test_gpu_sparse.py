@@ -61,7 +61,8 @@ def oracle_sparse(orc, ins, prec, T, tol=0.0, lam=0.1, x0=None):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("B,U,dens,T", [(300, 140, 0.05, 3), (2000, 700, 0.02, 4), (1000, 1000, 0.01, 2)])
+@pytest.mark.parametrize("B,U,dens,T", [(300, 140, 0.05, 3), (2000, 700, 0.02, 4), (1000, 1000, 0.01, 2),
+                                        (200, 90, 0.05, 3)])
 def test_sparse_sweeps_match_oracle(dev, orc, prec, B, U, dens, T):
     ins = inputs.sparse_uplink(B, U, dens, seed=7 * B + U)
     x, info, desc = run_sparse(dev, ins, prec, T)
@@ -141,3 +142,16 @@ def test_sparse_results_repeat_bit_for_bit(dev):
     a, _, _ = run_sparse(dev, ins, "c128", 5)
     b, _, _ = run_sparse(dev, ins, "c128", 5)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("B", [100000, 140000])
+def test_sparse_many_slices(dev, orc, B):
+    """The slice count at its cap (64 workgroups, so every exchange reads 64 partial
+    vectors) with slices of about 1,560 and 2,190 rows: 8 and 16 rows per thread."""
+    ins = inputs.sparse_uplink(B, 100, 0.01, seed=13)
+    x, info, desc = run_sparse(dev, ins, "c128", 3)
+    ref = oracle_sparse(orc, ins, "c128", 3)
+    err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+    print(desc, err)
+    assert '"workgroups": 64' in desc
+    assert info["sweeps"] == 3 and err <= TOL["c128"]
