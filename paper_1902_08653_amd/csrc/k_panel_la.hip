@@ -37,8 +37,9 @@ namespace cdm {
 constexpr int LA_NWT = 8;                 // tile waves
 constexpr int LA_NT = 64 * (LA_NWT + 1);  // + one control wave
 
-// Tagged words: a 32-bit payload and a 32-bit tag (panel sequence number + 1) in one
-// 64-bit word, stored and loaded single-copy atomically at agent scope.  A reader
+// Tagged words: a payload and a tag (panel sequence number + 1) in one 64-bit word
+// (complex64: 32 + 32 bits; complex128: 48 + 16), stored and loaded single-copy
+// atomically at agent scope.  A reader
 // that sees the expected tag in every word of a value has that value, so the data is
 // its own arrival signal: no store drain, no separate flag and no second read.  The
 // exchange buffers are cleared before each launch.
@@ -51,22 +52,30 @@ __device__ __forceinline__ uint64_t ld_tag(const uint64_t* p) {
                              __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T> struct Tagged;
-template <> struct Tagged<double> {             // complex128: four words (lo, hi of re and im)
-    static constexpr int NW = 4;
+template <> struct Tagged<double> {
+    // complex128: the 128 payload bits in three words of 48 bits, each with a 16-bit tag
+    // (sequence + 1 modulo 2^16; a slot is rewritten every second sequence, so the value
+    // it held before carries a different tag)
+    static constexpr int NW = 3;
+    __device__ static void st48(uint64_t* p, uint64_t payload, uint32_t tag) {
+        __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                           (unsigned long long)((payload & 0xffffffffffffull) | ((uint64_t)(tag & 0xffffu) << 48)),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __device__ static void put(uint64_t* p, double2 v, uint32_t tag) {
-        const unsigned long long a = __double_as_longlong(v.x), b = __double_as_longlong(v.y);
-        st_tag(p + 0, (uint32_t)a, tag);
-        st_tag(p + 1, (uint32_t)(a >> 32), tag);
-        st_tag(p + 2, (uint32_t)b, tag);
-        st_tag(p + 3, (uint32_t)(b >> 32), tag);
+        const uint64_t a = (uint64_t)__double_as_longlong(v.x), b = (uint64_t)__double_as_longlong(v.y);
+        st48(p + 0, a, tag);
+        st48(p + 1, (a >> 48) | (b << 16), tag);
+        st48(p + 2, b >> 32, tag);
     }
     // the words are loaded before any is tested (one memory round trip per attempt)
     __device__ static bool get(const uint64_t* p, uint32_t tag, double2& v) {
-        const uint64_t w0 = ld_tag(p + 0), w1 = ld_tag(p + 1), w2 = ld_tag(p + 2), w3 = ld_tag(p + 3);
-        const bool ok = ((uint32_t)(w0 >> 32) == tag) & ((uint32_t)(w1 >> 32) == tag) &
-                        ((uint32_t)(w2 >> 32) == tag) & ((uint32_t)(w3 >> 32) == tag);
-        v.x = __longlong_as_double((long long)(((w1 & 0xffffffffull) << 32) | (w0 & 0xffffffffull)));
-        v.y = __longlong_as_double((long long)(((w3 & 0xffffffffull) << 32) | (w2 & 0xffffffffull)));
+        const uint64_t w0 = ld_tag(p + 0), w1 = ld_tag(p + 1), w2 = ld_tag(p + 2);
+        const uint64_t t = (uint64_t)(tag & 0xffffu);
+        const bool ok = ((w0 >> 48) == t) & ((w1 >> 48) == t) & ((w2 >> 48) == t);
+        const uint64_t m = 0xffffffffffffull;
+        v.x = __longlong_as_double((long long)((w0 & m) | ((w1 & 0xffffull) << 48)));
+        v.y = __longlong_as_double((long long)(((w1 & m) >> 16) | ((w2 & 0xffffffffull) << 32)));
         return ok;
     }
 };
