@@ -33,6 +33,8 @@ constexpr int SM_RPL = 8;             // rows per lane
 constexpr int SM_BMAX = SM_LPT * SM_RPL;   // antennas per cluster at most
 constexpr int SM_UMAX = 16;           // users per cluster at most
 constexpr size_t SM_LDS = 64 * 1024;  // LDS budget of one workgroup
+// Vectors per quad (VQ): with two, a lane runs two independent chains that share each
+// channel read -- more work in flight per wave, half as many waves.  Chosen per launch.
 
 template <bool F16> struct SmNum;
 template <> struct SmNum<false> {
@@ -96,7 +98,7 @@ template <int UMAX> static size_t sm_lds_bytes(int NS, int C, int V, bool f16) {
     return (size_t)NS * C * sm_block<UMAX>(f16) * esz + (size_t)NS * C * V * UMAX * 8 + (size_t)NS * C * 4;
 }
 
-template <bool F16, int UMAX>
+template <bool F16, int UMAX, int VQ>
 __global__ __launch_bounds__(SM_NT) void k_detect_small(const typename SmNum<F16>::E* __restrict__ H,
                                                         const typename SmNum<F16>::E* __restrict__ Y,
                                                         typename SmNum<F16>::E* __restrict__ X, int S, int V, int C,
@@ -123,18 +125,24 @@ __global__ __launch_bounds__(SM_NT) void k_detect_small(const typename SmNum<F16
     __syncthreads();
     // ---- one task per quad: T sweeps of Algorithm 1 on (H_{s,c}, y_{s,v,c}).  The loop
     // bound is the same for the four lanes of a quad, so a quad is always whole.
-    const int tasks = ns * C * V;
+    const int VP = (V + VQ - 1) / VQ;
+    const int tasks = ns * C * VP;
     const int j = tid % SM_LPT;
     for (int t = tid / SM_LPT; t < tasks; t += SM_NT / SM_LPT) {
-        const int sub = t / (C * V), rem = t % (C * V);
-        const int c = rem / V, v = rem % V;
+        const int sub = t / (C * VP), rem = t % (C * VP);
+        const int c = rem / VP, v0 = (rem % VP) * VQ;
         const E* hb = Hl + (sub * C + c) * BLK + j;     // this lane's rows: j + 4 k
-        const E* yv = Y + ((int64_t)(s0 + sub) * V + v) * B + c * Bc;
-        E r[SM_RPL];
+        // the residuals of vectors v0, v0 + 1 (a vector past V is carried as zeros)
+        E r[VQ][SM_RPL];
 #pragma unroll
-        for (int k = 0; k < SM_RPL; ++k) {
-            const int i = j + SM_LPT * k;
-            r[k] = i < Bc ? yv[i] : N::zero();
+        for (int q = 0; q < VQ; ++q) {
+            const int v = v0 + q;
+            const E* yv = Y + ((int64_t)(s0 + sub) * V + min(v, V - 1)) * B + c * Bc;
+#pragma unroll
+            for (int k = 0; k < SM_RPL; ++k) {
+                const int i = j + SM_LPT * k;
+                r[q][k] = (i < Bc && v < V) ? yv[i] : N::zero();
+            }
         }
         // Algorithm 1 preprocessing: m_u = 1/(||h_u||^2 + lambda), n_u = m_u ||h_u||^2 (FP32;
         // a column with ||h_u||^2 + lambda == 0 stays inactive: (0, 1))
@@ -154,31 +162,53 @@ __global__ __launch_bounds__(SM_NT) void k_detect_small(const typename SmNum<F16
             nu[u] = act ? mu[u] * e : 1.f;
             if (u < U) msum += mu[u];
         }
-        float2 x[UMAX];
+        float2 x[VQ][UMAX];
 #pragma unroll
-        for (int u = 0; u < UMAX; ++u) x[u] = make_float2(0.f, 0.f);
+        for (int q = 0; q < VQ; ++q)
+#pragma unroll
+            for (int u = 0; u < UMAX; ++u) x[q][u] = make_float2(0.f, 0.f);
         for (int it = 0; it < T; ++it) {
 #pragma unroll
             for (int u = 0; u < UMAX; ++u) {
                 if (u < U) {
-                    float2 g = make_float2(0.f, 0.f);
+                    E h[SM_RPL];
 #pragma unroll
-                    for (int k = 0; k < SM_RPL; ++k) N::dot_acc(g, hb[u * SM_BMAX + SM_LPT * k], r[k]);
-                    g.x = quad_sum(g.x);
-                    g.y = quad_sum(g.y);
-                    const float2 xn = make_float2(mu[u] * g.x + nu[u] * x[u].x, mu[u] * g.y + nu[u] * x[u].y);
-                    const float2 d = make_float2(xn.x - x[u].x, xn.y - x[u].y);
-                    x[u] = xn;
+                    for (int k = 0; k < SM_RPL; ++k) h[k] = hb[u * SM_BMAX + SM_LPT * k];
+                    float2 g[VQ];
 #pragma unroll
-                    for (int k = 0; k < SM_RPL; ++k) N::axpy(r[k], hb[u * SM_BMAX + SM_LPT * k], d);
+                    for (int q = 0; q < VQ; ++q) {
+                        g[q] = make_float2(0.f, 0.f);
+#pragma unroll
+                        for (int k = 0; k < SM_RPL; ++k) N::dot_acc(g[q], h[k], r[q][k]);
+                    }
+#pragma unroll
+                    for (int q = 0; q < VQ; ++q) {
+                        g[q].x = quad_sum(g[q].x);
+                        g[q].y = quad_sum(g[q].y);
+                    }
+#pragma unroll
+                    for (int q = 0; q < VQ; ++q) {
+                        const float2 xn = make_float2(mu[u] * g[q].x + nu[u] * x[q][u].x,
+                                                      mu[u] * g[q].y + nu[u] * x[q][u].y);
+                        const float2 d = make_float2(xn.x - x[q][u].x, xn.y - x[q][u].y);
+                        x[q][u] = xn;
+#pragma unroll
+                        for (int k = 0; k < SM_RPL; ++k) N::axpy(r[q][k], h[k], d);
+                    }
                 }
             }
         }
         if (j == 0) {
-            float2* xo = xl + ((sub * C + c) * V + v) * UMAX;
 #pragma unroll
-            for (int u = 0; u < UMAX; ++u) xo[u] = x[u];
-            if (v == 0) wl[sub * C + c] = msum;
+            for (int q = 0; q < VQ; ++q) {
+                const int v = v0 + q;
+                if (v < V) {
+                    float2* xo = xl + ((sub * C + c) * V + v) * UMAX;
+#pragma unroll
+                    for (int u = 0; u < UMAX; ++u) xo[u] = x[q][u];
+                }
+            }
+            if (v0 == 0) wl[sub * C + c] = msum;
         }
     }
     __syncthreads();
@@ -198,19 +228,35 @@ __global__ __launch_bounds__(SM_NT) void k_detect_small(const typename SmNum<F16
     }
 }
 
-template <bool F16, int UMAX>
-static hipError_t launch_small(const void* H, const void* Y, void* X, int S, int V, int C, int Bc, int U, int T,
-                               float lam, hipStream_t st) {
+// Two vectors per quad pay off for FP16 when they still leave at least four waves per SIMD
+// of the whole chip (measured on the paper's shapes: FP16 with 8 clusters gains, every
+// FP32 shape and FP16 with 4 clusters do not)
+static int sm_vectors_per_quad(bool f16, int S, int C, int V) {
+    const int64_t waves2 = (int64_t)S * C * ((V + 1) / 2) * SM_LPT / 64;
+    return (f16 && waves2 >= 4 * 1024) ? 2 : 1;
+}
+
+template <bool F16, int UMAX, int VQ>
+static hipError_t launch_small_vq(const void* H, const void* Y, void* X, int S, int V, int C, int Bc, int U, int T,
+                                  float lam, hipStream_t st) {
     using E = typename SmNum<F16>::E;
     // subcarriers per workgroup: enough tasks to fill the 64 quads, within the LDS budget
-    int NS = std::max(1, SM_NT / SM_LPT / (C * V));
+    const int VP = (V + VQ - 1) / VQ;
+    int NS = std::max(1, SM_NT / SM_LPT / (C * VP));
     while (NS > 1 && sm_lds_bytes<UMAX>(NS, C, V, F16) > SM_LDS) --NS;
     const size_t lds = sm_lds_bytes<UMAX>(NS, C, V, F16);
     if (lds > SM_LDS) return hipErrorInvalidValue;   // within the default dynamic LDS limit
     const int blocks = (S + NS - 1) / NS;
-    hipLaunchKernelGGL((k_detect_small<F16, UMAX>), dim3(blocks), dim3(SM_NT), lds, st, (const E*)H, (const E*)Y,
-                       (E*)X, S, V, C, Bc, U, T, lam, NS);
+    hipLaunchKernelGGL((k_detect_small<F16, UMAX, VQ>), dim3(blocks), dim3(SM_NT), lds, st, (const E*)H,
+                       (const E*)Y, (E*)X, S, V, C, Bc, U, T, lam, NS);
     return hipGetLastError();
+}
+template <bool F16, int UMAX>
+static hipError_t launch_small(const void* H, const void* Y, void* X, int S, int V, int C, int Bc, int U, int T,
+                               float lam, hipStream_t st) {
+    return sm_vectors_per_quad(F16, S, C, V) == 2
+               ? launch_small_vq<F16, UMAX, 2>(H, Y, X, S, V, C, Bc, U, T, lam, st)
+               : launch_small_vq<F16, UMAX, 1>(H, Y, X, S, V, C, Bc, U, T, lam, st);
 }
 
 // ---- downlink: Algorithm 2 on the same shape ---------------------------------------
@@ -224,7 +270,7 @@ template <int UMAX> static size_t sm_pre_lds_bytes(int NS, int C, bool f16) {
     return (size_t)NS * C * sm_block<UMAX>(f16) * (f16 ? 4 : 8);
 }
 
-template <bool F16, int UMAX>
+template <bool F16, int UMAX, int VQ>
 __global__ __launch_bounds__(SM_NT) void k_precode_small(const typename SmNum<F16>::E* __restrict__ H,
                                                          const typename SmNum<F16>::E* __restrict__ Sym,
                                                          typename SmNum<F16>::E* __restrict__ X, int S, int V, int C,
@@ -246,16 +292,17 @@ __global__ __launch_bounds__(SM_NT) void k_precode_small(const typename SmNum<F1
         Hl[k * BLK + u * SM_BMAX + i] = v;
     }
     __syncthreads();
-    const int tasks = ns * C * V;
+    const int VP = (V + VQ - 1) / VQ;
+    const int tasks = ns * C * VP;
     const int j = tid % SM_LPT;
     for (int t = tid / SM_LPT; t < tasks; t += SM_NT / SM_LPT) {
-        const int sub = t / (C * V), rem = t % (C * V);
-        const int c = rem / V, v = rem % V;
+        const int sub = t / (C * VP), rem = t % (C * VP);
+        const int c = rem / VP, v0 = (rem % VP) * VQ;
         const E* hb = Hl + (sub * C + c) * BLK + j;
-        const E* sv = Sym + ((int64_t)(s0 + sub) * V + v) * U;
-        // preprocessing (FP32): p_u = 1/||h_u|| (a zero column stays inactive), sbar_u
+        // preprocessing (FP32): p_u = 1/||h_u|| (a zero column stays inactive), and sbar_u
+        // of vectors v0, v0 + 1 (a vector past V is carried as zeros)
         float pu[UMAX];
-        float2 sb[UMAX];
+        float2 sb[VQ][UMAX];
 #pragma unroll
         for (int u = 0; u < UMAX; ++u) {
             float e = 0.f;
@@ -266,65 +313,100 @@ __global__ __launch_bounds__(SM_NT) void k_precode_small(const typename SmNum<F1
             }
             e = quad_sum(e);
             pu[u] = (u < U && e > 0.f) ? 1.f / sqrtf(e) : 0.f;
-            const float2 su = u < U ? N::to_f(sv[u]) : make_float2(0.f, 0.f);
-            sb[u] = make_float2(pu[u] * su.x, pu[u] * su.y);
-        }
-        E x[SM_RPL];
 #pragma unroll
-        for (int k = 0; k < SM_RPL; ++k) x[k] = N::zero();
+            for (int q = 0; q < VQ; ++q) {
+                const int v = v0 + q;
+                const E* sv = Sym + ((int64_t)(s0 + sub) * V + min(v, V - 1)) * U;
+                const float2 su = (u < U && v < V) ? N::to_f(sv[u]) : make_float2(0.f, 0.f);
+                sb[q][u] = make_float2(pu[u] * su.x, pu[u] * su.y);
+            }
+        }
+        E x[VQ][SM_RPL];
+#pragma unroll
+        for (int q = 0; q < VQ; ++q)
+#pragma unroll
+            for (int k = 0; k < SM_RPL; ++k) x[q][k] = N::zero();
         for (int it = 0; it < T; ++it) {
 #pragma unroll
             for (int u = 0; u < UMAX; ++u) {
                 if (pu[u] != 0.f) {   // equal in the four lanes of the quad
-                    float2 g = make_float2(0.f, 0.f);
+                    E h[SM_RPL];
 #pragma unroll
-                    for (int k = 0; k < SM_RPL; ++k) N::dot_acc(g, hb[u * SM_BMAX + SM_LPT * k], x[k]);
-                    g.x = quad_sum(g.x);
-                    g.y = quad_sum(g.y);
-                    const float2 d = make_float2(pu[u] * (pu[u] * g.x - sb[u].x), pu[u] * (pu[u] * g.y - sb[u].y));
+                    for (int k = 0; k < SM_RPL; ++k) h[k] = hb[u * SM_BMAX + SM_LPT * k];
+                    float2 g[VQ];
 #pragma unroll
-                    for (int k = 0; k < SM_RPL; ++k) N::axpy(x[k], hb[u * SM_BMAX + SM_LPT * k], d);
+                    for (int q = 0; q < VQ; ++q) {
+                        g[q] = make_float2(0.f, 0.f);
+#pragma unroll
+                        for (int k = 0; k < SM_RPL; ++k) N::dot_acc(g[q], h[k], x[q][k]);
+                    }
+#pragma unroll
+                    for (int q = 0; q < VQ; ++q) {
+                        g[q].x = quad_sum(g[q].x);
+                        g[q].y = quad_sum(g[q].y);
+                    }
+#pragma unroll
+                    for (int q = 0; q < VQ; ++q) {
+                        const float2 d = make_float2(pu[u] * (pu[u] * g[q].x - sb[q][u].x),
+                                                     pu[u] * (pu[u] * g[q].y - sb[q][u].y));
+#pragma unroll
+                        for (int k = 0; k < SM_RPL; ++k) N::axpy(x[q][k], h[k], d);
+                    }
                 }
             }
         }
-        if (rho_c > 0.f) {
-            float nn = 0.f;
 #pragma unroll
-            for (int k = 0; k < SM_RPL; ++k) {
-                const float2 xf = N::to_f(x[k]);
-                nn += xf.x * xf.x + xf.y * xf.y;
-            }
-            nn = quad_sum(nn);
-            if (nn > 0.f) {
-                const float sc = rho_c / sqrtf(nn);
+        for (int q = 0; q < VQ; ++q) {
+            const int v = v0 + q;
+            if (rho_c > 0.f) {
+                float nn = 0.f;
 #pragma unroll
                 for (int k = 0; k < SM_RPL; ++k) {
-                    const float2 xf = N::to_f(x[k]);
-                    x[k] = N::from_f(make_float2(sc * xf.x, sc * xf.y));
+                    const float2 xf = N::to_f(x[q][k]);
+                    nn += xf.x * xf.x + xf.y * xf.y;
+                }
+                nn = quad_sum(nn);
+                if (nn > 0.f) {
+                    const float sc = rho_c / sqrtf(nn);
+#pragma unroll
+                    for (int k = 0; k < SM_RPL; ++k) {
+                        const float2 xf = N::to_f(x[q][k]);
+                        x[q][k] = N::from_f(make_float2(sc * xf.x, sc * xf.y));
+                    }
                 }
             }
-        }
-        E* xo = X + ((int64_t)(s0 + sub) * V + v) * B + c * Bc;
+            if (v < V) {
+                E* xo = X + ((int64_t)(s0 + sub) * V + v) * B + c * Bc;
 #pragma unroll
-        for (int k = 0; k < SM_RPL; ++k) {
-            const int i = j + SM_LPT * k;
-            if (i < Bc) xo[i] = x[k];
+                for (int k = 0; k < SM_RPL; ++k) {
+                    const int i = j + SM_LPT * k;
+                    if (i < Bc) xo[i] = x[q][k];
+                }
+            }
         }
     }
 }
 
-template <bool F16, int UMAX>
-static hipError_t launch_precode(const void* H, const void* Sym, void* X, int S, int V, int C, int Bc, int U, int T,
-                                 float rho_c, hipStream_t st) {
+template <bool F16, int UMAX, int VQ>
+static hipError_t launch_precode_vq(const void* H, const void* Sym, void* X, int S, int V, int C, int Bc, int U,
+                                   int T, float rho_c, hipStream_t st) {
     using E = typename SmNum<F16>::E;
-    int NS = std::max(1, SM_NT / SM_LPT / (C * V));
+    const int VP = (V + VQ - 1) / VQ;
+    int NS = std::max(1, SM_NT / SM_LPT / (C * VP));
     while (NS > 1 && sm_pre_lds_bytes<UMAX>(NS, C, F16) > SM_LDS) --NS;
     const size_t lds = sm_pre_lds_bytes<UMAX>(NS, C, F16);
     if (lds > SM_LDS) return hipErrorInvalidValue;
     const int blocks = (S + NS - 1) / NS;
-    hipLaunchKernelGGL((k_precode_small<F16, UMAX>), dim3(blocks), dim3(SM_NT), lds, st, (const E*)H, (const E*)Sym,
-                       (E*)X, S, V, C, Bc, U, T, rho_c, NS);
+    hipLaunchKernelGGL((k_precode_small<F16, UMAX, VQ>), dim3(blocks), dim3(SM_NT), lds, st, (const E*)H,
+                       (const E*)Sym, (E*)X, S, V, C, Bc, U, T, rho_c, NS);
     return hipGetLastError();
+}
+template <bool F16, int UMAX>
+static hipError_t launch_precode(const void* H, const void* Sym, void* X, int S, int V, int C, int Bc, int U, int T,
+                                 float rho_c, hipStream_t st) {
+    return sm_vectors_per_quad(F16, S, C, V) == 2
+               ? launch_precode_vq<F16, UMAX, 2>(H, Sym, X, S, V, C, Bc, U, T, rho_c, st)
+               : launch_precode_vq<F16, UMAX, 1>(H, Sym, X, S, V, C, Bc, U, T, rho_c, st);
 }
 
 }  // namespace cdm

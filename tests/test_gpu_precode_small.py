@@ -106,3 +106,14 @@ def test_precode_batch_power_and_zero_forcing(dev, orc):
     for c in range(C):
         got = np.einsum("sub,svb->svu", Ht[:, :, c, :].conj(), z[:, :, c, :])
         assert relerr(got, Xs) <= 1e-4
+
+
+def test_precode_batch_fp16_two_vectors_per_quad(dev, orc):
+    """A batch large enough for the two-vectors-per-quad launch (1100 subcarriers, C = 8,
+    FP16, 15 vectors), checked on a sample of subcarriers."""
+    C, Bc, U, S, V, T = 8, 32, 8, 1100, 15, 3
+    d = inputs.paper_shaped(C, Bc, U, S, V, snr_db=10.0, seed=78)
+    x = run(dev, d["Ht"], d["X"], C, Bc, U, T, 1.0, half=True)
+    pick = np.linspace(0, S - 1, 12).astype(int)
+    ref = oracle(orc, d["Ht"][pick], d["X"][pick], C, T, 1.0, half=True)
+    assert relerr(x[pick], ref) <= 3e-2

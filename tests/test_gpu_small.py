@@ -107,3 +107,16 @@ def test_detect_batch_fusion_weights(dev, orc):
     one = run(dev, dict(Ht=d["Ht"][:, :, :Bc].copy(), Y=d["Y"][:, :, :Bc].copy(), N0=d["N0"]), 1, Bc, U, T,
               half=False)
     assert relerr(x, one) <= 1e-6
+
+
+def test_detect_batch_fp16_two_vectors_per_quad(dev, orc):
+    """A batch large enough for the two-vectors-per-quad launch (1100 subcarriers, C = 8,
+    FP16, 15 vectors: the last pair of every task carries a vector past V), checked on a
+    sample of subcarriers."""
+    C, Bc, U, S, V, T = 8, 32, 8, 1100, 15, 3
+    d = inputs.paper_shaped(C, Bc, U, S, V, snr_db=10.0, seed=77)
+    x = run(dev, d, C, Bc, U, T, half=True)
+    pick = np.linspace(0, S - 1, 12).astype(int)
+    sub = dict(Ht=d["Ht"][pick], Y=d["Y"][pick], N0=d["N0"])
+    ref = oracle(orc, sub, C, T, half=True)
+    assert relerr(x[pick], ref) <= 3e-2
