@@ -52,23 +52,29 @@ struct SrcBF16 {                               // planar BF16 copy
         return make_float2(__uint_as_float(v.re << 16), __uint_as_float(v.im << 16));
     }
 };
-__device__ __forceinline__ float e4m3_to_float(uint32_t c) {
-    const uint32_t e = (c >> 3) & 15u, m = c & 7u;
-    const float v = e ? ldexpf((float)(8u + m), (int)e - 10) : ldexpf((float)m, -9);
-    return (c & 0x80u) ? -v : v;
+// E4M3 value of code c (bias 7; exponent field 0: subnormal m * 2^-9), times 2^-60.
+// Placing the exponent and mantissa fields in the FP32 fields (bits 23.. and 20..)
+// gives 2^(e-127) (1 + m/8) for e > 0 and m * 2^-129 (an FP32 subnormal, kept: the
+// kernels run with FP32 denormals preserved) for e = 0: both the E4M3 value times
+// 2^-120, exactly.  Times 2^60 is exact too.  The caller folds the other 2^60 into its
+// scale, so value * scale is rounded once, as from the exact value.
+__device__ __forceinline__ float e4m3_bits_scaled(uint32_t c) {
+    return __uint_as_float(((c & 0x7fu) << 20) | ((c & 0x80u) << 24)) * 0x1p60f;
 }
+constexpr float E4M3_UNSCALE = 0x1p60f;
 struct SrcFP8 {                                // planar FP8-e4m3 copy, one scale per 128 columns
     const uint8_t* re;
     const uint8_t* im;
     const float* scale;
+    // s * 2^60 is exact (a power-of-two factor) for every block scale below 2^68
     __device__ __forceinline__ float2 load(int64_t idx, int col) const {
-        const float s = scale[col >> 7];
-        return make_float2(e4m3_to_float(re[idx]) * s, e4m3_to_float(im[idx]) * s);
+        const float s = scale[col >> 7] * E4M3_UNSCALE;
+        return make_float2(e4m3_bits_scaled(re[idx]) * s, e4m3_bits_scaled(im[idx]) * s);
     }
     __device__ __forceinline__ float2 load_rc(int col, uint32_t row, int64_t ld) const {
         const int64_t c = (int64_t)col * ld;
-        const float s = scale[col >> 7];
-        return make_float2(e4m3_to_float(re[c + row]) * s, e4m3_to_float(im[c + row]) * s);
+        const float s = scale[col >> 7] * E4M3_UNSCALE;
+        return make_float2(e4m3_bits_scaled(re[c + row]) * s, e4m3_bits_scaled(im[c + row]) * s);
     }
     struct Raw {
         uint32_t re, im;
@@ -81,8 +87,8 @@ struct SrcFP8 {                                // planar FP8-e4m3 copy, one scal
         return v;
     }
     __device__ __forceinline__ float2 decode(const Raw& v, int col) const {
-        const float s = scale[col >> 7];
-        return make_float2(e4m3_to_float(v.re) * s, e4m3_to_float(v.im) * s);
+        const float s = scale[col >> 7] * E4M3_UNSCALE;
+        return make_float2(e4m3_bits_scaled(v.re) * s, e4m3_bits_scaled(v.im) * s);
     }
 };
 constexpr int PANEL_NWV = PANEL_NT / 64;
