@@ -433,6 +433,9 @@ __global__ __launch_bounds__(256) void k_gram_partial(Src src, int64_t ld, int B
         for (int j = 0; j < 4; ++j) acc[i][j] = czero<T>();
     const int colA0 = K * kp + bi * 64;
     const int colB0 = (CROSS ? (K + npanels - 1) % npanels : K) * kp + bj * 64;
+    // a diagonal sub-block multiplies a tile by itself: load it once
+    const bool same = colA0 == colB0;
+    V(*Bp)[64 + 1] = same ? As : Bs;
     for (int rb = r_lo; rb < r_hi; rb += 32) {
         // fill: thread -> (row i = tid & 31, column group tid >> 5, + 8 per step)
         const int i = tid & 31;
@@ -442,7 +445,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(Src src, int64_t ld, int B
             const int c = (tid >> 5) + 8 * k;
             const int ca = colA0 + c, cb = colB0 + c;
             As[i][c] = (row < r_hi && ca < U) ? src.load((int64_t)ca * ld + row, ca) : czero<T>();
-            Bs[i][c] = (row < r_hi && cb < U) ? src.load((int64_t)cb * ld + row, cb) : czero<T>();
+            if (!same) Bs[i][c] = (row < r_hi && cb < U) ? src.load((int64_t)cb * ld + row, cb) : czero<T>();
         }
         __syncthreads();
 #pragma unroll 4
@@ -451,7 +454,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(Src src, int64_t ld, int B
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 av[k] = As[ii][ty * 4 + k];
-                bv[k] = Bs[ii][tx * 4 + k];
+                bv[k] = Bp[ii][tx * 4 + k];
             }
 #pragma unroll
             for (int p = 0; p < 4; ++p)
