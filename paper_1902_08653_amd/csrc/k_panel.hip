@@ -609,6 +609,29 @@ __global__ void k_sum_splits(const V* __restrict__ part, int nsplit, int64_t n, 
     X[blk * kk + (int64_t)v * kp + j] = s;
 }
 
+// -Y_K = -M_K X_K for every panel, in place of X_K (complex128, 64-column panels: the
+// look-ahead schedule then forms delta_K = M_K q_K + (-Y_K) delta_{K-1} in one product
+// instead of correcting b first).  One workgroup per panel; M_K (packed lower, column
+// by column) and X_K (column-major) are read into LDS before any result is written.
+template <int KP>
+__global__ __launch_bounds__(256) void k_fold_mx(const double2* __restrict__ M, double2* __restrict__ X) {
+    constexpr int NE = KP * (KP + 1) / 2;
+    __shared__ double2 Ms[NE];
+    __shared__ double2 Xs[KP * KP];
+    const int64_t K = blockIdx.x;
+    const double2* Mk = M + K * NE;
+    double2* Xk = X + K * KP * KP;
+    for (int i = threadIdx.x; i < NE; i += 256) Ms[i] = Mk[i];
+    for (int i = threadIdx.x; i < KP * KP; i += 256) Xs[i] = Xk[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < KP * KP; i += 256) {
+        const int v = i / KP, j = i % KP;   // element (j, v), stored at v * KP + j
+        double2 acc = make_double2(0.0, 0.0);
+        for (int u = 0; u <= j; ++u) cfma(acc, Ms[u * KP - (u * (u - 1)) / 2 + (j - u)], Xs[v * KP + u]);
+        Xk[i] = make_double2(-acc.x, -acc.y);
+    }
+}
+
 template <typename T> static hipError_t launch_gram_cross_t(const GramLaunch& L, void* X, hipStream_t st) {
     const int nb = L.kp / 64;
     const int nsub = nb * nb;
@@ -633,7 +656,15 @@ template <typename T> static hipError_t launch_gram_cross_t(const GramLaunch& L,
     const int64_t n = (int64_t)L.npanels * L.kp * L.kp;
     hipLaunchKernelGGL(k_sum_splits<cv<T>>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        (const cv<T>*)L.gpart, L.nsplit, n, L.kp, (cv<T>*)X);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if constexpr (sizeof(T) == 8) {
+        if (L.kp == 64) {   // the configuration whose look-ahead forms b locally
+            hipLaunchKernelGGL(k_fold_mx<64>, dim3(L.npanels), dim3(256), 0, st, (const double2*)L.M, (double2*)X);
+            e = hipGetLastError();
+        }
+    }
+    return e;
 }
 
 hipError_t launch_gram_cross(const GramLaunch& L, void* X, hipStream_t st) {

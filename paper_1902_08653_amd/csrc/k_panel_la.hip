@@ -10,12 +10,14 @@
 // reduced b.  In exact arithmetic every delta equals the sequential sweep's.
 // Where X_K fits the LDS next to M (complex128, 64-column panels) the reducers publish
 // q_K = H_K^H r - lambda x_K as soon as the partials are in, and every workgroup forms
-// b_K = q_K - X_K delta_{K-1} itself from X_K staged in LDS: the chain from one panel's
-// delta to the next panel's then stays inside the workgroup, and the cross-workgroup
-// exchange runs a panel ahead of it.  Otherwise (64 KB of X_K would not fit) the
-// reducers apply the correction and publish b_K.
+// delta_K = M_K (q_K - X_K delta_{K-1}) = M_K q_K - Y_K delta_{K-1} itself, in one
+// product, from -Y_K = -M_K X_K (formed once per solve in place of X_K) staged in LDS:
+// the chain from one panel's delta to the next panel's then stays inside the
+// workgroup, and the cross-workgroup exchange runs a panel ahead of it.  Otherwise
+// (64 KB of X_K would not fit) the reducers apply the correction and publish b_K.
 //
-// Workgroup: 8 tile waves and one control wave, decoupled.
+// Workgroup: 8 tile waves, one control wave and (complex128) one X-staging wave,
+// decoupled.
 //  * Tile waves own the rows (lane = row) and NC panel columns each.  They keep
 //    three panels in registers (K for the update, K+1 already reduced, K+2 for the
 //    next look-ahead partials) and stream a fourth behind them; they touch global
@@ -25,7 +27,11 @@
 //    waves' partials, gathers b_K into LDS (with M_K, staged by LDS-direct loads),
 //    keeps the stop statistics, and in the reducer workgroups (w < KP; reducer w
 //    owns panel column j = w) sums the P partials of its column and publishes b.
-//  * The two sides meet only through LDS words (sequence counters), never at a
+//  * The X-staging wave (complex128) moves -Y_K of the next step into LDS with
+//    LDS-direct loads as soon as the tile waves have read the current one.  A wave
+//    that issues such loads waits for them to land before its next LDS access, so
+//    they are kept out of the control wave's loop.
+//  * The waves meet only through LDS words (sequence counters), never at a
 //    workgroup barrier, so a reducer's wait for partials does not hold back its own
 //    tile waves.  The tile waves synchronise among themselves with an LDS arrival
 //    counter.  Memory operations complete in issue order per wave, so keeping flag
@@ -35,7 +41,10 @@
 namespace cdm {
 
 constexpr int LA_NWT = 8;                 // tile waves
-constexpr int LA_NT = 64 * (LA_NWT + 1);  // + one control wave
+// b formed locally (X_K, 64 KB at most, fits the LDS next to M): complex128 panels
+template <typename T, int KP> constexpr bool la_localb() { return (int)sizeof(cv<T>) * KP * KP <= 64 * 1024; }
+// tile waves + one control wave (+ one X-staging wave where b is formed locally)
+template <typename T, int KP> constexpr int la_threads() { return 64 * (LA_NWT + (la_localb<T, KP>() ? 2 : 1)); }
 
 // Tagged words: a payload and a tag (panel sequence number + 1) in one 64-bit word
 // (complex64: 32 + 32 bits; complex128: 48 + 16), stored and loaded single-copy
@@ -117,19 +126,20 @@ __device__ __forceinline__ void lds_add(int* p, int v) {
 }
 
 template <typename T, int KP, int RPL, class Src>
-__global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
+__global__ __launch_bounds__((la_threads<T, KP>()), 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
     using V = cv<T>;
     constexpr int NC = KP / LA_NWT;             // panel columns per tile wave
     static_assert(NC >= 1 && NC <= 64 && (NC & (NC - 1)) == 0, "bad panel split");
     constexpr int NE = KP * (KP + 1) / 2;       // packed lower triangle of M_K
     constexpr int NS = 64 * LA_NWT / KP;        // matvec slices per row (tile threads)
     constexpr int KL = (KP + 63) / 64;          // panel entries per control lane
-    constexpr bool LOCALB = (int)sizeof(V) * KP * KP <= 64 * 1024;   // X_K in LDS, b formed locally
+    constexpr bool LOCALB = la_localb<T, KP>();   // X_K in LDS, b formed locally
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
     const bool ctl = wid == LA_NWT;
+    const bool xstg = LOCALB && wid == LA_NWT + 1;
     const int w = blockIdx.x;
     const int P = gridDim.x;                    // the planner keeps KP <= P <= 256
     const bool reducer = w < KP;
@@ -148,21 +158,24 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
     __shared__ V xsh[2][KP];                    // x of the step's panel before its update
     __shared__ V dsh[2][KP];                    // delta of the step's panel
     __shared__ V dpart[NS][KP];
-    // X_K (transposed: column v at v * KP) for the local correction of b
+    // -Y_K = -M_K X_K (column v at v * KP) for the local correction
     __shared__ __attribute__((aligned(16))) V Xs[LOCALB ? KP * KP : 1];
     __shared__ V axs[LA_NWT][RPL][64];
     // LDS words: b_ready = (last step whose b, x and M are in LDS) + 1; d_ready = (last
     // step whose delta is in dsh) + 1; p_done[k] = partial panels written by tile wave
     // k (per wave: a shared count could not tell a fast wave's second panel from a
     // slow wave's first); stop_w: 1 stopped (converged or T_max), 2 abandoned; t_bar:
-    // tile-wave arrival counter
-    __shared__ int b_ready, d_ready, stop_w, t_bar;
+    // tile-wave arrival counter; xs_ready = (last step whose -Y_K is in Xs) + 1; x_free =
+    // (last step whose product has read Xs) + 1
+    __shared__ int b_ready, d_ready, stop_w, t_bar, xs_ready, x_free;
     __shared__ int p_done[LA_NWT];
     if (tid == 0) {
         b_ready = 0;
         d_ready = 0;
         stop_w = 0;
         t_bar = 0;
+        xs_ready = 1;   // step 0 needs no X
+        x_free = 1;     // nor reads it
     }
     if (tid < LA_NWT) p_done[tid] = 0;
     __syncthreads();   // the only workgroup barrier
@@ -170,6 +183,36 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
     uint32_t* abort_flag = a.ctr + 2;
     const int row0 = w * 64 * RPL;
     const uint64_t tmo = a.timeout_ticks;
+
+    if (xstg) {
+        // ================================== X staging wave ==================================
+        // -Y_K of step j into LDS once every tile wave has read that of step j - 1; its
+        // own wave, so that waiting for these LDS-direct loads to land holds up no other
+        // work
+        if (!LOCALB || a.T_max < 1) return;
+        for (int j = 1;; ++j) {
+            const uint64_t t0 = wall_clock64();
+            bool go = true;
+            while (__builtin_amdgcn_readfirstlane(lds_get(&x_free)) < j) {
+                if (__builtin_amdgcn_readfirstlane(lds_get(&stop_w)) != 0 || wall_clock64() - t0 > 2 * tmo) {
+                    go = false;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (!go) break;
+            const char* src = reinterpret_cast<const char*>(a.X + (int64_t)(j % np) * KP * KP) + lane * 16;
+            char* dst = reinterpret_cast<char*>(Xs);
+#pragma unroll 4
+            for (int off = 0; off < KP * KP * (int)sizeof(V); off += 1024)
+                __builtin_amdgcn_global_load_lds(src + off, (__attribute__((address_space(3))) void*)(dst + off), 16, 0,
+                                                 0);
+            wave_drain_vmem();
+            if (lane == 0) lds_set(&xs_ready, j + 1);
+        }
+        wave_drain_vmem();
+        return;
+    }
 
     if (!ctl) {
         // ===================================== tile waves =====================================
@@ -245,7 +288,9 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
         auto wait_b = [&](int q) -> bool {
             const uint64_t t0 = wall_clock64();
             for (;;) {
-                if (__builtin_amdgcn_readfirstlane(lds_get(&b_ready)) > q) return true;
+                if (__builtin_amdgcn_readfirstlane(lds_get(&b_ready)) > q &&
+                    (!LOCALB || __builtin_amdgcn_readfirstlane(lds_get(&xs_ready)) > q))
+                    return true;
                 if (__builtin_amdgcn_readfirstlane(lds_get(&stop_w)) != 0) return false;
                 if (wall_clock64() - t0 > 2 * tmo) return false;
                 __builtin_amdgcn_s_sleep(1);
@@ -270,38 +315,24 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
 #define CDM_LA_TSTEP(cur, nn)                                                                         \
     {                                                                                                 \
         if (!wait_b(q)) goto tdone;                                                                   \
-        if constexpr (LOCALB) {                                                                       \
-            if (q > 0) { /* b = q_K - X_K delta_{K-1} (the first panel of the solve has no correction) */ \
-                constexpr int SX = KP / NS;                                                           \
-                const V* dp = dsh[(q - 1) & 1];                                                       \
-                const int j = tid % KP, v0 = (tid / KP) * SX;                                         \
-                V c0 = czero<T>(), c1 = czero<T>();                                                   \
-                for (int v = v0; v < v0 + SX; v += 2) {                                               \
-                    cfma(c0, Xs[v * KP + j], dp[v]);                                                  \
-                    cfma(c1, Xs[(v + 1) * KP + j], dp[v + 1]);                                        \
-                }                                                                                     \
-                dpart[tid / KP][j] = cmake<T>(c0.x + c1.x, c0.y + c1.y);                              \
-                tbar();                                                                               \
-                if (bad) goto tdone;                                                                  \
-                if (tid < KP) {                                                                       \
-                    V s_ = dpart[0][tid];                                                             \
-                    for (int k = 1; k < NS; ++k) {                                                    \
-                        s_.x += dpart[k][tid].x;                                                      \
-                        s_.y += dpart[k][tid].y;                                                      \
-                    }                                                                                 \
-                    bsh[q & 1][tid].x -= s_.x;                                                        \
-                    bsh[q & 1][tid].y -= s_.y;                                                        \
-                }                                                                                     \
-                tbar();                                                                               \
-                if (bad) goto tdone;                                                                  \
-            }                                                                                         \
-        }                                                                                             \
-        {   /* delta = M_K b; column v of the packed M holds rows v..KP-1 at offset v*KP - v(v-1)/2 */ \
+        {   /* delta = M_K b; column v of the packed M holds rows v..KP-1 at offset v*KP - v(v-1)/2.  \
+               LOCALB: b = q_K - X_K delta_{K-1}, so delta = M_K q_K + (-Y_K) delta_{K-1}, Y_K = M_K X_K\
+               (-Y_K in Xs); the first panel of the solve has no correction */                        \
             constexpr int SV = KP / NS;                                                               \
             const V* Mq = Ms[q & 1];                                                                  \
             const V* bq = bsh[q & 1];                                                                 \
             const int j = tid % KP, sl = tid / KP, v0 = sl * SV, v1 = min(v0 + SV - 1, j);            \
             V d0 = czero<T>(), d1 = czero<T>();                                                       \
+            if constexpr (LOCALB) {                                                                   \
+                if (q > 0) { /* Xs holds -Y_K */                                                      \
+                    __builtin_amdgcn_sched_barrier(0);                                                \
+                    const V* dp = dsh[(q - 1) & 1];                                                   \
+                    for (int u = v0; u < v0 + SV; u += 2) {                                           \
+                        cfma(d0, Xs[u * KP + j], dp[u]);                                              \
+                        cfma(d1, Xs[(u + 1) * KP + j], dp[u + 1]);                                    \
+                    }                                                                                 \
+                }                                                                                     \
+            }                                                                                         \
             int off = v0 * KP - (v0 * (v0 - 1)) / 2 + (j - v0);                                       \
             int v = v0;                                                                               \
             for (; v + 1 <= v1; v += 2) {                                                             \
@@ -315,6 +346,9 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
         }                                                                                             \
         tbar();                                                                                       \
         if (bad) goto tdone;                                                                          \
+        if constexpr (LOCALB) {                                                                       \
+            if (tid == 0) lds_set(&x_free, q + 1); /* every wave is done reading Xs */                \
+        }                                                                                             \
         if (tid < KP) {                                                                               \
             V s_ = dpart[0][tid];                                                                     \
             for (int k = 1; k < NS; ++k) {                                                            \
@@ -493,8 +527,30 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
         }
         return true;
     };
-    // reducer: publish b_j = g_j - lambda x_j (+ bias) of panel K (sequence s)
-    auto publish_b = [&](int K, int s, V g) {
+    auto load_xb = [&](int K, V& xo, V& bb) {
+        const int u = K * KP + w;
+        xo = czero<T>();
+        bb = czero<T>();
+        if (lane == 0 && u < U) {
+            xo = a.x[u];
+            if (a.bias) bb = a.bias[u];
+        }
+    };
+    auto publish_b = [&](int s, V g, V xo, V bb) {
+        if (lane == 0) {
+            g.x += bb.x;
+            g.y += bb.y;
+            V b;
+            b.x = g.x - lambda * xo.x;
+            b.y = g.y - lambda * xo.y;
+            uint64_t* q0 = gb64 + (((int64_t)(s & 1) * KP + w) * 2) * NW;
+            TG::put(q0, b, (uint32_t)s + 1);
+            TG::put(q0 + NW, xo, (uint32_t)s + 1);
+        }
+    };
+    // the same, loading x_j and bias_j of panel K itself (where they cannot be loaded
+    // ahead: the reducer-side correction)
+    auto publish_b_at = [&](int K, int s, V g) {
         if (lane == 0) {
             const int u = K * KP + w;
             const V xo = (u < U) ? a.x[u] : czero<T>();
@@ -521,16 +577,6 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
             __builtin_amdgcn_global_load_lds(src + off, (__attribute__((address_space(3))) void*)(dst + off), 16, 0, 0);
     };
 
-    auto stage_X = [&](int K) {
-        if constexpr (LOCALB) {
-            const char* src = reinterpret_cast<const char*>(a.X + (int64_t)K * KP * KP) + lane * 16;
-            char* dst = reinterpret_cast<char*>(Xs);
-#pragma unroll 4
-            for (int off = 0; off < KP * KP * (int)sizeof(V); off += 1024)
-                __builtin_amdgcn_global_load_lds(src + off, (__attribute__((address_space(3))) void*)(dst + off), 16, 0,
-                                                 0);
-        }
-    };
     // LOCALB: the reducers publish q of the next panel before this step's delta unless the
     // next panel is this one (a single panel), whose x this step still changes
     const bool early = LOCALB && np > 1;
@@ -545,11 +591,13 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
         if (ok && reducer) {
             V g0;
             ok = gather_partials(0, g0);
-            if (ok) publish_b(0, 0, g0);   // no correction for the first panel
+            if (ok) publish_b_at(0, 0, g0);   // no correction for the first panel
         }
         int K = 0, t = 1;
         for (int q = 0; ok; ++q) {
             const int K1 = (K + 1 < np) ? K + 1 : 0;
+            V xo1 = czero<T>(), bb1 = czero<T>();
+            if (LOCALB && reducer && np > 1) load_xb(K1, xo1, bb1);
             // b, x and M of this step's panel into LDS buffer q & 1 (free: the tile waves
             // finished step q - 2, whose delta this wave has already seen)
             stage_M(K, q & 1);
@@ -563,7 +611,7 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
             }
             ok = gather_b(q);
             if (!ok) break;
-            wave_drain_vmem();   // the LDS-direct loads of M_K (and X_K) have landed
+            wave_drain_vmem();   // the LDS-direct loads of M_K have landed
             if (lane == 0) lds_set(&b_ready, q + 1);
             // LOCALB reducer: q of panel K+1 from its look-ahead partials (published one
             // step ago), while this workgroup's tile waves work on panel K
@@ -571,7 +619,7 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
                 V g;
                 ok = gather_partials(q + 1, g);
                 if (!ok) break;
-                publish_b(K1, q + 1, g);
+                publish_b(q + 1, g, xo1, bb1);
             }
             // statistics and x of panel K once the tile waves have delta
             ok = wait_delta(q);
@@ -612,6 +660,7 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
                     break;
                 }
             }
+            if (LOCALB && reducer && np == 1) load_xb(K1, xo1, bb1);
             // reducer: b of panel K+1 = (sum of its look-ahead partials) - X_{K+1} delta_K
             // - lambda x (the partials were published one step ago); with LOCALB and a
             // single panel, q of the next sweep's panel once this step's x is written
@@ -627,15 +676,13 @@ __global__ __launch_bounds__(LA_NT, 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
                 }
                 c.x = wave_allsum(c.x);
                 c.y = wave_allsum(c.y);
-                publish_b(K1, q + 1, cmake<T>(g.x - c.x, g.y - c.y));
+                publish_b_at(K1, q + 1, cmake<T>(g.x - c.x, g.y - c.y));
             } else if (LOCALB && !early && reducer) {
                 V g;
                 ok = gather_partials(q + 1, g);
                 if (!ok) break;
-                publish_b(K1, q + 1, g);
+                publish_b(q + 1, g, xo1, bb1);
             }
-            // X of panel K+1 into LDS: this step's delta, its last use of X_K, is done
-            stage_X(K1);
             // the tile waves' partials of panel K+2 (sequence q + 2)
             ok = wait_parts(q + 3);
             if (!ok) break;
@@ -682,7 +729,7 @@ static hipError_t launch_la_src(const PanelLaunch& L, const Src& src, hipStream_
     a.npanels = L.npanels;
     a.T_max = L.T_max;
     void* args[] = {&a};
-    return hipLaunchCooperativeKernel((const void*)k_cd_panel_la<T, KP, RPL, Src>, dim3(L.P), dim3(LA_NT), args, 0,
+    return hipLaunchCooperativeKernel((const void*)k_cd_panel_la<T, KP, RPL, Src>, dim3(L.P), dim3(la_threads<T, KP>()), args, 0,
                                       st);
 }
 
@@ -704,7 +751,7 @@ static int la_coresident_t() {
     int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cd_panel_la<T, KP, RPL, SrcC<T>>, LA_NT, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cd_panel_la<T, KP, RPL, SrcC<T>>, la_threads<T, KP>(), 0) !=
         hipSuccess)
         return 0;
     return per * ncu;

@@ -157,7 +157,9 @@ struct GramLaunch {
 };
 hipError_t launch_gram(const GramLaunch& L, hipStream_t st);
 // Cross blocks X_K = H_K^H H_{K-1 mod npanels} (full kp x kp, transposed) into X,
-// using gpart as split scratch (call after launch_gram: its contents are consumed).
+// using gpart as split scratch (call after launch_gram: its contents are consumed,
+// and M is read).  For complex128 with 64-column panels X receives -M_K X_K
+// instead, the form the look-ahead schedule uses there.
 hipError_t launch_gram_cross(const GramLaunch& L, void* X, hipStream_t st);
 
 // (D + L)^-1 from summed Gram blocks already in gpart (row-major, lower part).
