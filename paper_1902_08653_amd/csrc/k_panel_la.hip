@@ -125,6 +125,42 @@ __device__ __forceinline__ void lds_add(int* p, int v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// ---- row sums by DPP ---------------------------------------------------------------
+// v of lane i + n within the lane's row of 16 (0 past the row's end): DPP row_shl,
+// a register move with no LDS traffic
+template <int N> __device__ __forceinline__ double row_shl(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x100 | N, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x100 | N, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+template <int N> __device__ __forceinline__ float row_shl(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x100 | N, 0xF, 0xF, true));
+}
+// Transpose-reduce of 4 values per lane (as wave_transpose_sum<T, 4>): the two exchange
+// levels across half- and quarter-waves, then the sum over each row of 16 lanes by DPP
+// shifts into the row's first lane (lanes 0, 16, 32, 48 hold the four sums)
+template <typename T> __device__ __forceinline__ void transpose_sum4_rows(T (&v)[4], int lane) {
+    int mask = 32;
+#pragma unroll
+    for (int lvl = 0; lvl < 2; ++lvl) {
+        const int half = 2 >> lvl;
+        const bool upper = (lane & mask) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            T lo = v[i], hi = v[i + half];
+            asm("" : "+v"(lo), "+v"(hi));
+            const T send = upper ? lo : hi;
+            const T keep = upper ? hi : lo;
+            v[i] = keep + __shfl_xor(send, mask, 64);
+        }
+        mask >>= 1;
+    }
+    v[0] += row_shl<1>(v[0]);
+    v[0] += row_shl<2>(v[0]);
+    v[0] += row_shl<4>(v[0]);
+    v[0] += row_shl<8>(v[0]);
+}
+
 template <typename T, int KP, int RPL, class Src>
 __global__ __launch_bounds__((la_threads<T, KP>()), 1) void k_cd_panel_la(PanelArgs<T, Src> a) {
     using V = cv<T>;
@@ -262,8 +298,14 @@ __global__ __launch_bounds__((la_threads<T, KP>()), 1) void k_cd_panel_la(PanelA
                         pi[c] += h.x * r[q].y - h.y * r[q].x;
                     }
                 }
-                wave_transpose_sum<T, NH>(pr, lane);
-                wave_transpose_sum<T, NH>(pi, lane);
+                if constexpr (NH == 4) {   // the row reduction by DPP fits exactly
+                    transpose_sum4_rows<T>(pr, lane);
+                    __builtin_amdgcn_sched_barrier(0);
+                    transpose_sum4_rows<T>(pi, lane);
+                } else {
+                    wave_transpose_sum<T, NH>(pr, lane);
+                    wave_transpose_sum<T, NH>(pi, lane);
+                }
                 if ((lane & ((1 << HSHIFT) - 1)) == 0)
                     psh[s & 1][wu + LA_NWT * (h0 + (lane >> HSHIFT))] = cmake<T>(pr[0], pi[0]);
             }
