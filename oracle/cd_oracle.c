@@ -140,8 +140,14 @@ int cdo_local_cd(int Bc, int U, const cplx* H, long ldh, const cplx* y, double l
 /* The fusion weight is lambda_c = sigma_c^-2 / sum_c' sigma_c'^-2 (Sec. III); */
 /* the paper leaves sigma_c^2 undefined.  Reading used here: the diagonal      */
 /* approximation of the local L-MMSE error, sigma_c^2 = (N0/U) sum_u m_{u,c}.  */
-/* lam_c (C weights) overrides it when not NULL.  Bc == NULL means C equal     */
-/* blocks (B % C == 0).                                                        */
+/* The factor N0/U is common to every cluster and cancels from the ratio, so   */
+/* the weights are formed as lambda_c = s_c^-1 / sum_c' s_c'^-1 with           */
+/* s_c = sum_u m_{u,c}: equal to the definition for N0 > 0, and defined at     */
+/* N0 = 0 as its limit.  A cluster with s_c = 0 (possible only at N0 = 0 when  */
+/* every column of it is zero, so every coordinate is inactive) carries no     */
+/* estimate and gets weight 0; if every cluster does, x_hat = 0.               */
+/* lam_c (C weights) overrides the weights, used as given, when not NULL.      */
+/* Bc == NULL means C equal blocks (B % C == 0).                               */
 /* Per-cluster outputs: x_local [C*U] (may be NULL), sweeps/rel_step/flags [C].*/
 /* ------------------------------------------------------------------------- */
 int cdo_uplink_cd(int B, int U, int C, const int* Bc, const cplx* H, long ldh,
@@ -162,12 +168,12 @@ int cdo_uplink_cd(int B, int U, int C, const int* Bc, const cplx* H, long ldh,
         sweeps[c] = cdo_local_cd(bc, U, Hc, ldh, y + row0, lambda, x0, T_max, tol,
                                  xl + (long)c * U, &rel_step[c], &flags[c],
                                  NULL, NULL, NULL, NULL);
-        /* sigma_c^2 reading (see header comment). */
+        /* sigma_c^2 reading (see header comment): s_c = sum_u m_{u,c}, where an  */
+        /* inactive coordinate (||h_u||^2 + lambda == 0) has m_u = 0.             */
         cdo_column_scalars(bc, U, Hc, ldh, lambda, e, m, n);
         double sm = 0.0;
-        for (int u = 0; u < U; ++u) sm += m[u];
-        double sigma2 = (N0 / (double)U) * sm;
-        w[c] = 1.0 / sigma2;
+        for (int u = 0; u < U; ++u) sm += (e[u] + lambda > 0.0) ? m[u] : 0.0;
+        w[c] = (sm > 0.0) ? 1.0 / sm : 0.0;
         row0 += bc;
     }
     if (lam_c) {
@@ -175,7 +181,7 @@ int cdo_uplink_cd(int B, int U, int C, const int* Bc, const cplx* H, long ldh,
     } else {
         double tot = 0.0;
         for (int c = 0; c < C; ++c) tot += w[c];
-        for (int c = 0; c < C; ++c) w[c] = w[c] / tot;
+        for (int c = 0; c < C; ++c) w[c] = (tot > 0.0) ? w[c] / tot : 0.0;
     }
     for (int u = 0; u < U; ++u) {
         cplx s = 0.0;

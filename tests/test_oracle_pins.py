@@ -217,6 +217,88 @@ def test_fusion_single_cluster_is_centralised_and_weights_sum_to_one(orc):
         assert np.array_equal(four["x_local"][c], lc["x"])
 
 
+def _hand_fusion_case():
+    """Two uneven clusters (B_1 = 2, B_2 = 3 rows, U = 2 users) whose columns are
+    orthogonal with integer squared norms, so every quantity of Sec. III's fusion
+    can be worked by hand: e_{u,1} = (1, 4), e_{u,2} = (9, 1)."""
+    H = np.zeros((5, 2), complex)
+    H[0, 0], H[1, 1] = 1, 2            # cluster 1
+    H[2, 0], H[3, 1] = 3, 1j           # cluster 2 (row 4 is an idle antenna)
+    y = np.array([1, 1, 1, 1, 5], complex)
+    return H, y, [(1, 4), (9, 1)]
+
+
+def _sec3_weights(e_per_cluster, N0, Ex, U):
+    """lambda_c = sigma_c^-2 / sum_c' sigma_c'^-2 with sigma_c^2 = (N0/U) sum_u m_{u,c},
+    m_{u,c} = 1/(e_{u,c} + N0/Ex), in exact rational arithmetic."""
+    from fractions import Fraction as F
+    lam = F(N0) / F(Ex)
+    sig2 = [F(N0, 1) / U * sum(1 / (F(e) + lam) for e in es) for es in e_per_cluster]
+    inv = [1 / s2 for s2 in sig2]
+    return [v / sum(inv) for v in inv]
+
+
+def test_fusion_weights_worked_by_hand(orc):
+    """Sec. III fusion with reading A7, on the hand case: N0 = Ex = 1 gives
+    m_{u,1} = (1/2, 1/5), m_{u,2} = (1/10, 1/2), sigma_1^2 = 7/20, sigma_2^2 = 3/10,
+    so lambda_1 = 6/13 and lambda_2 = 7/13."""
+    from fractions import Fraction as F
+    H, y, es = _hand_fusion_case()
+    w = _sec3_weights(es, 1, 1, 2)
+    assert w == [F(6, 13), F(7, 13)]
+    # the pin discriminates: weights proportional to sigma^2 (inverted), or sigma^2 built
+    # from the energies e_u instead of m_u, or equal weights, all differ from it
+    assert [F(7, 13), F(6, 13)] != w and [F(2, 3), F(1, 3)] != w and [F(1, 2)] * 2 != w
+    out = orc.uplink_cd(H, y, N0=1.0, Ex=1.0, T_max=1, C_clusters=2, Bc=[2, 3])
+    assert np.allclose(out["weights"], [float(v) for v in w], rtol=0, atol=1e-15)
+    # orthogonal columns: one sweep gives each cluster's exact local L-MMSE estimate
+    # x_{u,c} = h_{u,c}^H y_c / (e_{u,c} + lambda)
+    x1 = np.array([1 / 2, 2 / 5])
+    x2 = np.array([3 / 10, -1j / 2])
+    assert np.allclose(out["x_local"], [x1, x2], rtol=0, atol=1e-15)
+    fused = float(w[0]) * x1 + float(w[1]) * x2
+    assert np.allclose(out["x"], fused, rtol=0, atol=1e-15)
+
+
+def test_fusion_weights_at_zero_noise_are_finite(orc):
+    """N0 = 0: the common factor N0/U cancels from lambda_c, so the weights are the
+    limit of the Sec. III rule: m = 1/e gives s_1 = 5/4, s_2 = 10/9 and
+    lambda = (8/17, 9/17).  Both clusters have B_c >= U (eq. (1) strictly convex)."""
+    from fractions import Fraction as F
+    H, y, es = _hand_fusion_case()
+    eps = 1e-30   # the rule at a vanishing N0 equals the N0 = 0 limit
+    w_lim = _sec3_weights(es, F(eps), 1, 2)
+    assert abs(float(w_lim[0]) - 8 / 17) < 1e-20
+    out = orc.uplink_cd(H, y, N0=0.0, Ex=1.0, T_max=1, C_clusters=2, Bc=[2, 3])
+    assert np.all(np.isfinite(out["weights"])) and np.all(np.isfinite(out["x"]))
+    assert np.allclose(out["weights"], [8 / 17, 9 / 17], rtol=0, atol=1e-15)
+
+
+def test_fusion_cluster_without_active_coordinate_gets_zero_weight(orc):
+    """At N0 = 0 a cluster whose columns are all zero has no active coordinate
+    (reading A9), sum_u m_u = 0, and carries weight 0; the other takes weight 1."""
+    H, y, _ = _hand_fusion_case()
+    H2 = H.copy()
+    H2[2:, :] = 0
+    out = orc.uplink_cd(H2, y, N0=0.0, Ex=1.0, T_max=1, C_clusters=2, Bc=[2, 3])
+    assert list(out["weights"]) == [1.0, 0.0]
+    assert np.allclose(out["x"], [1.0, 0.5], rtol=0, atol=1e-15)   # cluster 1 alone at lambda = 0
+
+
+def test_fusion_caller_weights_drop_a_cluster(orc):
+    """Caller weights are used as given: dropping cluster 2 of three and
+    renormalising the rest equals fusing clusters 1 and 3 alone."""
+    inst = inputs.dense_uplink(36, 6, 21)
+    three = orc.uplink_cd(inst.H, inst.y, N0=0.1, Ex=1.0, T_max=4, C_clusters=3, Bc=[10, 14, 12])
+    w = three["weights"].copy()
+    w[1] = 0.0
+    w /= w.sum()
+    dropped = orc.uplink_cd(inst.H, inst.y, N0=0.1, Ex=1.0, T_max=4, C_clusters=3, Bc=[10, 14, 12], lam_c=w)
+    keep = np.r_[0:10, 24:36]
+    two = orc.uplink_cd(inst.H[keep], inst.y[keep], N0=0.1, Ex=1.0, T_max=4, C_clusters=2, Bc=[10, 12])
+    assert np.allclose(dropped["x"], two["x"], rtol=1e-14, atol=0)
+
+
 # ----------------------------------------------------------------------------- downlink (Alg. 2)
 
 def zf_closed_form(H, s):
