@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define CDM_ABI_VERSION 1
+#define CDM_ABI_VERSION 2
 
 typedef enum cdm_status {
     CDM_OK = 0,
@@ -90,14 +90,18 @@ typedef struct cdm_desc {
     int32_t engine;      /* cdm_engine */
     int32_t B;           /* antennas = rows of H (sum of the cluster sizes), >= 1 */
     int32_t U;           /* users = columns of H, >= 1 */
-    int32_t C;           /* antenna clusters (Sec. II-A), >= 1, B % C == 0; cluster c owns
-                            rows [c*B/C, (c+1)*B/C) */
+    int32_t C;           /* antenna clusters (Sec. II-A), 1 <= C <= B; cluster c owns the
+                            c-th block of consecutive rows: B/C rows each (then B % C == 0),
+                            or Bc[c] rows if Bc is given */
     int32_t T_max;       /* sweep cap T_max of Algorithms 1 and 2, 1..100000 */
     double tol;          /* 0: run exactly T_max sweeps (the paper's mode); > 0: stop after
                             sweep t once sqrt(sum_u |delta_u|^2) <= tol * ||x^(t)||_2 */
     int64_t nnz;         /* CDM_CSR: number of stored entries of H (exactly rowptr[B]), else 0 */
     int32_t panel;       /* CDM_ENGINE_PANEL panel width (64 or 128); 0 = choose */
     int32_t flags;       /* CDM_F_* */
+    const int32_t* Bc;   /* host, optional: C cluster sizes B_c >= 1 summing to B (uneven
+                            clusters, Sec. II-A); NULL = C equal blocks.  Read by cdm_create
+                            only (the plan keeps a copy).  Batched plans: must be NULL. */
 } cdm_desc;
 
 /* Per-instance (per-cluster) result record written to device memory by a solve.
@@ -106,6 +110,11 @@ typedef struct cdm_desc {
 #define CDM_INFO_NONFINITE     2   /* the returned x holds NaN or Inf */
 #define CDM_INFO_NOT_CONVERGED 4   /* tol > 0 and T_max sweeps ran without meeting it */
 #define CDM_INFO_TIMEOUT       8   /* a cross-workgroup wait gave up (should never happen) */
+#define CDM_INFO_BAD_INPUT    16   /* CDM_CSR: rowptr/colidx malformed (rowptr[0] != 0, rowptr
+                                      decreasing, rowptr[B] != nnz, a column index outside
+                                      [0, U), or column indices not strictly increasing in a
+                                      row); no entry was read through them: the solve ran
+                                      Algorithm 1 on H = 0 (all columns empty) */
 typedef struct cdm_info {
     int32_t sweeps;      /* sweeps performed */
     int32_t flags;       /* CDM_INFO_* */
@@ -149,6 +158,13 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan);
  *  rho    downlink: total power constraint rho (each cluster scales to
  *         rho/sqrt(C), Sec. IV-B); rho <= 0 skips the scaling
  *  x0     device, optional warm start (U complex, uplink only), NULL = x^(0) = 0
+ *  lambda_c device, optional: C fusion weights (double) of Algorithm 1's output,
+ *         x_hat = sum_c lambda_c x_c, used as given (uplink with C > 1 only; a weight
+ *         of 0 drops cluster c, e.g. one whose data did not arrive).  NULL = the
+ *         weights of Sec. III, lambda_c = sigma_c^-2 / sum_c' sigma_c'^-2 with
+ *         sigma_c^2 = (N0/U) sum_u m_{u,c}; the common factor N0/U cancels, so they
+ *         are s_c^-1 / sum_c' s_c'^-1 (s_c = sum_u m_{u,c}), defined for N0 = 0 too;
+ *         a cluster without an active coordinate (s_c = 0) gets weight 0
  *  x      device output; uplink: the fused estimate x_hat (U complex);
  *         downlink: the stacked precoded vector [x_1; ...; x_C] (B complex)
  *  info   device cdm_info[C] (one record per cluster)
@@ -156,11 +172,12 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan);
  * Mixed precisions run the outer FP64 refinement loop: residual r = y - H x in
  * FP64, inner CD sweeps on the correction problem from the low-precision copy of
  * H, x += d, until ||d|| <= tol ||x|| (tol > 0 required) or T_max outer steps.
- * Errors: CDM_EINVAL (NULL pointer, lambda < 0), CDM_ESHAPE (ldh < B),
- * CDM_EINFEASIBLE, CDM_EHIP. */
+ * Errors: CDM_EINVAL (NULL pointer, lambda < 0, lambda_c given for a downlink or
+ * C = 1 plan), CDM_ESHAPE (ldh < B), CDM_EINFEASIBLE (lambda = 0 and some B_c < U),
+ * CDM_EHIP. */
 int32_t cdm_solve(cdm_plan* plan, const void* H, int64_t ldh, const int32_t* rowptr,
                   const int32_t* colidx, const void* rhs, double N0, double Ex, double rho,
-                  const void* x0, void* x, void* info, void* stream);
+                  const void* x0, const double* lambda_c, void* x, void* info, void* stream);
 
 /* Create a plan for a batch of independent uplink instances of uneven size
  * (Algorithm 1 with C = 1 per instance).  m, n: host int32[batch], rows (antennas)
@@ -205,8 +222,10 @@ int32_t cdm_solve_batched(cdm_plan* plan, const void* H, const void* y, double N
  * can be checked.  Transposes the CSR input (val, rowptr, colidx as in cdm_solve)
  * and copies the result to the caller's device buffers (any may be NULL):
  * colptr_out int32[U+1], rowidx_out int32[nnz], cval_out complex[nnz].  Within a
- * column, entries are ordered by increasing row (the form is unique).
- * Errors: CDM_EINVAL (not a CSR plan, NULL input), CDM_EHIP. */
+ * column, entries are ordered by increasing row (the form is unique).  Unlike the
+ * solve, this call synchronises `stream` to report malformed CSR arrays (the
+ * conditions of CDM_INFO_BAD_INPUT) as CDM_EINVAL; the outputs then hold the empty form.
+ * Errors: CDM_EINVAL (not a CSR plan, NULL input, malformed rowptr/colidx), CDM_EHIP. */
 int32_t cdm_csr_transpose(cdm_plan* plan, const void* val, const int32_t* rowptr, const int32_t* colidx,
                           int32_t* colptr_out, int32_t* rowidx_out, void* cval_out, void* stream);
 
@@ -242,9 +261,12 @@ int32_t cdm_residual(cdm_plan* plan, const void* H, int64_t ldh, const void* y, 
  *  X  device output, S*V vectors of U, vector (s, v) at element (s*V + v)*U
  * Elements are complex in `precision`: CDM_C64 (FP32 arithmetic) or CDM_C16 (FP16
  * storage; residual updates and dot products in packed FP16, scalar rule in FP32).
- * Limits: C in {1, 2, 4, 8}, 1 <= Bc <= 32, 1 <= U <= 16; N0 > 0 when C > 1.
+ * The factor N0/U is common to every cluster and cancels from lambda_c, so the weights
+ * are s_c^-1 / sum_c' s_c'^-1 with s_c = sum_u m_{u,c} (a cluster with s_c = 0 gets 0).
+ * Limits: C in {1, 2, 4, 8}, 1 <= Bc <= 32, 1 <= U <= 16; N0 = 0 needs Bc >= U.
  * Enqueues one kernel; allocates nothing.  Errors: CDM_EINVAL (NULL pointer, N0 < 0,
- * Ex <= 0, T_max < 1), CDM_EDTYPE, CDM_ESHAPE, CDM_EHIP. */
+ * Ex <= 0, T_max < 1), CDM_EDTYPE, CDM_ESHAPE, CDM_EINFEASIBLE (N0 = 0 with Bc < U),
+ * CDM_EHIP. */
 int32_t cdm_detect_batch(int32_t S, int32_t V, int32_t C, int32_t Bc, int32_t U, int32_t T_max,
                          int32_t precision, const void* H, const void* Y, double N0, double Ex,
                          void* X, void* stream);

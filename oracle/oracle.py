@@ -18,7 +18,25 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cd_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# CDO_SANITIZE=1: an AddressSanitizer + UndefinedBehaviorSanitizer build of the same
+# source (loaded into a process started with libasan preloaded; see
+# tests/test_sanitizers.py), kept apart from the plain build
+_SANITIZE = os.environ.get("CDO_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+# clang instruments every load, including those of `double complex` elements, which
+# gcc's AddressSanitizer leaves unchecked; the shared sanitizer runtime is preloaded
+SAN_CC = "/opt/rocm/llvm/bin/clang"
+_SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-shared-libsan",
+              "-fno-sanitize-recover=all"]
+
+
+def sanitizer_runtime():
+    """Path of the shared ASan (+UBSan) runtime that a process loading the sanitized
+    oracle must preload, or None where the compiler is absent."""
+    if not os.path.exists(SAN_CC):
+        return None
+    path = subprocess.check_output([SAN_CC, "-print-file-name=libclang_rt.asan-x86_64.so"], text=True).strip()
+    return path if os.path.isabs(path) and os.path.exists(path) else None
 
 FLAG_ZERO_COLUMN = 1
 FLAG_NONFINITE = 2
@@ -34,8 +52,9 @@ def build(force: bool = False) -> str:
     """
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fcx-limited-range", "-fPIC", "-shared",
-                               _SRC, "-o", tmp, "-lm"])
+        cc, opt = (SAN_CC, _SAN_FLAGS) if _SANITIZE else ("gcc", ["-O2"])
+        subprocess.check_call([cc] + opt + ["-std=c99", "-fcx-limited-range", "-fPIC", "-shared",
+                                            _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

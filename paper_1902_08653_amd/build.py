@@ -26,29 +26,39 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    """Compile every source to an object (in parallel) and link libcdm.so."""
-    objdir = os.path.join(PKG, "_build")
+# host pass only: AddressSanitizer and UndefinedBehaviorSanitizer for the library's CPU
+# code (descriptor validation, planning); the device code is built as always
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-sanitize-recover=all",
+                 "-Xarch_host", "-fno-omit-frame-pointer"]
+HOST_SANITIZE_LINK = ["-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-shared-libsan"]
+
+
+def build(verbose: bool = False, jobs: int = 8, host_sanitize: bool = False, out: str | None = None) -> str:
+    """Compile every source to an object (in parallel) and link libcdm.so (or `out`).
+    host_sanitize: the host-sanitizer build (objects kept apart from the plain ones)."""
+    objdir = os.path.join(PKG, "_build_san" if host_sanitize else "_build")
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+        cmd = [HIPCC] + FLAGS + (HOST_SANITIZE if host_sanitize else []) + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         if len(procs) >= jobs:
             _drain(procs)
     _drain(procs)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    lib = out or LIB
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + (HOST_SANITIZE_LINK if host_sanitize else []) + \
+        ["-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 def _drain(procs):

@@ -15,7 +15,9 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libcdm.so")
+# CDM_LIB names another build of the same library (the host-sanitizer build the CPU
+# tests load); the default is the in-tree libcdm.so
+LIB_PATH = os.environ.get("CDM_LIB") or os.path.join(_PKG, "libcdm.so")
 
 UPLINK_LMMSE, DOWNLINK_ZF = 0, 1
 C128, C64, MIXED_BF16, MIXED_FP8, MIXED_C64, C16 = 0, 1, 2, 3, 4, 5
@@ -44,7 +46,7 @@ class Desc(C.Structure):
     _fields_ = [("problem", C.c_int32), ("precision", C.c_int32), ("layout", C.c_int32),
                 ("engine", C.c_int32), ("B", C.c_int32), ("U", C.c_int32), ("C", C.c_int32),
                 ("T_max", C.c_int32), ("tol", C.c_double), ("nnz", C.c_int64),
-                ("panel", C.c_int32), ("flags", C.c_int32)]
+                ("panel", C.c_int32), ("flags", C.c_int32), ("Bc", C.POINTER(C.c_int32))]
 
 
 INFO_DTYPE = np.dtype([("sweeps", np.int32), ("flags", np.int32), ("rel_step", np.float64),
@@ -76,7 +78,7 @@ def lib():
         L.cdm_last_error.restype = C.c_char_p
         L.cdm_create.argtypes = [C.POINTER(Desc), C.POINTER(P)]
         L.cdm_create.restype = i32
-        L.cdm_solve.argtypes = [P, P, i64, P, P, P, f64, f64, f64, P, P, P, P]
+        L.cdm_solve.argtypes = [P, P, i64, P, P, P, f64, f64, f64, P, P, P, P, P]
         L.cdm_solve.restype = i32
         L.cdm_create_batched.argtypes = [C.POINTER(Desc), i32, P, P, C.POINTER(P)]
         L.cdm_create_batched.restype = i32
@@ -157,8 +159,11 @@ class Plan:
 
     def __init__(self, B, U, C_clusters=1, precision="c128", T_max=200, tol=0.0, engine="auto",
                  panel=0, residual=False, problem="uplink", layout="dense", nnz=0, timing=False,
-                 lookahead=True):
+                 lookahead=True, Bc=None):
         self.B, self.U, self.C = int(B), int(U), int(C_clusters)
+        bc = None
+        if Bc is not None:
+            bc = (C.c_int32 * self.C)(*[int(v) for v in Bc])
         self.precision = precision
         self.problem = problem
         d = Desc(problem=UPLINK_LMMSE if problem == "uplink" else DOWNLINK_ZF,
@@ -166,7 +171,8 @@ class Plan:
                  engine=_ENGINE[engine], B=self.B, U=self.U, C=self.C, T_max=int(T_max),
                  tol=float(tol), nnz=int(nnz), panel=int(panel),
                  flags=(F_RESIDUAL if residual else 0) | (F_TIMING if timing else 0)
-                 | (0 if lookahead else F_NO_LOOKAHEAD))
+                 | (0 if lookahead else F_NO_LOOKAHEAD),
+                 Bc=C.cast(bc, C.POINTER(C.c_int32)) if bc is not None else None)
         self.desc = d
         h = C.c_void_p()
         _check(lib().cdm_create(C.byref(d), C.byref(h)), "cdm_create")
@@ -178,9 +184,10 @@ class Plan:
         return buf.value.decode()
 
     def solve(self, Hc, rhs, N0=0.1, Ex=1.0, rho=0.0, x0=None, x=None, info=None, stream=None,
-              rowptr=None, colidx=None):
+              rowptr=None, colidx=None, lambda_c=None):
         """Enqueue one solve.  Returns (x, info) device tensors; call parse_info(info)
-        after synchronising to read the records."""
+        after synchronising to read the records.  lambda_c: optional device float64
+        tensor of C fusion weights (used as given)."""
         import torch
         dev = rhs.device
         ldh = Hc.shape[1] if Hc.dim() == 2 else 0
@@ -190,8 +197,8 @@ class Plan:
         if info is None:
             info = torch.empty(32 * self.C, dtype=torch.uint8, device=dev)
         st = lib().cdm_solve(self._h, _ptr(Hc), int(ldh), _ptr(rowptr), _ptr(colidx), _ptr(rhs),
-                             float(N0), float(Ex), float(rho), _ptr(x0), _ptr(x), _ptr(info),
-                             _stream(stream))
+                             float(N0), float(Ex), float(rho), _ptr(x0), _ptr(lambda_c), _ptr(x),
+                             _ptr(info), _stream(stream))
         _check(st, "cdm_solve")
         return x, info
 

@@ -181,30 +181,36 @@ hipError_t launch_resid(const ResidLaunch& L, hipStream_t st) {
 }
 
 // ---- fusion of the local estimates (uplink, C > 1) --------------------------
+// Sec. III: x_hat = sum_c lambda_c x_c with lambda_c = sigma_c^-2 / sum_c' sigma_c'^-2.
+// With sigma_c^2 = (N0/U) s_c, s_c = sum_u m_{u,c}, the common factor N0/U cancels, so
+// lambda_c = s_c^-1 / sum_c' s_c'^-1 (defined at N0 = 0 too).  A cluster with s_c = 0 (no
+// active coordinate) gets weight 0.  Caller weights (lam_c, device, C values) are used
+// as given.
 template <typename T>
-__global__ void k_fuse(const cv<T>* __restrict__ xloc, const double* __restrict__ msum, int C, int U, double N0,
-                       cv<T>* __restrict__ x) {
+__global__ void k_fuse(const cv<T>* __restrict__ xloc, const double* __restrict__ msum,
+                       const double* __restrict__ lam_c, int C, int U, cv<T>* __restrict__ x) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= U) return;
     double tot = 0.0;
-    for (int c = 0; c < C; ++c) tot += 1.0 / ((N0 / (double)U) * msum[c]);
+    if (!lam_c)
+        for (int c = 0; c < C; ++c) tot += msum[c] > 0.0 ? 1.0 / msum[c] : 0.0;
     double re = 0.0, im = 0.0;
     for (int c = 0; c < C; ++c) {
-        const double wc = (1.0 / ((N0 / (double)U) * msum[c])) / tot;
+        const double wc = lam_c ? lam_c[c] : (msum[c] > 0.0 && tot > 0.0 ? (1.0 / msum[c]) / tot : 0.0);
         const cv<T> v = xloc[(int64_t)c * U + u];
         re += wc * (double)v.x;
         im += wc * (double)v.y;
     }
     x[u] = cmake<T>((T)re, (T)im);
 }
-hipError_t launch_fuse(bool c128, const void* xloc, const double* msum, int C, int U, double N0, void* x,
+hipError_t launch_fuse(bool c128, const void* xloc, const double* msum, const double* lam_c, int C, int U, void* x,
                        hipStream_t st) {
     if (c128)
-        hipLaunchKernelGGL(k_fuse<double>, dim3((U + 255) / 256), dim3(256), 0, st, (const double2*)xloc, msum, C,
-                           U, N0, (double2*)x);
+        hipLaunchKernelGGL(k_fuse<double>, dim3((U + 255) / 256), dim3(256), 0, st, (const double2*)xloc, msum,
+                           lam_c, C, U, (double2*)x);
     else
-        hipLaunchKernelGGL(k_fuse<float>, dim3((U + 255) / 256), dim3(256), 0, st, (const float2*)xloc, msum, C, U,
-                           N0, (float2*)x);
+        hipLaunchKernelGGL(k_fuse<float>, dim3((U + 255) / 256), dim3(256), 0, st, (const float2*)xloc, msum,
+                           lam_c, C, U, (float2*)x);
     return hipGetLastError();
 }
 

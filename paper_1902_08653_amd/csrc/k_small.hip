@@ -5,7 +5,7 @@
 // For every (s, v) each cluster c runs T sweeps of Algorithm 1 on its rows
 // (H_{s,c}, y_{s,v,c}) from x = 0, and the C local estimates are fused (Sec. III):
 //   x_hat = sum_c lambda_c x_c,  lambda_c = sigma_c^-2 / sum_c' sigma_c'^-2,
-//   sigma_c^2 = (N0 / U) sum_u m_{u,c}.
+//   sigma_c^2 = (N0 / U) sum_u m_{u,c}  (N0/U cancels: lambda_c = s_c^-1 / sum s_c'^-1).
 // Mapping: a quad of lanes per (subcarrier, cluster, vector) task.  A cluster is at most
 // 32 x 16, so lane j of the quad keeps rows j, j + 4, ... (8 at most) of the residual and
 // the task's U coordinates in registers; the coordinate dot is a quad reduction (two
@@ -215,11 +215,17 @@ __global__ __launch_bounds__(SM_NT) void k_detect_small(const typename SmNum<F16
     // ---- fusion: one thread per (subcarrier, vector, user), clusters in order
     for (int e = tid; e < ns * V * U; e += SM_NT) {
         const int u = e % U, v = (e / U) % V, sub = e / (U * V);
+        // lambda_c = s_c^-1 / sum_c' s_c'^-1 with s_c = sum_u m_{u,c} (the factor N0/U of
+        // sigma_c^2 cancels); a cluster without an active coordinate (s_c = 0) gets 0
         float tot = 0.f;
-        for (int k = 0; k < C; ++k) tot += 1.f / wl[sub * C + k];
+        for (int k = 0; k < C; ++k) {
+            const float sk = wl[sub * C + k];
+            tot += sk > 0.f ? 1.f / sk : 0.f;
+        }
         float2 acc = make_float2(0.f, 0.f);
         for (int k = 0; k < C; ++k) {
-            const float w = (1.f / wl[sub * C + k]) / tot;
+            const float sk = wl[sub * C + k];
+            const float w = (sk > 0.f && tot > 0.f) ? (1.f / sk) / tot : 0.f;
             const float2 xc = xl[((sub * C + k) * V + v) * UMAX + u];
             acc.x += w * xc.x;
             acc.y += w * xc.y;
@@ -445,7 +451,7 @@ extern "C" int32_t cdm_detect_batch(int32_t S, int32_t V, int32_t C, int32_t Bc,
     if (precision != CDM_C64 && precision != CDM_C16) return CDM_EDTYPE;
     if (S < 1 || V < 1 || U < 1 || U > SM_UMAX || Bc < 1 || Bc > SM_BMAX) return CDM_ESHAPE;
     if (C != 1 && C != 2 && C != 4 && C != 8) return CDM_ESHAPE;
-    if (C > 1 && !(N0 > 0.0)) return CDM_EINVAL;   // the fusion weights need sigma_c^2 > 0
+    if (N0 == 0.0 && Bc < U) return CDM_EINFEASIBLE;   // lambda = 0: eq. (1) needs Bc >= U
     const bool f16 = precision == CDM_C16;
     // one subcarrier's staging must fit the workgroup's LDS
     if ((U <= 8 ? sm_lds_bytes<8>(1, C, V, f16) : sm_lds_bytes<16>(1, C, V, f16)) > SM_LDS) return CDM_ESHAPE;

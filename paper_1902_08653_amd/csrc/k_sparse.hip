@@ -19,7 +19,40 @@
 namespace cdm {
 
 // ---- CSR -> CSC --------------------------------------------------------------
-__global__ void k_csr_count(const int32_t* __restrict__ colidx, int64_t nnz, int32_t* __restrict__ cnt) {
+// Validation of the caller's CSR arrays before any indexed write: rowptr[0] == 0,
+// rowptr non-decreasing, rowptr[B] == nnz, and in every row column indices in [0, U)
+// and strictly increasing.  A violation sets CDM_INFO_BAD_INPUT in *status; the kernels
+// that index with the caller's arrays then do nothing, so the column-compressed form
+// stays empty (every column without entries) and every access stays in bounds.
+__global__ void k_csr_check(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx, int B, int U,
+                            int64_t nnz, uint32_t* __restrict__ status) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B) return;
+    const int32_t a0 = rowptr[i], a1 = rowptr[i + 1];
+    bool bad = a0 < 0 || a1 < a0 || (int64_t)a1 > nnz;
+    if (i == 0 && a0 != 0) bad = true;
+    if (i == B - 1 && (int64_t)a1 != nnz) bad = true;
+    if (!bad) {
+        int32_t prev = -1;
+        for (int32_t k = a0; k < a1; ++k) {
+            const int32_t c = colidx[k];
+            if (c <= prev || c >= U) {   // c <= prev also catches c < 0 (prev >= -1)
+                bad = true;
+                break;
+            }
+            prev = c;
+        }
+    }
+    if (bad) atomicOr(status, (uint32_t)CDM_INFO_BAD_INPUT);
+}
+
+__device__ __forceinline__ bool csr_bad(const uint32_t* status) {
+    return (__atomic_load_n(status, __ATOMIC_RELAXED) & (uint32_t)CDM_INFO_BAD_INPUT) != 0u;
+}
+
+__global__ void k_csr_count(const int32_t* __restrict__ colidx, int64_t nnz, int32_t* __restrict__ cnt,
+                            const uint32_t* status) {
+    if (csr_bad(status)) return;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += stride)
         atomicAdd(&cnt[colidx[k] + 1], 1);
@@ -57,9 +90,9 @@ __global__ __launch_bounds__(1024) void k_scan_inplace(int32_t* __restrict__ a, 
 template <typename T>
 __global__ void k_csr_fill(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
                            const cv<T>* __restrict__ val, int B, int32_t* __restrict__ fill,
-                           int32_t* __restrict__ rowidx, cv<T>* __restrict__ cval) {
+                           int32_t* __restrict__ rowidx, cv<T>* __restrict__ cval, const uint32_t* status) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= B) return;
+    if (i >= B || csr_bad(status)) return;
     for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
         const int32_t pos = atomicAdd(&fill[colidx[k]], 1);
         rowidx[pos] = i;
@@ -689,11 +722,12 @@ __global__ __launch_bounds__(SR_NT) void k_cd_sparse(const SparseRsArgs a) {
 template <typename T>
 __global__ void k_sparse_init(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
                               const cv<T>* __restrict__ val, const cv<T>* __restrict__ y, int B,
-                              const cv<T>* __restrict__ x0, int U, cv<T>* __restrict__ r, cv<T>* __restrict__ x) {
+                              const cv<T>* __restrict__ x0, int U, cv<T>* __restrict__ r, cv<T>* __restrict__ x,
+                              const uint32_t* status) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < B) {
         cv<T> ri = y[i];
-        if (x0)
+        if (x0 && !csr_bad(status))
             for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) cfms(ri, val[e], x0[colidx[e]]);
         r[i] = ri;
     }
@@ -710,14 +744,17 @@ template <typename T> static hipError_t launch_sparse_t(const SparseLaunch& L, h
     // 1. CSR -> column-compressed, rows ascending per column
     hipError_t e = launch_zero_u32((uint32_t*)L.colptr, L.U + 1, st);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_csr_check, dim3((L.B + 255) / 256), dim3(256), 0, st, L.rowptr, L.colidx, L.B, L.U, L.nnz,
+                       L.status);
     if (L.nnz > 0) {
         int64_t blocks = (L.nnz + 255) / 256;
         if (blocks > 65536) blocks = 65536;
-        hipLaunchKernelGGL(k_csr_count, dim3((unsigned)blocks), dim3(256), 0, st, L.colidx, L.nnz, L.colptr);
+        hipLaunchKernelGGL(k_csr_count, dim3((unsigned)blocks), dim3(256), 0, st, L.colidx, L.nnz, L.colptr,
+                           L.status);
     }
     hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, st, L.colptr, L.U + 1, L.fill);
     hipLaunchKernelGGL((k_csr_fill<T>), dim3((L.B + 255) / 256), dim3(256), 0, st, L.rowptr, L.colidx,
-                       (const V*)L.val, L.B, L.fill, L.rowidx, (V*)L.cval);
+                       (const V*)L.val, L.B, L.fill, L.rowidx, (V*)L.cval, L.status);
     hipLaunchKernelGGL((k_csc_sort<T>), dim3((L.U + 3) / 4), dim3(256), 0, st, L.colptr, L.U, L.rowidx, (V*)L.cval);
     e = hipGetLastError();
     if (e != hipSuccess || L.transpose_only) return e;
@@ -736,7 +773,7 @@ template <typename T> static hipError_t launch_sparse_t(const SparseLaunch& L, h
                        L.npanels, L.R, L.pi, L.bcnt, L.roff);
     const int n = L.B > L.U ? L.B : L.U;
     hipLaunchKernelGGL((k_sparse_init<T>), dim3((n + 255) / 256), dim3(256), 0, st, L.rowptr, L.colidx,
-                       (const V*)L.val, (const V*)L.y, L.B, (const V*)L.x0, L.U, (V*)L.r, (V*)L.x);
+                       (const V*)L.val, (const V*)L.y, L.B, (const V*)L.x0, L.U, (V*)L.r, (V*)L.x, L.status);
     e = launch_zero_u32((uint32_t*)L.xbuf, (int64_t)2 * L.P * SR_KP * SpTag<T>::NW * 2, st);
     if (e != hipSuccess) return e;
     SparseRsArgs A;

@@ -91,7 +91,7 @@ int wg_occupancy(bool c128, int nt, int rmax, size_t bytes);
 
 // Fusion of C local estimates (Sec. III): x = sum_c lambda_c x_c with
 // lambda_c = sigma_c^-2 / sum_c' sigma_c'^-2 and sigma_c^2 = (N0/U) sum_u m_{u,c}.
-hipError_t launch_fuse(bool c128, const void* xloc, const double* msum, int C, int U, double N0, void* x,
+hipError_t launch_fuse(bool c128, const void* xloc, const double* msum, const double* lam_c, int C, int U, void* x,
                        hipStream_t st);
 
 // Where the panel engine reads H from.

@@ -94,6 +94,8 @@ struct cdm_plan {
     double* e = nullptr;
     void* xloc = nullptr;
     double* msum = nullptr;
+    std::vector<int> bc;      // cluster sizes B_c (rows of each cluster, in order)
+    int bc_min = 0, bc_max = 0;
     void* rpart = nullptr;    // warm-start product scratch
     int nchunk = 1;
     double* res_rpart = nullptr;
@@ -483,9 +485,22 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
     int32_t st = validate_common(desc);
     if (st) return st;
     const cdm_desc& d = *desc;
-    if (d.B < 1 || d.U < 1 || d.C < 1 || d.B % d.C) return CDM_ESHAPE;
-    const int Bc = d.B / d.C;
-    if (d.problem == CDM_DOWNLINK_ZF && Bc < d.U) return CDM_EINFEASIBLE;
+    if (d.B < 1 || d.U < 1 || d.C < 1 || d.C > d.B) return CDM_ESHAPE;
+    if (!d.Bc && d.B % d.C) return CDM_ESHAPE;
+    // cluster sizes: C contiguous row blocks, B/C rows each or the caller's Bc[] (Sec. II-A)
+    std::vector<int> bc(d.C, d.B / std::max(1, d.C));
+    if (d.Bc) {
+        int64_t sum = 0;
+        for (int c = 0; c < d.C; ++c) {
+            if (d.Bc[c] < 1) return CDM_ESHAPE;
+            bc[c] = d.Bc[c];
+            sum += d.Bc[c];
+        }
+        if (sum != d.B) return CDM_ESHAPE;
+    }
+    const int Bc = *std::max_element(bc.begin(), bc.end());      // the largest cluster
+    const int Bc_min = *std::min_element(bc.begin(), bc.end());
+    if (d.problem == CDM_DOWNLINK_ZF && Bc_min < d.U) return CDM_EINFEASIBLE;
     if (d.precision == CDM_MIXED_C64) return CDM_ENOTIMPL;   // batched plans only
     const bool mixed = d.precision == CDM_MIXED_BF16 || d.precision == CDM_MIXED_FP8;
     if (mixed && (d.problem != CDM_UPLINK_LMMSE || d.layout != CDM_DENSE || d.C != 1)) return CDM_ENOTIMPL;
@@ -498,6 +513,10 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
 
     cdm_plan* p = new cdm_plan();
     p->d = d;
+    p->d.Bc = nullptr;   // the sizes are kept in the plan, not the caller's array
+    p->bc = bc;
+    p->bc_min = Bc_min;
+    p->bc_max = Bc;
     p->mixed = mixed;
     p->src_kind = d.precision == CDM_MIXED_BF16 ? SRC_BF16 : (d.precision == CDM_MIXED_FP8 ? SRC_FP8 : SRC_COMPLEX);
     p->c128 = d.precision == CDM_C128;      // mixed: the inner engine runs in FP32
@@ -631,18 +650,20 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
             p->msum = (double*)(b + o_msum);
         }
         std::vector<WgJob> jobs(d.C);
+        int64_t row0 = 0;
         for (int c = 0; c < d.C; ++c) {
             WgJob& j = jobs[c];
-            j.h_off = (int64_t)c * Bc;
+            j.h_off = row0;
             j.ld = 0;   // the solve's ldh
             const bool dl = d.problem == CDM_DOWNLINK_ZF;
-            j.y_off = dl ? 0 : (int64_t)c * Bc;        // downlink: s is broadcast to every cluster
+            j.y_off = dl ? 0 : row0;        // downlink: s is broadcast to every cluster
             j.x0_off = 0;
-            j.x_off = dl ? (int64_t)c * Bc : (int64_t)c * d.U;
-            j.m = Bc;
+            j.x_off = dl ? row0 : (int64_t)c * d.U;
+            j.m = bc[c];
             j.n = d.U;
             j.info_idx = c;
-            j.rpt = rpt_for(Bc, p->wg_nt);
+            j.rpt = rpt_for(bc[c], p->wg_nt);
+            row0 += bc[c];
         }
         if (hipMemcpy(p->jobs, jobs.data(), sizeof(WgJob) * d.C, hipMemcpyHostToDevice) != hipSuccess) {
             (void)hipFree(p->ws);
@@ -725,8 +746,8 @@ static int32_t run_resid(cdm_plan* p, const void* H, int64_t ldh, const void* y,
 }
 
 int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr, const int32_t* colidx,
-                  const void* rhs, double N0, double Ex, double rho, const void* x0, void* x, void* info,
-                  void* stream) {
+                  const void* rhs, double N0, double Ex, double rho, const void* x0, const double* lambda_c,
+                  void* x, void* info, void* stream) {
     (void)rowptr;
     (void)colidx;
     (void)rho;
@@ -736,7 +757,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         return CDM_EINVAL;
     if (d.layout == CDM_DENSE && ldh < d.B) return CDM_ESHAPE;
     const double lambda = N0 / Ex;
-    const int Bc = d.B / d.C;
+    if (lambda_c && (d.problem != CDM_UPLINK_LMMSE || d.C == 1)) return CDM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     cdm_info* inf = (cdm_info*)info;
     if (d.problem == CDM_DOWNLINK_ZF) {
@@ -772,7 +793,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         ev_record(p, 4, st);
         return CDM_OK;
     }
-    if (lambda == 0.0 && Bc < d.U) return CDM_EINFEASIBLE;
+    if (lambda == 0.0 && p->bc_min < d.U) return CDM_EINFEASIBLE;
     if (d.layout == CDM_CSR) {
         if (!rowptr || !colidx) return CDM_EINVAL;
         ev_record(p, 0, st);
@@ -814,7 +835,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         L.resid = 0;
         HIP_TRY(launch_wg(L, st));
         ev_record(p, 3, st);
-        if (d.C > 1) HIP_TRY(launch_fuse(p->c128, p->xloc, p->msum, d.C, d.U, N0, x, st));
+        if (d.C > 1) HIP_TRY(launch_fuse(p->c128, p->xloc, p->msum, lambda_c, d.C, d.U, x, st));
     } else {
         GramLaunch G;
         G.c128 = p->c128;
@@ -893,7 +914,10 @@ int32_t cdm_csr_transpose(cdm_plan* p, const void* val, const int32_t* rowptr, c
         HIP_TRY(hipMemcpyAsync(colptr_out, p->sp_colptr, 4 * ((size_t)p->d.U + 1), hipMemcpyDeviceToDevice, st));
     if (rowidx_out && nnz) HIP_TRY(hipMemcpyAsync(rowidx_out, p->sp_rowidx, 4 * nnz, hipMemcpyDeviceToDevice, st));
     if (cval_out && nnz) HIP_TRY(hipMemcpyAsync(cval_out, p->sp_cval, p->esz * nnz, hipMemcpyDeviceToDevice, st));
-    return CDM_OK;
+    uint32_t status = 0;
+    HIP_TRY(hipMemcpyAsync(&status, p->ctr + 3, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return (status & CDM_INFO_BAD_INPUT) ? CDM_EINVAL : CDM_OK;
 }
 
 int32_t cdm_quantized_copy(cdm_plan* p, const void* H, int64_t ldh, void* re_out, void* im_out, float* scale_out,
@@ -1034,6 +1058,7 @@ int32_t cdm_create_batched(const cdm_desc* desc, int32_t batch, const int32_t* m
     int32_t st = validate_common(desc);
     if (st) return st;
     if (batch < 1 || !m || !n) return CDM_EINVAL;
+    if (desc->Bc || desc->C != 1) return CDM_ENOTIMPL;   // one cluster per batch entry
     const cdm_desc& d = *desc;
     const int low = d.precision == CDM_MIXED_C64 ? WG_LOW_C64 : (d.precision == CDM_MIXED_BF16 ? WG_LOW_BF16 : 0);
     if (d.problem != CDM_UPLINK_LMMSE || d.layout != CDM_DENSE ||

@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version_and_status_strings(lib):
-    assert lib.cdm_version() == 1
+    assert lib.cdm_version() == 2
     assert lib.cdm_status_string(0) == b"ok"
     assert b"infeasible" in lib.cdm_status_string(-6)
     assert lib.cdm_status_string(12345) == b"unknown status"
@@ -67,6 +67,7 @@ def _desc(**kw):
     (dict(U=0), -2),
     (dict(B=65, C=2), -2),
     (dict(problem=1, B=32, U=16, C=4), -6),      # downlink cluster with B_c = 8 < U
+    (dict(B=4, C=5), -2),                         # more clusters than rows
 ])
 def test_create_rejects_invalid_descriptors_on_the_host(lib, kw, status):
     h = C.c_void_p(1)
@@ -75,9 +76,36 @@ def test_create_rejects_invalid_descriptors_on_the_host(lib, kw, status):
     assert h.value is None
 
 
+@pytest.mark.parametrize("sizes,kw,status", [
+    ([30, 30], dict(B=64, C=2), -2),                 # sizes do not sum to B
+    ([64, 0], dict(B=64, C=2), -2),                  # an empty cluster
+    ([40, -6, 30], dict(B=64, C=3), -2),             # a negative size
+    ([50, 14], dict(B=64, U=16, C=2, problem=1), -6),  # downlink cluster with B_c = 14 < U
+])
+def test_create_rejects_invalid_cluster_sizes_on_the_host(lib, sizes, kw, status):
+    arr = (C.c_int32 * len(sizes))(*sizes)
+    d = _desc(**kw)
+    d.Bc = C.cast(arr, C.POINTER(C.c_int32))
+    h = C.c_void_p(1)
+    assert lib.cdm_create(C.byref(d), C.byref(h)) == status
+    assert h.value is None
+
+
+def test_batched_plans_take_no_cluster_sizes(lib):
+    m = np.array([64, 100], np.int32)
+    n = np.array([32, 50], np.int32)
+    arr = (C.c_int32 * 2)(32, 32)
+    d = _desc(B=64, C=2)
+    d.Bc = C.cast(arr, C.POINTER(C.c_int32))
+    h = C.c_void_p(1)
+    assert lib.cdm_create_batched(C.byref(d), 2, m.ctypes.data, n.ctypes.data, C.byref(h)) == -7
+    assert h.value is None
+    assert lib.cdm_create_batched(C.byref(_desc(C=2)), 2, m.ctypes.data, n.ctypes.data, C.byref(h)) == -7
+
+
 def test_null_arguments(lib):
     assert lib.cdm_create(None, None) == -1
-    assert lib.cdm_solve(None, None, 0, None, None, None, 0.1, 1.0, 0.0, None, None, None, None) == -1
+    assert lib.cdm_solve(None, None, 0, None, None, None, 0.1, 1.0, 0.0, None, None, None, None, None) == -1
     assert lib.cdm_destroy(None) == 0
     m = np.array([4], np.int32)
     assert lib.cdm_create_batched(C.byref(_desc()), 0, m.ctypes.data, m.ctypes.data,
@@ -106,7 +134,8 @@ def test_mixed_c64_is_batched_only(lib):
 
 @pytest.mark.parametrize("args,status", [
     (dict(C=3), -2), (dict(Bc=33), -2), (dict(U=17), -2), (dict(U=0), -2), (dict(S=0), -2),
-    (dict(prec=0), -3), (dict(T=0), -1), (dict(N0=0.0), -1), (dict(Ex=0.0), -1),
+    (dict(prec=0), -3), (dict(T=0), -1), (dict(N0=-1.0), -1), (dict(Ex=0.0), -1),
+    (dict(N0=0.0, Bc=4), -6),                     # lambda = 0 with B_c < U
 ])
 def test_detect_batch_rejects_on_the_host(lib, args, status):
     a = dict(S=4, V=3, C=4, Bc=32, U=8, T=3, prec=1, N0=0.5, Ex=1.0)
@@ -133,4 +162,4 @@ def test_precode_batch_rejects_on_the_host(lib, args, status):
 def test_info_record_layout():
     from paper_1902_08653_amd import cdm
     assert cdm.INFO_DTYPE.itemsize == 32
-    assert C.sizeof(cdm.Desc) == 56
+    assert C.sizeof(cdm.Desc) == 64

@@ -79,8 +79,11 @@ def test_gradients_vs_oracle(dev, mo, rows):
         assert relerr(got_b, want_b) <= 2e-3
     loss = float(parts.double().sum().cpu()) / (rows * SHAPE[3])
     assert abs(loss - mo.loss(w.astype(np.float64), SHAPE, X, T, bf16=True)) <= 1e-4 * loss
-    # the BF16 operand rounding is a small perturbation of the exact FP64 gradient
-    assert relerr(g, mo.gradients(w.astype(np.float64), SHAPE, X, T)) <= 8e-2
+    # against the exact FP64 gradient the kernel may be off by no more than the BF16
+    # operand rounding itself (the oracle's distance, computed on the CPU: 3.8e-2 at 5
+    # rows, 5.4e-3 at 300, 4.2e-3 at 512) plus the parity bar above
+    exact = mo.gradients(w.astype(np.float64), SHAPE, X, T)
+    assert relerr(g, exact) <= relerr(want, exact) + 2e-3
     net.close()
 
 

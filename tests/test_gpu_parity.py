@@ -332,3 +332,58 @@ def test_quantized_copy_bit_exact(dev, orc, kind):
         assert np.array_equal(out[0].cpu().numpy(), ref[0])
         assert np.array_equal(out[1].cpu().numpy(), ref[1])
         assert np.array_equal(out[2].cpu().numpy(), ref[2])
+
+
+def _full_range_batch(count=64):
+    """The uneven batch's own draws (m ~ U{64..2048}) plus the two extremes, m = 2048
+    and m = 64: rows per thread 1 to 8 mixed in one launch."""
+    ins = [inputs.batch_instance(i) for i in range(count - 2)]
+    ins.append(inputs.batch_instance(5000, m_lo=2048, m_hi=2048))
+    ins.append(inputs.batch_instance(5001, m_lo=64, m_hi=64))
+    return ins
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("autotune", [False, True])
+def test_batched_full_size_range_fixed_sweeps(dev, orc, prec, autotune):
+    """64 instances spanning m = 64..2048 (n = m/2) in one persistent launch, fixed T = 3:
+    every instance against the oracle."""
+    from paper_1902_08653_amd import cdm
+    ins = _full_range_batch()
+    Hf, yf, m, n, ho, yo, xo = inputs.pack_batch(ins, dtype=DT[prec])
+    assert m.min() == 64 and m.max() == 2048
+    plan = cdm.BatchedPlan(m, n, precision=prec, T_max=3, autotune=autotune)
+    x, info = plan.solve(torch.from_numpy(Hf).to(dev), torch.from_numpy(yf).to(dev), N0=0.1)
+    torch.cuda.synchronize()
+    x = x.cpu().numpy().astype(np.complex128)
+    rec = cdm.parse_info(info)
+    assert np.all(rec["sweeps"] == 3) and np.all(rec["flags"] == 0)
+    worst = 0.0
+    for k, inst in enumerate(ins):
+        Ho, yo_ = oracle_inputs(inst.H, inst.y, prec)
+        ref = orc.local_cd(Ho, yo_, 0.1, T_max=3)
+        worst = max(worst, relerr(x[xo[k]:xo[k] + n[k]], ref["x"]))
+    assert worst <= TOL[prec], worst
+    plan.close()
+
+
+def test_batched_full_size_range_tolerance_mode(dev, orc):
+    """The benchmark's stop rule (complex64, relative step 1e-6, cap 200) over the full
+    size range: per instance the sweep count is within one of the oracle's and x equals
+    the oracle's at the GPU's count."""
+    from paper_1902_08653_amd import cdm
+    ins = _full_range_batch()
+    Hf, yf, m, n, ho, yo, xo = inputs.pack_batch(ins, dtype=np.complex64)
+    plan = cdm.BatchedPlan(m, n, precision="c64", T_max=200, tol=1e-6, autotune=True)
+    x, info = plan.solve(torch.from_numpy(Hf).to(dev), torch.from_numpy(yf).to(dev), N0=0.1)
+    torch.cuda.synchronize()
+    x = x.cpu().numpy().astype(np.complex128)
+    rec = cdm.parse_info(info)
+    assert np.all(rec["flags"] == 0)
+    for k, inst in enumerate(ins):
+        Ho, yo_ = oracle_inputs(inst.H, inst.y, "c64")
+        ref = orc.local_cd(Ho, yo_, 0.1, T_max=200, tol=1e-6)
+        assert abs(int(rec["sweeps"][k]) - int(ref["sweeps"])) <= 1, k
+        at = orc.local_cd(Ho, yo_, 0.1, T_max=int(rec["sweeps"][k]))
+        assert relerr(x[xo[k]:xo[k] + n[k]], at["x"]) <= 1e-5, k
+    plan.close()

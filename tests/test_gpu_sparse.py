@@ -155,3 +155,57 @@ def test_sparse_many_slices(dev, orc, B):
     print(desc, err)
     assert '"workgroups": 64' in desc
     assert info["sweeps"] == 3 and err <= TOL["c128"]
+
+
+def _malformed(kind):
+    """A valid CSR instance with one defect planted in its index arrays.  The arrays
+    keep their sizes (rowptr B+1 entries, colidx nnz entries), as the ABI requires."""
+    ins = inputs.sparse_uplink(300, 140, 0.05, seed=5)
+    rp, ci = ins.rowptr.copy(), ins.colidx.copy()
+    nnz = int(rp[-1])
+    r = int(np.argmax(np.diff(rp) >= 3))          # a row with at least 3 entries
+    a = int(rp[r])
+    if kind == "col_too_large":
+        ci[a + 1] = 140
+    elif kind == "col_negative":
+        ci[a] = -7
+    elif kind == "col_repeated":
+        ci[a + 1] = ci[a]
+    elif kind == "col_unsorted":
+        ci[a], ci[a + 1] = ci[a + 1], ci[a]
+    elif kind == "rowptr_decreasing":
+        rp[r + 1] = rp[r] - 1
+    elif kind == "rowptr_end":
+        rp[-1] = nnz + 10                          # past the nnz the plan was made for
+    elif kind == "rowptr_start":
+        rp[0] = 1
+    return ins, rp, ci, nnz
+
+
+@pytest.mark.parametrize("kind", ["col_too_large", "col_negative", "col_repeated", "col_unsorted",
+                                  "rowptr_decreasing", "rowptr_end", "rowptr_start"])
+def test_malformed_csr_is_flagged_without_touching_it(dev, kind):
+    """Malformed index arrays are caught on the device before any write indexed by
+    them: the solve returns CDM_INFO_BAD_INPUT with x from H = 0 (x = 0 for lambda > 0),
+    and the transpose hook reports CDM_EINVAL."""
+    from paper_1902_08653_amd import cdm
+    ins, rp, ci, nnz = _malformed(kind)
+    plan = cdm.Plan(ins.B, ins.U, layout="csr", nnz=nnz, precision="c128", T_max=3)
+    val = torch.from_numpy(ins.val).to(dev)
+    rpd, cid = torch.from_numpy(rp).to(dev), torch.from_numpy(ci).to(dev)
+    y = torch.from_numpy(ins.y).to(dev)
+    x, info = plan.solve(val, y, N0=0.1, rowptr=rpd, colidx=cid)
+    torch.cuda.synchronize()
+    rec = cdm.parse_info(info)[0]
+    assert rec["flags"] & 16, rec
+    assert np.all(x.cpu().numpy() == 0)
+    with pytest.raises(cdm.CdmError) as e:
+        plan.csr_transpose(val, rpd, cid)
+    assert e.value.status == -1
+    # the same plan still solves a well-formed input afterwards
+    x2, info2 = plan.solve(val, y, N0=0.1, rowptr=torch.from_numpy(ins.rowptr).to(dev),
+                           colidx=torch.from_numpy(ins.colidx).to(dev))
+    torch.cuda.synchronize()
+    assert cdm.parse_info(info2)[0]["flags"] == 0
+    assert np.linalg.norm(x2.cpu().numpy()) > 0
+    plan.close()
