@@ -4,8 +4,11 @@ per subcarrier channel, fixed T sweeps, per-cluster power scaling to rho/sqrt(C)
 
 Reference: the oracle's Algorithm 2 end to end (downlink_cd) on each (subcarrier,
 vector), in FP64 on the inputs as the kernel sees them (rounded to FP32 or FP16).
-Bars as for the batched detector: complex64 1e-5 relative over the batch; complex FP16
-(FP16 iterate, packed FP16 dot products and updates, FP32 scalar rule) 3e-2.
+Every stacked output vector is checked on its own: the maximum over (subcarrier,
+vector) of ||x - x_oracle|| / ||x_oracle||.
+  complex64: 1e-5 per vector (measured maximum over the shapes below 1.8e-7).
+  complex FP16 (FP16 iterate, packed FP16 dot products and updates, FP32 scalar rule):
+  measured maximum 1.77e-3 (one cluster of 32 x 16); bar 5e-3 per vector.
 """
 import numpy as np
 import pytest
@@ -23,6 +26,16 @@ def dev():
     from paper_1902_08653_amd import cdm
     cdm.lib()
     return torch.device("cuda:0")
+
+
+def max_vec_err(x, ref):
+    """Largest relative error of any single output vector (last axis)."""
+    num = np.linalg.norm(x - ref, axis=-1)
+    den = np.maximum(np.linalg.norm(ref, axis=-1), 1e-300)
+    return float((num / den).max())
+
+
+C64_BAR, F16_BAR = 1e-5, 5e-3
 
 
 def relerr(a, b):
@@ -82,7 +95,7 @@ def test_precode_batch_c64_matches_oracle(dev, orc, C, Bc, U, S, V, T, rho):
     d = inputs.paper_shaped(C, Bc, U, S, V, snr_db=10.0, seed=300 + C * Bc + U)
     x = run(dev, d["Ht"], d["X"], C, Bc, U, T, rho, half=False)
     ref = oracle(orc, d["Ht"], d["X"], C, T, rho, half=False)
-    assert relerr(x, ref) <= 1e-5
+    assert max_vec_err(x, ref) <= C64_BAR
 
 
 @pytest.mark.parametrize("C,Bc,U,S,V,T,rho", SHAPES)
@@ -90,7 +103,7 @@ def test_precode_batch_fp16_matches_oracle(dev, orc, C, Bc, U, S, V, T, rho):
     d = inputs.paper_shaped(C, Bc, U, S, V, snr_db=10.0, seed=400 + C * Bc + U)
     x = run(dev, d["Ht"], d["X"], C, Bc, U, T, rho, half=True)
     ref = oracle(orc, d["Ht"], d["X"], C, T, rho, half=True)
-    assert relerr(x, ref) <= 3e-2
+    assert max_vec_err(x, ref) <= F16_BAR
 
 
 def test_precode_batch_power_and_zero_forcing(dev, orc):
@@ -116,4 +129,4 @@ def test_precode_batch_fp16_two_vectors_per_quad(dev, orc):
     x = run(dev, d["Ht"], d["X"], C, Bc, U, T, 1.0, half=True)
     pick = np.linspace(0, S - 1, 12).astype(int)
     ref = oracle(orc, d["Ht"][pick], d["X"][pick], C, T, 1.0, half=True)
-    assert relerr(x[pick], ref) <= 3e-2
+    assert max_vec_err(x[pick], ref) <= F16_BAR

@@ -4,11 +4,12 @@ V received vectors per subcarrier channel, fixed T sweeps, cluster fusion.
 
 Reference: the oracle's Algorithm 1 with fusion (uplink_cd) on each (subcarrier,
 vector), run in FP64 on the inputs as the kernel sees them (rounded to FP32 or FP16).
-Bars: complex64 1e-5 relative over the batch (as for the other FP32 paths).  Complex
-FP16 keeps the residual and channel in FP16 and forms dot products and residual
-updates in packed FP16 (unit roundoff 2^-11 = 4.9e-4); a 32-term dot in a five-level
-tree carries about sqrt(32) unit roundoffs and T <= 4 sweeps over U users compound it,
-so the bar is 3e-2 relative.
+Every fused vector is checked on its own: the maximum over (subcarrier, vector) of the
+relative error ||x - x_oracle|| / ||x_oracle||.
+  complex64: 1e-5 per vector (measured maximum over the shapes below 1.7e-7).
+  complex FP16 (residual and channel in FP16, packed FP16 dot products and updates,
+  unit roundoff 2^-11 = 4.9e-4): measured maximum 1.07e-3 (one cluster of 32 x 16, the
+  largest U), 3.7e-4 on the 1100-subcarrier launch; bar 3e-3 per vector.
 """
 import numpy as np
 import pytest
@@ -30,6 +31,16 @@ def dev():
 
 def relerr(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def max_vec_err(x, ref):
+    """Largest relative error of any single output vector (last axis)."""
+    num = np.linalg.norm(x - ref, axis=-1)
+    den = np.maximum(np.linalg.norm(ref, axis=-1), 1e-300)
+    return float((num / den).max())
+
+
+C64_BAR, F16_BAR = 1e-5, 3e-3
 
 
 def to_half(z):
@@ -85,7 +96,7 @@ def test_detect_batch_c64_matches_oracle(dev, orc, C, Bc, U, S, V, T):
     d = inputs.paper_shaped(C, Bc, U, S, V, snr_db=10.0, seed=100 + C * Bc + U)
     x = run(dev, d, C, Bc, U, T, half=False)
     ref = oracle(orc, d, C, T, half=False)
-    assert relerr(x, ref) <= 1e-5
+    assert max_vec_err(x, ref) <= C64_BAR
 
 
 @pytest.mark.parametrize("C,Bc,U,S,V,T", SHAPES)
@@ -93,7 +104,7 @@ def test_detect_batch_fp16_matches_oracle(dev, orc, C, Bc, U, S, V, T):
     d = inputs.paper_shaped(C, Bc, U, S, V, snr_db=10.0, seed=200 + C * Bc + U)
     x = run(dev, d, C, Bc, U, T, half=True)
     ref = oracle(orc, d, C, T, half=True)
-    assert relerr(x, ref) <= 3e-2
+    assert max_vec_err(x, ref) <= F16_BAR
 
 
 def test_detect_batch_fusion_weights(dev, orc):
@@ -119,4 +130,4 @@ def test_detect_batch_fp16_two_vectors_per_quad(dev, orc):
     pick = np.linspace(0, S - 1, 12).astype(int)
     sub = dict(Ht=d["Ht"][pick], Y=d["Y"][pick], N0=d["N0"])
     ref = oracle(orc, sub, C, T, half=True)
-    assert relerr(x[pick], ref) <= 3e-2
+    assert max_vec_err(x[pick], ref) <= F16_BAR
