@@ -346,6 +346,32 @@ int32_t cdm_plan_timings(const cdm_plan* plan, double* out_ms, int32_t n, int32_
  * src, dst: device, 16-byte aligned, non-overlapping. */
 int32_t cdm_stream_copy(const void* src, void* dst, int64_t bytes, void* stream);
 
+/* ---- solve without allocation -------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The same solve as cdm_create +
+ * cdm_solve + cdm_destroy for the per-cluster engine (one workgroup per cluster; the
+ * same kernels, so the same bits), with no plan: every buffer beyond the caller's
+ * inputs and outputs lives in one static device array of CDM_NOALLOC_SCRATCH_BYTES per
+ * device, held from the first call on that device until the process ends.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine) and does not
+ * synchronise.  All calls on one device share its array and its contents persist
+ * between calls: calls whose executions overlap on one device (different streams,
+ * threads, or an unsynchronised graph replay next to a direct call) race and give
+ * wrong results; order them on one stream.
+ * Arguments as cdm_create (desc, read by this call only) and cdm_solve (no rowptr /
+ * colidx).  Limits: dense layout, CDM_C128 or CDM_C64, engine AUTO or WG, every cluster
+ * within the per-cluster engine's rows (4096 complex128, 8192 complex64 per cluster),
+ * C <= CDM_NOALLOC_MAX_CLUSTERS, and for an uplink with C > 1 the C x U local estimates
+ * within the array (16 or 8 B each, CDM_NOALLOC_SCRATCH_BYTES - 8 KiB in all).
+ * Errors: as cdm_create and cdm_solve; CDM_ESHAPE (message via cdm_last_error) for
+ * sizes beyond the limits, CDM_EDTYPE for other layouts or precisions, CDM_ENOTIMPL for
+ * the panel engine. */
+#define CDM_NOALLOC_SCRATCH_BYTES (4u << 20)
+#define CDM_NOALLOC_MAX_CLUSTERS 64
+int32_t cdm_solve_noalloc(const cdm_desc* desc, const void* H, int64_t ldh, const void* rhs, double N0,
+                          double Ex, double rho, const void* x0, const double* lambda_c, void* x, void* info,
+                          void* stream);
+
 /* Release the plan and its device workspace. NULL is accepted. */
 int32_t cdm_destroy(cdm_plan* plan);
 

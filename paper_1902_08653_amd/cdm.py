@@ -58,7 +58,7 @@ EXPORTS = ["cdm_version", "cdm_status_string", "cdm_last_error", "cdm_create", "
            "cdm_plan_describe", "cdm_plan_timings", "cdm_stream_copy", "cdm_csr_transpose", "cdm_quantized_copy", "cdm_batched_features", "cdm_mlp_create",
            "cdm_mlp_param_count", "cdm_mlp_set_weights", "cdm_mlp_get_weights", "cdm_mlp_forward",
            "cdm_mlp_gradients", "cdm_mlp_train_step", "cdm_mlp_predict", "cdm_mlp_destroy", "cdm_destroy",
-           "cdm_detect_batch", "cdm_precode_batch"]
+           "cdm_detect_batch", "cdm_precode_batch", "cdm_solve_noalloc"]
 
 _lib = None
 
@@ -80,6 +80,8 @@ def lib():
         L.cdm_create.restype = i32
         L.cdm_solve.argtypes = [P, P, i64, P, P, P, f64, f64, f64, P, P, P, P, P]
         L.cdm_solve.restype = i32
+        L.cdm_solve_noalloc.argtypes = [C.POINTER(Desc), P, i64, P, f64, f64, f64, P, P, P, P, P]
+        L.cdm_solve_noalloc.restype = i32
         L.cdm_create_batched.argtypes = [C.POINTER(Desc), i32, P, P, C.POINTER(P)]
         L.cdm_create_batched.restype = i32
         L.cdm_batched_offsets.argtypes = [P, P, P, P]
@@ -251,6 +253,30 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def solve_noalloc(Hc, rhs, B, U, C_clusters=1, Bc=None, precision="c128", T_max=3, tol=0.0,
+                  problem="uplink", N0=0.1, Ex=1.0, rho=0.0, x0=None, lambda_c=None, x=None, info=None,
+                  stream=None):
+    """cdm_solve_noalloc: the per-cluster solve with the library's static scratch (no
+    plan, no allocation inside the library).  x and info may be given to keep the call
+    free of allocations on the Python side as well.  Returns (x, info)."""
+    import torch
+    Cn = int(C_clusters)
+    bc = None if Bc is None else (C.c_int32 * Cn)(*[int(v) for v in Bc])
+    d = Desc(problem=UPLINK_LMMSE if problem == "uplink" else DOWNLINK_ZF, precision=_PREC[precision],
+             layout=DENSE, engine=ENGINE_AUTO, B=int(B), U=int(U), C=Cn, T_max=int(T_max), tol=float(tol),
+             nnz=0, panel=0, flags=0, Bc=C.cast(bc, C.POINTER(C.c_int32)) if bc is not None else None)
+    dev = rhs.device
+    if x is None:
+        x = torch.empty(int(U) if problem == "uplink" else int(B), dtype=rhs.dtype, device=dev)
+    if info is None:
+        info = torch.empty(32 * Cn, dtype=torch.uint8, device=dev)
+    ldh = Hc.shape[1] if Hc.dim() == 2 else int(B)
+    _check(lib().cdm_solve_noalloc(C.byref(d), _ptr(Hc), int(ldh), _ptr(rhs), float(N0), float(Ex), float(rho),
+                                   _ptr(x0), _ptr(lambda_c), _ptr(x), _ptr(info), _stream(stream)),
+           "cdm_solve_noalloc")
+    return x, info
 
 
 def detect_batch(H, Y, S, V, C_clusters, Bc, U, T_max, N0, Ex=1.0, out=None, stream=None):

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -1369,3 +1370,184 @@ int32_t cdm_destroy(cdm_plan* p) {
 }
 
 }  // extern "C"
+
+// ---- the entry point that allocates nothing ------------------------------------------
+// cdm_solve_noalloc runs the per-cluster (one workgroup per cluster) solve with every
+// buffer beyond the caller's inputs and outputs in `scratch`, a file-scope device array
+// of fixed size: the queue and status words, the job records, and (uplink, C > 1) the
+// local estimates and the sums of m_u,c that the fusion reads.  Each device holds its
+// own copy of the array until the process ends; host code uses the address that
+// hipGetSymbolAddress returns for the current device, never the array's name.
+namespace {
+
+constexpr size_t kNaBytes = CDM_NOALLOC_SCRATCH_BYTES;
+constexpr size_t kNaCtr = 0;          // 64 control words (queue counter, status)
+constexpr size_t kNaJobs = 256;       // CDM_NOALLOC_MAX_CLUSTERS job records
+constexpr size_t kNaMsum = 4096;      // one double per cluster
+constexpr size_t kNaXloc = 8192;      // C x U local estimates
+static_assert(kNaJobs + sizeof(WgJob) * CDM_NOALLOC_MAX_CLUSTERS <= kNaMsum, "job records overlap");
+static_assert(kNaMsum + 8 * CDM_NOALLOC_MAX_CLUSTERS <= kNaXloc, "cluster sums overlap");
+
+__device__ __align__(256) unsigned char scratch[kNaBytes];
+
+constexpr int kNaMaxDev = 64;
+void* g_na_ptr[kNaMaxDev] = {};
+int g_na_ncu[kNaMaxDev] = {};
+std::mutex g_na_mu;
+
+// The device's scratch address and CU count, set up once per device with it current.
+int32_t na_device(int dev, char** ptr, int* ncu) {
+    if (dev < 0 || dev >= kNaMaxDev) return CDM_ENODEV;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return CDM_ENODEV;
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            snprintf(g_last_error, sizeof(g_last_error), "device %d is %s, this library is built for gfx950", dev,
+                     prop.gcnArchName);
+            return CDM_ENODEV;
+        }
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_err("hipGetSymbolAddress(scratch)", e);
+            return CDM_EHIP;
+        }
+        g_na_ncu[dev] = prop.multiProcessorCount;
+        g_na_ptr[dev] = p;
+    }
+    *ptr = (char*)g_na_ptr[dev];
+    *ncu = g_na_ncu[dev];
+    return CDM_OK;
+}
+
+// Job records of the C clusters (contiguous row blocks), written on the device so that
+// the solve issues no host-to-device copy.
+struct NaJobsArg {
+    int C, U, downlink;
+    int32_t m[CDM_NOALLOC_MAX_CLUSTERS];
+    int32_t rpt[CDM_NOALLOC_MAX_CLUSTERS];
+    int64_t row0[CDM_NOALLOC_MAX_CLUSTERS];
+};
+__global__ void k_na_jobs(NaJobsArg a, WgJob* jobs) {
+    const int c = threadIdx.x;
+    if (c >= a.C) return;
+    WgJob j;
+    j.h_off = a.row0[c];
+    j.ld = 0;
+    j.y_off = a.downlink ? 0 : a.row0[c];
+    j.x0_off = 0;
+    j.x_off = a.downlink ? a.row0[c] : (int64_t)c * a.U;
+    j.m = a.m[c];
+    j.n = a.U;
+    j.info_idx = c;
+    j.rpt = a.rpt[c];
+    jobs[c] = j;
+}
+
+}  // namespace
+
+extern "C" int32_t cdm_solve_noalloc(const cdm_desc* desc, const void* H, int64_t ldh, const void* rhs, double N0,
+                                     double Ex, double rho, const void* x0, const double* lambda_c, void* x,
+                                     void* info, void* stream) {
+    int32_t st0 = validate_common(desc);
+    if (st0) return st0;
+    const cdm_desc& d = *desc;
+    if (!H || !rhs || !x || !info) return CDM_EINVAL;
+    if (d.layout != CDM_DENSE || (d.precision != CDM_C128 && d.precision != CDM_C64)) return CDM_EDTYPE;
+    if (d.engine == CDM_ENGINE_PANEL) return CDM_ENOTIMPL;
+    const bool dl = d.problem == CDM_DOWNLINK_ZF;
+    if (d.B < 1 || d.U < 1 || d.C < 1 || d.C > d.B) return CDM_ESHAPE;
+    if (!d.Bc && d.B % d.C) return CDM_ESHAPE;
+    if (ldh < d.B) return CDM_ESHAPE;
+    if (dl && (x0 || lambda_c)) return CDM_EINVAL;
+    if (lambda_c && d.C == 1) return CDM_EINVAL;
+    if (!dl && (!(Ex > 0.0) || !(N0 >= 0.0) || !std::isfinite(N0) || !std::isfinite(Ex))) return CDM_EINVAL;
+    const bool c128 = d.precision == CDM_C128;
+    const size_t esz = c128 ? 16 : 8;
+    if (d.C > CDM_NOALLOC_MAX_CLUSTERS ||
+        (!dl && d.C > 1 && kNaXloc + esz * (size_t)d.C * d.U > kNaBytes)) {
+        snprintf(g_last_error, sizeof(g_last_error),
+                 "cdm_solve_noalloc: C = %d clusters x U = %d users exceed the static scratch (%d clusters, %zu bytes)",
+                 d.C, d.U, CDM_NOALLOC_MAX_CLUSTERS, kNaBytes);
+        return CDM_ESHAPE;
+    }
+    NaJobsArg ja;
+    ja.C = d.C;
+    ja.U = d.U;
+    ja.downlink = dl ? 1 : 0;
+    int bc_min = d.B, bc_max = 0;
+    int64_t row0 = 0;
+    for (int c = 0; c < d.C; ++c) {
+        const int m = d.Bc ? d.Bc[c] : d.B / d.C;
+        if (m < 1) return CDM_ESHAPE;
+        ja.m[c] = m;
+        ja.row0[c] = row0;
+        row0 += m;
+        bc_min = std::min(bc_min, m);
+        bc_max = std::max(bc_max, m);
+    }
+    if (row0 != d.B) return CDM_ESHAPE;
+    if (dl && bc_min < d.U) return CDM_EINFEASIBLE;
+    const double lambda = dl ? 0.0 : N0 / Ex;
+    if (!dl && lambda == 0.0 && bc_min < d.U) return CDM_EINFEASIBLE;
+    if (bc_max > (c128 ? kWgMaxRows / 2 : kWgMaxRows)) return CDM_ESHAPE;   // one workgroup per cluster
+    const int nt = wg_nt_single(bc_max, c128);
+    const int rmax = rpt_for(bc_max, nt);
+    if (rmax == 0) return CDM_ESHAPE;
+    for (int c = 0; c < d.C; ++c) ja.rpt[c] = rpt_for(ja.m[c], nt);
+    const size_t lds = wg_lds_bytes(d.U, c128);
+    if (lds + 2048 > kLdsMax) return CDM_ESHAPE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CDM_ENODEV;
+    char* sp = nullptr;
+    int ncu = 0;
+    int32_t st1 = na_device(dev, &sp, &ncu);
+    if (st1) return st1;
+    if (lds > 64 * 1024 && wg_set_lds_limit(c128, nt, rmax, lds) != hipSuccess) return CDM_ESHAPE;
+    const int occ = std::max(1, wg_occupancy(c128, nt, rmax, lds));
+
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t* ctr = (uint32_t*)(sp + kNaCtr);
+    WgJob* jobs = (WgJob*)(sp + kNaJobs);
+    double* msum = (double*)(sp + kNaMsum);
+    void* xloc = sp + kNaXloc;
+    HIP_TRY(launch_zero_u32(ctr, 16, st));
+    hipLaunchKernelGGL(k_na_jobs, dim3(1), dim3(CDM_NOALLOC_MAX_CLUSTERS), 0, st, ja, jobs);
+    HIP_TRY(hipGetLastError());
+    WgLaunch L;
+    L.c128 = c128;
+    L.nt = nt;
+    L.rmax = rmax;
+    L.grid = std::max(1, std::min(d.C, occ * ncu));
+    L.n_max = d.U;
+    L.jobs = jobs;
+    L.njobs = d.C;
+    L.order = nullptr;
+    L.queue = ctr + 4;
+    L.H = H;
+    L.Y = rhs;
+    L.info = (cdm_info*)info;
+    L.T_max = d.T_max;
+    L.tol = d.tol;
+    L.ld = ldh;
+    L.resid = 0;
+    if (dl) {
+        L.X0 = nullptr;
+        L.X = x;
+        L.lambda = 0.0;
+        L.msum = nullptr;
+        L.rho_c = rho > 0.0 ? rho / std::sqrt((double)d.C) : 0.0;
+        HIP_TRY(launch_zf(L, st));
+        return CDM_OK;
+    }
+    const bool fuse = d.C > 1;
+    L.X0 = x0;
+    L.X = fuse ? xloc : x;
+    L.lambda = lambda;
+    L.msum = fuse ? msum : nullptr;
+    L.rho_c = 0.0;
+    HIP_TRY(launch_wg(L, st));
+    if (fuse) HIP_TRY(launch_fuse(c128, xloc, msum, lambda_c, d.C, d.U, x, st));
+    return CDM_OK;
+}
