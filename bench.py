@@ -798,7 +798,7 @@ def bench_warm(a):
         from oracle import oracle
         oracle.build()
         order = np.argsort(-mn)
-        pick = order[np.linspace(0, a.batch - 1, a.sample).astype(int)]
+        pick = order[np.linspace(0, a.batch - 1, a.sample or 12).astype(int)]
         ho = np.concatenate([[0], np.cumsum(mn)[:-1]])
         yo = np.concatenate([[0], np.cumsum(m.astype(np.int64))[:-1]])
         xo = np.concatenate([[0], np.cumsum(n.astype(np.int64))[:-1]])
@@ -842,6 +842,11 @@ def bench_warm(a):
         "cpu_baseline": cpu,
         "forms": {k: stats(k) for k in ms},
         "speedup_vs_plain_cold": {k: ms["plain_cold"] / ms[k] for k in ms},
+        # the two effects apart: the learned warm start against the same form cold (> 1:
+        # the network pays for itself), and mixed precision against plain, both cold
+        "network_net_effect": {"plain": ms["plain_cold"] / ms["plain_warm"],
+                               "mixed": ms["mixed_cold"] / ms["mixed_warm"]},
+        "mixed_precision_effect_cold": ms["plain_cold"] / ms["mixed_cold"],
         "warm_stage_ms": {"features": st[0], "network": st[1], "solve": st[2]},
         "network_tflops": mlp_flop / (st[1] * 1e-3) / 1e12,
         "train": {"rows": train_rows, "steps": a.epochs * steps_per_epoch, "seconds": train_s,

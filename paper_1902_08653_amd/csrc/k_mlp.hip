@@ -1,8 +1,9 @@
 // k_mlp.hip -- the small per-coordinate MLP of the learned warm start.
 //
 // Three weight layers F -> H1 -> H2 -> 2 with ReLU between them; BF16 operands on
-// MFMA (v_mfma_f32_16x16x16_bf16) with FP32 accumulation; FP32 master weights and
-// Adam state.  The GEMM is generic over strides so that one kernel serves the
+// gfx950's doubled-K MFMA (v_mfma_f32_16x16x32_bf16: 16 x 16 output, K = 32 per
+// instruction, each lane holding 8 consecutive k of its row or column) with FP32
+// accumulation; FP32 master weights and Adam state.  The GEMM is generic over strides so that one kernel serves the
 // forward products, the weight gradients (A^T B) and the input gradients (A B^T).
 #include <algorithm>
 
@@ -11,24 +12,32 @@
 
 namespace cdm {
 
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16 bits, round to nearest even (NaN kept quiet)
+// the MFMA fragment of 8 consecutive BF16 values at p (16-B aligned)
+__device__ __forceinline__ bf16x8_t frag8(const unsigned short* p) { return *reinterpret_cast<const bf16x8_t*>(p); }
+__device__ __forceinline__ f32x4_t mfma32(const bf16x8_t& a, const bf16x8_t& b, const f32x4_t& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+
+// FP32 -> BF16 bits, round to nearest even, by gfx950's conversion instruction
+// (v_cvt_pk_bf16_f32; a NaN stays a NaN)
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
+}
 __device__ __forceinline__ unsigned short f32_to_bf16(float f) {
-    const uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (unsigned short)((u >> 16) | 0x40u);
-    uint32_t q = u >> 16;
-    const uint32_t rem = u & 0xffffu;
-    if (rem > 0x8000u || (rem == 0x8000u && (q & 1u))) q += 1u;
-    return (unsigned short)q;
+    return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
 
 // C[m][n] = sum_k A(m, k) B(k, n) (+ bias[n]); A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn];
 // C row-major with leading dimension ldc.  64 x 64 tile per workgroup of 4 waves,
-// each wave a 32 x 32 block of 2 x 2 MFMA 16 x 16 x 16 tiles.  beta: 0 overwrite, 1 accumulate.
+// each wave a 32 x 32 block of 2 x 2 MFMA 16 x 16 x 32 tiles.  beta: 0 overwrite, 1 accumulate.
 constexpr int GT = 64;
-constexpr int GK = 16;
+constexpr int GK = 32;
 
 __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, int64_t sam, int64_t sak,
                                                    const float* __restrict__ Bm, int64_t sbk, int64_t sbn,
@@ -42,8 +51,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, 
         C += (int64_t)z * zc;
         K = min(kc, K - z * kc);
     }
-    __shared__ unsigned short As[GT][GK + 4];
-    __shared__ unsigned short Bs[GK][GT + 4];
+    // both tiles k-fastest (a fragment is 8 consecutive k: one 16-B read); rows padded by
+    // 8 values to keep the 16-B reads of a wave on distinct banks
+    __shared__ __align__(16) unsigned short As[GT][GK + 8];
+    __shared__ __align__(16) unsigned short Bs[GT][GK + 8];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
     const int wm = (wid >> 1) * 32, wn = (wid & 1) * 32;
@@ -53,31 +64,29 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, 
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += GK) {
-        // stage A (64 x 16) and B (16 x 64) as BF16: 1024 elements each, 4 per thread
+        // stage A (64 x 32) and B (32 x 64) as BF16: 2048 elements each, 8 per thread
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
             const int e = tid + 256 * q;
             const int am = e / GK, ak = e % GK;
             const int gm = m0 + am, gk = k0 + ak;
             As[am][ak] = (gm < M && gk < K) ? f32_to_bf16(A[(int64_t)gm * sam + (int64_t)gk * sak]) : (unsigned short)0;
             const int bk = e / GT, bn = e % GT;
             const int hk = k0 + bk, hn = n0 + bn;
-            Bs[bk][bn] = (hk < K && hn < N) ? f32_to_bf16(Bm[(int64_t)hk * sbk + (int64_t)hn * sbn]) : (unsigned short)0;
+            Bs[bn][bk] = (hk < K && hn < N) ? f32_to_bf16(Bm[(int64_t)hk * sbk + (int64_t)hn * sbn]) : (unsigned short)0;
         }
         __syncthreads();
-        bf16x4_t a[2], b[2];
-        const int kk = 4 * (lane >> 4);
+        bf16x8_t a[2], b[2];
+        const int kk = 8 * (lane >> 4);
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const int r = wm + 16 * i + (lane & 15);
-            a[i] = bf16x4_t{(short)As[r][kk], (short)As[r][kk + 1], (short)As[r][kk + 2], (short)As[r][kk + 3]};
-            const int c = wn + 16 * i + (lane & 15);
-            b[i] = bf16x4_t{(short)Bs[kk][c], (short)Bs[kk + 1][c], (short)Bs[kk + 2][c], (short)Bs[kk + 3][c]};
+            a[i] = frag8(&As[wm + 16 * i + (lane & 15)][kk]);
+            b[i] = frag8(&Bs[wn + 16 * i + (lane & 15)][kk]);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
         __syncthreads();
     }
     // D layout: lane -> column (lane & 15), rows 4 * (lane >> 4) + r
@@ -102,8 +111,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, 
 // 64 x 64 block of 4 x 4 MFMA tiles), K in chunks of 32 staged as BF16 in LDS with the next
 // chunk's FP32 loads in flight during the current chunk's MFMAs.  Operands are read with
 // 16-B loads along their contiguous dimension: AK = A contiguous in k (else in m), BN = B
-// contiguous in n (else in k).  LDS keeps both tiles k-fastest, so an MFMA fragment (4
-// consecutive k) is one 8-B read.
+// contiguous in n (else in k).  LDS keeps both tiles k-fastest, so an MFMA fragment (8
+// consecutive k) is one 16-B read, and one 16 x 16 x 32 MFMA covers the chunk.
 constexpr int G2T = 128, G2K = 32, G2P = G2K + 8;   // tile, K chunk, padded LDS row
 template <bool AK, bool BN>
 __global__ __launch_bounds__(256) void k_gemm2_bf16(const float* __restrict__ A, int64_t lda,
@@ -159,15 +168,12 @@ __global__ __launch_bounds__(256) void k_gemm2_bf16(const float* __restrict__ A,
         }
     };
     auto store = [&]() {
-        if (AK) {
+        if (AK) {   // 4 consecutive k per float4: two packed BF16 pairs, one 8-B store
             const int r = tid >> 1, kk = (tid & 1) * 16;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                As[r][kk + 4 * q + 0] = f32_to_bf16(ra[q].x);
-                As[r][kk + 4 * q + 1] = f32_to_bf16(ra[q].y);
-                As[r][kk + 4 * q + 2] = f32_to_bf16(ra[q].z);
-                As[r][kk + 4 * q + 3] = f32_to_bf16(ra[q].w);
-            }
+            for (int q = 0; q < 4; ++q)
+                *reinterpret_cast<uint2*>(&As[r][kk + 4 * q]) =
+                    make_uint2(pack_bf16x2(ra[q].x, ra[q].y), pack_bf16x2(ra[q].z, ra[q].w));
         } else {
             const int kk = tid >> 3, mm = (tid & 7) * 16;
 #pragma unroll
@@ -187,15 +193,12 @@ __global__ __launch_bounds__(256) void k_gemm2_bf16(const float* __restrict__ A,
                 Bs[nn + 4 * q + 2][kk] = f32_to_bf16(rb[q].z);
                 Bs[nn + 4 * q + 3][kk] = f32_to_bf16(rb[q].w);
             }
-        } else {
+        } else {    // B contiguous in k: packed like A
             const int r = tid >> 1, kk = (tid & 1) * 16;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                Bs[r][kk + 4 * q + 0] = f32_to_bf16(rb[q].x);
-                Bs[r][kk + 4 * q + 1] = f32_to_bf16(rb[q].y);
-                Bs[r][kk + 4 * q + 2] = f32_to_bf16(rb[q].z);
-                Bs[r][kk + 4 * q + 3] = f32_to_bf16(rb[q].w);
-            }
+            for (int q = 0; q < 4; ++q)
+                *reinterpret_cast<uint2*>(&Bs[r][kk + 4 * q]) =
+                    make_uint2(pack_bf16x2(rb[q].x, rb[q].y), pack_bf16x2(rb[q].z, rb[q].w));
         }
     };
     f32x4_t acc[4][4];
@@ -203,26 +206,23 @@ __global__ __launch_bounds__(256) void k_gemm2_bf16(const float* __restrict__ A,
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    const int kq = 4 * (lane >> 4);
+    const int kq = 8 * (lane >> 4);
     load(0);
     for (int k0 = 0; k0 < K; k0 += G2K) {
         __syncthreads();   // the previous chunk's MFMAs are done with the tiles
         store();
         __syncthreads();
         if (k0 + G2K < K) load(k0 + G2K);
+        bf16x8_t a[4], b[4];
 #pragma unroll
-        for (int ks = 0; ks < G2K; ks += 16) {
-            bf16x4_t a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = *reinterpret_cast<const bf16x4_t*>(&As[wm + 16 * i + (lane & 15)][ks + kq]);
-                b[i] = *reinterpret_cast<const bf16x4_t*>(&Bs[wn + 16 * i + (lane & 15)][ks + kq]);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < 4; ++i) {
+            a[i] = frag8(&As[wm + 16 * i + (lane & 15)][kq]);
+            b[i] = frag8(&Bs[wn + 16 * i + (lane & 15)][kq]);
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
     }
     // D layout: lane -> column (lane & 15), rows 4 * (lane >> 4) + r
 #pragma unroll
@@ -480,7 +480,7 @@ hipError_t launch_out_complex(const float* O, void* x, int64_t n, bool c128, hip
 // One launch evaluates the whole network for a tile of MI_R rows, with the same
 // operand rounding as the layered forward pass (BF16 operands, FP32 accumulation):
 //   layer 1 (nin <= 16, VALU): A1 = relu(bf16(X) bf16(W1) + b1), kept as BF16 in LDS;
-//   layer 2 (MFMA 16x16x16): Z2 = A1 bf16(W2) + b2 by column blocks of 64 (one 16-column
+//   layer 2 (MFMA 16x16x32): Z2 = A1 bf16(W2) + b2 by column blocks of 64 (one 16-column
 //            slice per wave), B fragments straight from a transposed BF16 copy of W2;
 //   layer 3 in the epilogue of each block: Y += bf16(relu(Z2)) bf16(W3), reduced over the
 //            slice's 16 lanes and kept per wave in LDS; the waves' sums are added in a
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(MI_NT) void k_mlp_infer(const float* __restrict__ X
     }
     __syncthreads();
     // ---- layers 2 and 3
-    const int kq = 4 * (lane >> 4);                  // this lane's k offset inside a 16-step
+    const int kq = 8 * (lane >> 4);                  // this lane's k offset inside a 32-step
     float y0[MI_R / 16][4], y1[MI_R / 16][4];        // layer-3 partials of this lane's rows
 #pragma unroll
     for (int i = 0; i < MI_R / 16; ++i)
@@ -561,27 +561,23 @@ __global__ __launch_bounds__(MI_NT) void k_mlp_infer(const float* __restrict__ X
         f32x4_t acc[MI_R / 16];
 #pragma unroll
         for (int i = 0; i < MI_R / 16; ++i) acc[i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-        // B fragments in groups of 8 sixteen-steps of K: the next group's 8 loads are in
+        // B fragments in groups of 4 thirty-two-steps of K: the next group's 4 loads are in
         // flight while the current group's MFMAs run (one L2 round trip per group)
-        constexpr int GRP = 8;
-        bf16x4_t cur[GRP], nxt[GRP];
+        constexpr int GRP = 4;
+        bf16x8_t cur[GRP], nxt[GRP];
 #pragma unroll
-        for (int k = 0; k < GRP; ++k) cur[k] = *reinterpret_cast<const bf16x4_t*>(bsrc + 16 * k);
+        for (int k = 0; k < GRP; ++k) cur[k] = frag8(bsrc + 32 * k);
 #pragma unroll 1
-        for (int k0 = 0; k0 < HID; k0 += 16 * GRP) {
-            if (k0 + 16 * GRP < HID) {
+        for (int k0 = 0; k0 < HID; k0 += 32 * GRP) {
+            if (k0 + 32 * GRP < HID) {
 #pragma unroll
-                for (int k = 0; k < GRP; ++k)
-                    nxt[k] = *reinterpret_cast<const bf16x4_t*>(bsrc + k0 + 16 * GRP + 16 * k);
+                for (int k = 0; k < GRP; ++k) nxt[k] = frag8(bsrc + k0 + 32 * GRP + 32 * k);
             }
 #pragma unroll
             for (int k = 0; k < GRP; ++k) {
 #pragma unroll
-                for (int i = 0; i < MI_R / 16; ++i) {
-                    const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(
-                        &A1[(16 * i + (lane & 15)) * LDA + k0 + 16 * k + kq]);
-                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, cur[k], acc[i], 0, 0, 0);
-                }
+                for (int i = 0; i < MI_R / 16; ++i)
+                    acc[i] = mfma32(frag8(&A1[(16 * i + (lane & 15)) * LDA + k0 + 32 * k + kq]), cur[k], acc[i]);
             }
 #pragma unroll
             for (int k = 0; k < GRP; ++k) cur[k] = nxt[k];
