@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # kernel hash to the recorded value.
 TRAFFIC = {
     ("k_cd_panel_la", "c128 16384x8192 tol 1e-11"): {
-        "sources": ['paper_1902_08653_amd/csrc/k_panel_la.hip', 'paper_1902_08653_amd/csrc/panel.hpp', 'paper_1902_08653_amd/csrc/common.hpp'], "sha256_16": "e1336a8830e329f7", "bytes": 143082596749.0},
+        "sources": ['paper_1902_08653_amd/csrc/k_panel_la.hip', 'paper_1902_08653_amd/csrc/la_common.hpp', 'paper_1902_08653_amd/csrc/panel.hpp', 'paper_1902_08653_amd/csrc/common.hpp'], "sha256_16": "e1336a8830e329f7", "bytes": 143082596749.0},
     ("k_cd_wg", "c64 batch 4096 tol 1e-06"): {
         "sources": ['paper_1902_08653_amd/csrc/k_wg.hip', 'paper_1902_08653_amd/csrc/common.hpp', 'paper_1902_08653_amd/csrc/wg.hpp'], "sha256_16": "0250e54ccc4fc8b0", "bytes": 713278845676.0},
     ("k_cd_sparse", "c128 16384x8192 0.01 tol 1e-11"): {
@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--eps", type=float, default=None, help="accuracy target vs the oracle")
     ap.add_argument("--lam", type=float, default=0.1)
+    ap.add_argument("--lookahead", default="one", choices=["one", "deep", "none"],
+                    help="dense panel engine schedule: one panel ahead, two panels ahead, or two-hop")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle check and CPU baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=0,
                     help="oracle sweeps for the CPU baseline (0 = a full solve)")
@@ -121,7 +123,8 @@ def main():
     y = torch.from_numpy(inst.y.astype(npdt)).to(dev)
     print("[bench] inputs ready in %.1fs" % (time.time() - t0), file=sys.stderr, flush=True)
 
-    plan = cdm.Plan(a.B, a.U, precision=prec, T_max=200, tol=tol, timing=True)
+    plan = cdm.Plan(a.B, a.U, precision=prec, T_max=200, tol=tol, timing=True,
+                    lookahead={"one": True, "deep": "deep", "none": False}[a.lookahead])
     stream = torch.cuda.current_stream()
     x = torch.empty(a.U, dtype=y.dtype, device=dev)
     info = torch.empty(32, dtype=torch.uint8, device=dev)
@@ -166,6 +169,8 @@ def main():
     desc = json.loads(plan.describe())
     sweep_kernel = "k_cd_panel_la" if desc.get("schedule") == "lookahead" else (
         "k_cd_panel" if desc.get("engine") == "panel" else "k_cd_wg")
+    if desc.get("lookahead_panels") == 2:
+        sweep_kernel = "k_cd_panel_deep"
     if prec in ("bf16", "fp8"):
         sweep_kernel = "outer refinement loop (k_mx_* FP64 passes + k_cd_panel_la inner sweeps)"
     sweep_ms = stage["sweeps"] / a.steps

@@ -82,6 +82,12 @@ typedef enum cdm_engine { CDM_ENGINE_AUTO = 0, CDM_ENGINE_WG = 1, CDM_ENGINE_PAN
                                per panel) instead of the look-ahead schedule, whose exchange of panel
                                K+1's partials overlaps the wait for panel K's update (same deltas in
                                exact arithmetic; kept for comparison) */
+#define CDM_F_DEEP_LOOKAHEAD 16 /* panel engine, complex128 with 64-column panels and at least three
+                               panels: look two panels ahead (partials of panel K+3 formed after
+                               panel K's update, with a distance-two correction at the reducers)
+                               instead of one (panel K+2); same deltas in exact arithmetic.  Slower
+                               than the default on the devices measured (each tile is read twice
+                               per sweep, and the exchange loads wait behind that stream) */
 
 typedef struct cdm_desc {
     int32_t problem;     /* cdm_problem */

@@ -27,6 +27,7 @@ F_RESIDUAL = 1
 F_TIMING = 2
 F_AUTOTUNE = 4
 F_NO_LOOKAHEAD = 8
+F_DEEP_LOOKAHEAD = 16
 
 INFO_ZERO_COLUMN, INFO_NONFINITE, INFO_NOT_CONVERGED, INFO_TIMEOUT = 1, 2, 4, 8
 
@@ -157,7 +158,11 @@ def _cdtype(precision):
 
 
 class Plan:
-    """A plan for single solves (``cdm_create`` / ``cdm_solve`` / ``cdm_destroy``)."""
+    """A plan for single solves (``cdm_create`` / ``cdm_solve`` / ``cdm_destroy``).
+
+    lookahead (dense panel engine): True, the look-ahead schedule (one panel ahead);
+    "deep", two panels ahead where it applies (CDM_F_DEEP_LOOKAHEAD); False, the two-hop
+    schedule (CDM_F_NO_LOOKAHEAD)."""
 
     def __init__(self, B, U, C_clusters=1, precision="c128", T_max=200, tol=0.0, engine="auto",
                  panel=0, residual=False, problem="uplink", layout="dense", nnz=0, timing=False,
@@ -173,7 +178,8 @@ class Plan:
                  engine=_ENGINE[engine], B=self.B, U=self.U, C=self.C, T_max=int(T_max),
                  tol=float(tol), nnz=int(nnz), panel=int(panel),
                  flags=(F_RESIDUAL if residual else 0) | (F_TIMING if timing else 0)
-                 | (0 if lookahead else F_NO_LOOKAHEAD),
+                 | (F_NO_LOOKAHEAD if lookahead is False else 0)
+                 | (F_DEEP_LOOKAHEAD if lookahead == "deep" else 0),
                  Bc=C.cast(bc, C.POINTER(C.c_int32)) if bc is not None else None)
         self.desc = d
         h = C.c_void_p()

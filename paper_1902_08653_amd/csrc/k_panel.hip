@@ -331,6 +331,7 @@ static hipError_t launch_panel_src(const PanelLaunch& L, const Src& src, hipStre
     a.x = (cv<T>*)L.x;
     a.M = (const cv<T>*)L.M;
     a.X = nullptr;
+    a.X2 = nullptr;
     a.part = (cv<T>*)L.part;
     a.gbuf = (cv<T>*)L.gbuf;
     a.ctr = L.ctr;
@@ -399,11 +400,11 @@ int panel_max_coresident(bool c128, int kp, int rpl) {
 // grid.x = npanels * nsub, grid.y = nsplit; 256 threads as a 16 x 16 grid, each
 // accumulating a 4 x 4 complex tile; rows stream through LDS 32 at a time.
 // ============================================================================
-// CROSS: the full block H_K^H H_{K-1 mod npanels} instead (nsub = (kp/64)^2 sub-blocks).
+// CROSS: the full block H_K^H H_{K-dist mod npanels} instead (nsub = (kp/64)^2 sub-blocks).
 template <typename T, class Src, bool CROSS = false>
 __global__ __launch_bounds__(256) void k_gram_partial(Src src, int64_t ld, int B, int U, int kp,
                                                       int nsub, int rows_per_split, cv<T>* __restrict__ gpart,
-                                                      int npanels) {
+                                                      int npanels, int dist = 1) {
     using V = cv<T>;
     __shared__ V As[32][64 + 1];
     __shared__ V Bs[32][64 + 1];
@@ -432,7 +433,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(Src src, int64_t ld, int B
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = czero<T>();
     const int colA0 = K * kp + bi * 64;
-    const int colB0 = (CROSS ? (K + npanels - 1) % npanels : K) * kp + bj * 64;
+    const int colB0 = (CROSS ? (K + npanels - dist % npanels) % npanels : K) * kp + bj * 64;
     // a diagonal sub-block multiplies a tile by itself: load it once
     const bool same = colA0 == colB0;
     V(*Bp)[64 + 1] = same ? As : Bs;
@@ -632,7 +633,8 @@ __global__ __launch_bounds__(256) void k_fold_mx(const double2* __restrict__ M, 
     }
 }
 
-template <typename T> static hipError_t launch_gram_cross_t(const GramLaunch& L, void* X, hipStream_t st) {
+template <typename T>
+static hipError_t launch_gram_cross_t(const GramLaunch& L, void* X, hipStream_t st, int dist = 1, bool fold = true) {
     const int nb = L.kp / 64;
     const int nsub = nb * nb;
     int rps = (L.B + L.nsplit - 1) / L.nsplit;
@@ -641,15 +643,15 @@ template <typename T> static hipError_t launch_gram_cross_t(const GramLaunch& L,
     if (L.src_kind == SRC_BF16) {
         if constexpr (sizeof(T) == 4)
             hipLaunchKernelGGL((k_gram_partial<T, SrcBF16, true>), grid, dim3(256), 0, st, SrcBF16{L.q_re16, L.q_im16},
-                               L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels);
+                               L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels, dist);
     } else if (L.src_kind == SRC_FP8) {
         if constexpr (sizeof(T) == 4)
             hipLaunchKernelGGL((k_gram_partial<T, SrcFP8, true>), grid, dim3(256), 0, st,
                                SrcFP8{L.q_re8, L.q_im8, L.q_scale}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart,
-                               L.npanels);
+                               L.npanels, dist);
     } else {
         hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>, true>), grid, dim3(256), 0, st, SrcC<T>{(const cv<T>*)L.H},
-                           L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels);
+                           L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels, dist);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -659,7 +661,7 @@ template <typename T> static hipError_t launch_gram_cross_t(const GramLaunch& L,
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if constexpr (sizeof(T) == 8) {
-        if (L.kp == 64) {   // the configuration whose look-ahead forms b locally
+        if (fold && L.kp == 64) {   // the configuration whose look-ahead forms b locally
             hipLaunchKernelGGL(k_fold_mx<64>, dim3(L.npanels), dim3(256), 0, st, (const double2*)L.M, (double2*)X);
             e = hipGetLastError();
         }
@@ -669,6 +671,10 @@ template <typename T> static hipError_t launch_gram_cross_t(const GramLaunch& L,
 
 hipError_t launch_gram_cross(const GramLaunch& L, void* X, hipStream_t st) {
     return L.c128 ? launch_gram_cross_t<double>(L, X, st) : launch_gram_cross_t<float>(L, X, st);
+}
+
+hipError_t launch_gram_cross2(const GramLaunch& L, void* X2, hipStream_t st) {
+    return L.c128 ? launch_gram_cross_t<double>(L, X2, st, 2, false) : launch_gram_cross_t<float>(L, X2, st, 2, false);
 }
 
 }  // namespace cdm

@@ -119,6 +119,7 @@ struct PanelLaunch {
     const void* M;       // [npanels][kp*(kp+1)/2] packed lower (D + L)^-1 per panel, column by column
     const void* X = nullptr;  // look-ahead: [npanels][kp][kp] X_K = H_K^H H_{K-1 mod npanels}, transposed
                               // (element (j, v) of X_K at (K, v, j))
+    const void* X2 = nullptr; // deeper look-ahead: H_K^H H_{K-2 mod npanels}, same layout
     void* part;          // [2][kp][P] partial dot products
     void* gbuf;          // [2][kp][2] reduced right-hand sides and old x
     uint32_t* ctr;       // [2] abort, [3] status word, [16..) arrival flags
@@ -135,6 +136,14 @@ int panel_max_coresident(bool c128, int kp, int rpl);
 // P >= kp; needs PanelLaunch::X.
 hipError_t launch_panel_la(const PanelLaunch& L, hipStream_t st);
 int panel_la_max_coresident(bool c128, int kp);
+// Deeper look-ahead (complex128, kp = 64, npanels >= 3): the partials of panel K+3 are
+// formed after panel K's update, so that their exchange has two panel steps to arrive;
+// needs PanelLaunch::X (as -M_K X_K) and X2.
+hipError_t launch_panel_deep(const PanelLaunch& L, hipStream_t st);
+// its exchange buffers hold DP_SLOTS sequences: part DP_SLOTS x kp x P and gbuf DP_SLOTS x
+// kp x 2 values of 24 B (three tagged 64-bit words per complex128 value)
+constexpr int DP_SLOTS = 4;
+int panel_deep_max_coresident();
 
 // Panel Gram blocks and the inverses of the Gauss-Seidel splitting matrices.
 struct GramLaunch {
@@ -161,6 +170,9 @@ hipError_t launch_gram(const GramLaunch& L, hipStream_t st);
 // and M is read).  For complex128 with 64-column panels X receives -M_K X_K
 // instead, the form the look-ahead schedule uses there.
 hipError_t launch_gram_cross(const GramLaunch& L, void* X, hipStream_t st);
+// Cross blocks at distance two, H_K^H H_{K-2 mod npanels} (transposed, never folded),
+// for the deeper look-ahead's reducer-side correction.
+hipError_t launch_gram_cross2(const GramLaunch& L, void* X2, hipStream_t st);
 
 // (D + L)^-1 from summed Gram blocks already in gpart (row-major, lower part).
 hipError_t launch_gram_invert(bool c128, void* gpart, int nsplit, int npanels, int kp, int U, double lambda, void* M,

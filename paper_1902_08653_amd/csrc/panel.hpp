@@ -102,6 +102,7 @@ template <typename T, class Src> struct PanelArgs {
     cv<T>* x;
     const cv<T>* M;
     const cv<T>* X;         // look-ahead schedule: cross blocks H_K^H H_{K-1}, row-major per panel
+    const cv<T>* X2;        // deeper look-ahead: cross blocks H_K^H H_{K-2}, same layout
     cv<T>* part;
     cv<T>* gbuf;
     uint32_t* ctr;

@@ -78,6 +78,8 @@ struct cdm_plan {
     // PANEL engine
     int kp = 128, rpl = 1, P = 1, npanels = 1, nsplit = 1;
     bool la = false;          // look-ahead schedule (k_cd_panel_la)
+    bool deep = false;        // its two-panel form (k_cd_panel_deep)
+    void* X2 = nullptr;       // the latter's cross blocks H_K^H H_{K-2}
     size_t part_bytes = 0, gbuf_bytes = 0;
     void* X = nullptr;        // its cross blocks H_K^H H_{K-1}
     uint64_t timeout_ticks = 0;
@@ -347,7 +349,15 @@ static hipError_t launch_sweep(cdm_plan* p, const PanelLaunch& L, hipStream_t st
     if (!p->la) return launch_panel(L, st);
     hipError_t e = launch_zero_u32((uint32_t*)p->part, (int)(p->part_bytes / 4), st);
     if (e == hipSuccess) e = launch_zero_u32((uint32_t*)p->gbuf, (int)(p->gbuf_bytes / 4), st);
-    if (e == hipSuccess) e = launch_panel_la(L, st);
+    if (e == hipSuccess) {
+        if (p->deep) {
+            PanelLaunch D = L;
+            D.X2 = p->X2;
+            e = launch_panel_deep(D, st);
+        } else {
+            e = launch_panel_la(L, st);
+        }
+    }
     return e;
 }
 
@@ -551,7 +561,7 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
     Arena ar;
     const size_t o_ctr = ar.take(kCtrWords * 4);
     size_t o_jobs = 0, o_r0 = 0, o_M = 0, o_gpart = 0, o_part = 0, o_gbuf = 0, o_e = 0, o_xloc = 0,
-           o_msum = 0, o_rpart = 0, o_X = 0;
+           o_msum = 0, o_rpart = 0, o_X = 0, o_X2 = 0;
     p->nchunk = std::max(1, std::min(64, (d.U + 127) / 128));
     if (engine == CDM_ENGINE_WG) {
         st = setup_wg(p, Bc, d.U, d.C, wg_nt_single(Bc, p->c128));
@@ -601,6 +611,9 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
             return CDM_ESHAPE;
         }
         p->npanels = (d.U + p->kp - 1) / p->kp;
+        // complex128 64-column panels, at least three of them: the look-ahead of two panels
+        p->deep = p->la && p->c128 && p->kp == 64 && p->npanels >= 3 && (d.flags & CDM_F_DEEP_LOOKAHEAD) &&
+                  p->P <= panel_deep_max_coresident();
         const int nb = p->kp / 64;
         const int nsub = nb * (nb + 1) / 2;
         p->nsplit = std::max(1, std::min(32, (1024 + p->npanels * nsub - 1) / (p->npanels * nsub)));
@@ -609,14 +622,17 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         o_r0 = ar.take(p->esz * d.B);
         o_M = ar.take(p->esz * kk);
         o_gpart = ar.take(p->esz * kk * std::max(2, p->nsplit));
-        // the look-ahead schedule exchanges tagged words: twice the bytes per value
-        p->part_bytes = (p->la ? 2 : 1) * p->esz * 2 * (size_t)p->kp * p->P;
-        p->gbuf_bytes = (p->la ? 2 : 1) * p->esz * 2 * (size_t)p->kp * 2;
+        // the look-ahead schedule exchanges tagged words: twice the bytes per value (two
+        // sequence slots); its two-panel form keeps DP_SLOTS slots
+        const size_t slots = p->deep ? DP_SLOTS : 2;
+        p->part_bytes = (p->la ? 2 : 1) * p->esz * slots * (size_t)p->kp * p->P;
+        p->gbuf_bytes = (p->la ? 2 : 1) * p->esz * slots * (size_t)p->kp * 2;
         o_part = ar.take(p->part_bytes);
         o_gbuf = ar.take(p->gbuf_bytes);
         o_e = ar.take(sizeof(double) * d.U);
         o_rpart = ar.take(16 * (size_t)p->nchunk * d.B);
         if (p->la) o_X = ar.take(p->esz * kk);
+        if (p->deep) o_X2 = ar.take(p->esz * kk);
     }
     size_t o_q1 = 0, o_q2 = 0, o_qs = 0, o_ca = 0, o_r64 = 0, o_g32 = 0, o_d32 = 0, o_r32 = 0, o_done = 0;
     if (mixed) {
@@ -680,6 +696,7 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         p->e = (double*)(b + o_e);
         p->rpart = b + o_rpart;
         if (p->la) p->X = b + o_X;
+        if (p->deep) p->X2 = b + o_X2;
     }
     if (mixed) {
         if (p->src_kind == SRC_BF16) {
@@ -710,10 +727,10 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
                  p->c128 ? "c128" : "c64", d.B, d.U, d.C, p->wg_nt, p->wg_rpt, p->wg_grid, p->wg_lds, p->ws_bytes);
     else
         snprintf(buf, sizeof(buf),
-                 "{\"engine\": \"panel\", \"schedule\": \"%s\", \"precision\": \"%s\", \"B\": %d, \"U\": %d, "
-                 "\"panel\": %d, \"rpl\": %d, \"workgroups\": %d, \"npanels\": %d, \"gram_splits\": %d, "
-                 "\"workspace\": %zu}",
-                 p->la ? "lookahead" : "two-hop",
+                 "{\"engine\": \"panel\", \"schedule\": \"%s\", \"lookahead_panels\": %d, \"precision\": \"%s\", "
+                 "\"B\": %d, \"U\": %d, \"panel\": %d, \"rpl\": %d, \"workgroups\": %d, \"npanels\": %d, "
+                 "\"gram_splits\": %d, \"workspace\": %zu}",
+                 p->la ? "lookahead" : "two-hop", p->deep ? 2 : (p->la ? 1 : 0),
                  mixed ? (p->src_kind == SRC_BF16 ? "mixed-bf16" : "mixed-fp8") : (p->c128 ? "c128" : "c64"), d.B, d.U,
                  p->kp, p->rpl, p->P, p->npanels, p->nsplit, p->ws_bytes);
     p->text = buf;
@@ -854,6 +871,7 @@ int32_t cdm_solve(cdm_plan* p, const void* H, int64_t ldh, const int32_t* rowptr
         G.lambda = lambda;
         HIP_TRY(launch_gram(G, st));
         if (p->la) HIP_TRY(launch_gram_cross(G, p->X, st));
+        if (p->deep) HIP_TRY(launch_gram_cross2(G, p->X2, st));
         ev_record(p, 1, st);
         InitLaunch I;
         I.c128 = p->c128;

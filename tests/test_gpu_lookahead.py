@@ -4,7 +4,9 @@ The look-ahead schedule forms panel K+1's partial products before panel K's upda
 and corrects them with the cross block H_{K+1}^H H_K; in exact arithmetic every
 delta equals the sequential sweep's.  Cases: ragged last panels, both precisions,
 warm start, tolerance mode, the mixed-precision inner solves, and agreement with the
-two-hop schedule (CDM_F_NO_LOOKAHEAD).  Bars as in test_gpu_parity: 1e-10 (c128),
+two-hop schedule (CDM_F_NO_LOOKAHEAD).  The two-panel form (CDM_F_DEEP_LOOKAHEAD:
+partials of panel K+3 after panel K, with the distance-two correction applied by the
+reducers) is held to the same bars.  Bars as in test_gpu_parity: 1e-10 (c128),
 1e-5 (c64, oracle on the FP32-rounded inputs), sweep counts exact at fixed T.
 """
 import numpy as np
@@ -33,6 +35,9 @@ def relerr(a, b):
 
 
 def solve(dev, H, y, prec, T, tol=0.0, lookahead=True, x0=None, lam=0.1):
+    """lookahead: True (one panel ahead), "deep" (two panels ahead where complex128 with
+    64-column panels has at least three panels, else one) or False (the two-hop
+    schedule)."""
     from paper_1902_08653_amd import cdm
     B, U = H.shape
     plan = cdm.Plan(B, U, precision=prec, T_max=T, tol=tol, engine="panel", lookahead=lookahead)
@@ -46,6 +51,10 @@ def solve(dev, H, y, prec, T, tol=0.0, lookahead=True, x0=None, lam=0.1):
     out = x.cpu().numpy().astype(np.complex128), cdm.parse_info(info)[0], desc
     plan.close()
     return out
+
+
+def deep(desc):
+    return '"lookahead_panels": 2' in desc
 
 
 def oracle_in(H, y, prec):
@@ -110,3 +119,51 @@ def test_lookahead_mixed_refinement(dev, orc, prec):
     ref = orc.local_cd(inst.H, inst.y, 0.1, 2000, tol=1e-14)
     assert rec["flags"] == 0
     assert relerr(x, ref["x"]) <= 1e-9
+
+
+# complex128, two panels ahead: three panels, a ragged fourth, many panels
+DEEP_CASES = [(4096, 192), (4096, 200), (4160, 1000), (8192, 515)]
+
+
+@pytest.mark.parametrize("B,U", DEEP_CASES)
+@pytest.mark.parametrize("T", [1, 2, 5])
+def test_two_panel_lookahead_matches_oracle(dev, orc, B, U, T):
+    inst = inputs.dense_uplink(B, U, 31 + U)
+    x, rec, desc = solve(dev, inst.H, inst.y, "c128", T, lookahead="deep")
+    assert deep(desc), desc
+    ref = orc.local_cd(inst.H, inst.y, 0.1, T)
+    assert rec["sweeps"] == T and rec["flags"] == 0
+    assert relerr(x, ref["x"]) <= 1e-10
+
+
+@pytest.mark.parametrize("B,U", [(4096, 200), (4096, 1000)])
+def test_two_panel_lookahead_equals_one_panel_and_two_hop(dev, B, U):
+    inst = inputs.dense_uplink(B, U, 6)
+    xd, rd, dd = solve(dev, inst.H, inst.y, "c128", 4, lookahead="deep")
+    xs, rs, ds = solve(dev, inst.H, inst.y, "c128", 4)
+    xt, rt, dt = solve(dev, inst.H, inst.y, "c128", 4, lookahead=False)
+    assert deep(dd) and '"lookahead_panels": 1' in ds and '"schedule": "two-hop"' in dt
+    assert rd["sweeps"] == rs["sweeps"] == rt["sweeps"] == 4
+    assert relerr(xd, xs) <= 1e-10 and relerr(xd, xt) <= 1e-10
+
+
+def test_two_panel_lookahead_warm_start_and_tolerance(dev, orc):
+    inst = inputs.dense_uplink(4096, 600, 4)
+    x0 = np.random.default_rng(2).standard_normal(600) * 0.3 + 0j
+    x, rec, desc = solve(dev, inst.H, inst.y, "c128", 3, x0=x0, lookahead="deep")
+    assert deep(desc)
+    ref = orc.local_cd(inst.H, inst.y, 0.1, 3, x0=x0)
+    assert relerr(x, ref["x"]) <= 1e-10
+    x, rec, _ = solve(dev, inst.H, inst.y, "c128", 300, tol=1e-10, lookahead="deep")
+    ref = orc.local_cd(inst.H, inst.y, 0.1, 300, tol=1e-10)
+    assert rec["flags"] == 0 and abs(int(rec["sweeps"]) - int(ref["sweeps"])) <= 1
+    at = orc.local_cd(inst.H, inst.y, 0.1, int(rec["sweeps"]))
+    assert relerr(x, at["x"]) <= 1e-10
+
+
+def test_one_or_two_panels_stay_shallow(dev, orc):
+    for U in (64, 128):
+        inst = inputs.dense_uplink(4096, U, U)
+        x, rec, desc = solve(dev, inst.H, inst.y, "c128", 3, lookahead="deep")
+        assert '"lookahead_panels": 1' in desc, desc
+        assert relerr(x, orc.local_cd(inst.H, inst.y, 0.1, 3)["x"]) <= 1e-10
