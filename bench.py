@@ -74,7 +74,8 @@ def parse():
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle check and CPU baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=0,
                     help="oracle sweeps for the CPU baseline (0 = a full solve)")
-    ap.add_argument("--copy-probe", action="store_true", help="also run the library copy kernel")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="accepted for old command lines: the read and copy probes always run")
     ap.add_argument("--workload", default="dense", choices=["dense", "batched", "warm", "paper", "sparse"],
                     help="dense: one 16384x8192 instance (default); batched: 4096 uneven instances; "
                          "warm: learned warm start against a cold start on 4096 held-out uneven instances; "
@@ -177,7 +178,7 @@ def main():
     mean_sweeps = float(np.mean(sweeps))
     achieved = mean_sweeps * h_bytes / (sweep_ms * 1e-3) / 1e9
 
-    copy_gbs = _copy_probe(cdm, dev, stream) if a.copy_probe else None
+    probes = _hbm_probes(cdm, dev, stream)
 
     oracle_err = None
     cpu = None
@@ -225,7 +226,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(sweep_kernel, "%s %dx%d tol %g" % (prec, a.B, a.U, tol)),
                      "kernel": sweep_kernel, "algorithmic_bytes_per_launch": mean_sweeps * h_bytes,
-                     "avg_launch_ms": sweep_ms},
+                     "avg_launch_ms": sweep_ms, **_ceiling(achieved, probes)},
         "cpu_baseline": cpu,
         "accuracy": {"sweeps": sweeps, "rel_step": float(rec["rel_step"]), "flags": int(rec["flags"]),
                      "fp64_normal_residual": resid, "rel_err_vs_oracle": oracle_err,
@@ -233,8 +234,7 @@ def main():
         "stages_ms_per_solve": {k: v / a.steps for k, v in stage.items()},
         "wall_s_timed": wall,
     }
-    if copy_gbs is not None:
-        out["copy_probe_gbs"] = copy_gbs
+    out["copy_probe_gbs"] = probes["copy_gbs"]
     out.setdefault("host", _host_info())
     print(json.dumps(out))
     plan.close()
@@ -284,6 +284,7 @@ def bench_batched(a):
         kernel = "k_cd_wg"
         acc = {"sweeps_mean": float(sweeps.mean()), "sweeps_max": int(sweeps.max())}
     achieved = alg_bytes / (ms * 1e-3) / 1e9
+    probes = _hbm_probes(cdm, dev, torch.cuda.current_stream())
     print("[bench] %.3f ms per batch solve, %s, flags %d" % (ms, acc, int(np.bitwise_or.reduce(rec["flags"]))),
           file=sys.stderr, flush=True)
     cpu = None
@@ -304,7 +305,8 @@ def bench_batched(a):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(kernel, "%s batch %d tol %g" % (prec, a.batch, tol)),
-                     "kernel": kernel, "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": ms},
+                     "kernel": kernel, "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": ms,
+                     **_ceiling(achieved, probes)},
         "cpu_baseline": cpu,
         "accuracy": dict(acc, flags_or=int(np.bitwise_or.reduce(rec["flags"])),
                          instances_checked=len(errs),
@@ -313,8 +315,7 @@ def bench_batched(a):
                          within_eps=bool(max(errs) <= eps) if errs else None),
         "host": _host_info(),
     }
-    if a.copy_probe:
-        out["copy_probe_gbs"] = _copy_probe(cdm, dev, torch.cuda.current_stream())
+    out["copy_probe_gbs"] = probes["copy_gbs"]
     out.setdefault("host", _host_info())
     print(json.dumps(out))
     plan.close()
@@ -480,6 +481,7 @@ def bench_sparse(a):
     # scatter the panel's update back into r
     alg_bytes = mean_sweeps * 2.0 * nnz * (esz + 4)
     achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
+    probes = _hbm_probes(cdm, dev, stream)
     print("[bench] %.3f ms per solve (sweep kernel %.3f ms), sweeps %s" % (ms_per, sweep_ms, sweeps),
           file=sys.stderr, flush=True)
     cpu = None
@@ -526,14 +528,14 @@ def bench_sparse(a):
                      "traffic": measured_traffic("k_cd_sparse", "%s %dx%d %g tol %g" % (prec, a.B, a.U, density, tol)),
                      "kernel": "k_cd_sparse",
                      "limiter": "per-panel exchange latency across the slice workgroups, not HBM",
-                     "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": sweep_ms},
+                     "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": sweep_ms,
+                     **_ceiling(achieved, probes)},
         "cpu_baseline": cpu,
         "accuracy": {"sweeps": sweeps, "rel_step": float(rec["rel_step"]), "flags": int(rec["flags"]),
                      "rel_err_vs_oracle": err, "within_eps": (err is not None and err <= eps)},
         "stages_ms_per_solve": {k: v / a.steps for k, v in stage.items()},
     }
-    if a.copy_probe:
-        out["copy_probe_gbs"] = _copy_probe(cdm, dev, stream)
+    out["copy_probe_gbs"] = probes["copy_gbs"]
     out.setdefault("host", _host_info())
     print(json.dumps(out))
     plan.close()
@@ -641,23 +643,40 @@ def bench_paper(a):
     print(json.dumps(out))
 
 
-def _copy_probe(cdm, dev, stream):
-    """GB/s of the library's plain copy kernel over 1 GiB (read + write); its HBM
-    counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
+def _hbm_probes(cdm, dev, stream):
+    """Achievable HBM rates on this device with the library's own kernels, each over a
+    1 GiB buffer, 5 timed launches after 2 untimed ones: a read-only stream (the ceiling
+    the read-dominated sweep kernels are compared with) and a plain copy (read + write
+    counted; its HBM counter readings calibrate FETCH_SIZE / WRITE_SIZE).  GB/s."""
     import torch
     nb = 1 << 30
     src = torch.empty(nb // 16, dtype=torch.complex128, device=dev)
     dst = torch.empty_like(src)
-    for _ in range(2):
-        cdm.stream_copy(src, dst)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(5):
-        cdm.stream_copy(src, dst)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return 2 * nb * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    acc = torch.empty((cdm.STREAM_READ_SLOTS, 4), dtype=torch.int32, device=dev)
+
+    def rate(fn, moved):
+        for _ in range(2):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return moved * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    out = {"read_gbs": rate(lambda: cdm.stream_read(src, acc), nb),
+           "copy_gbs": rate(lambda: cdm.stream_copy(src, dst), 2 * nb)}
+    del src, dst, acc
+    return out
+
+
+def _ceiling(achieved, probes):
+    """The roofline's measured-ceiling fields: the probes and the fraction of the
+    read-only rate that the kernel reaches."""
+    return {"measured_read_gbs": probes["read_gbs"], "measured_copy_gbs": probes["copy_gbs"],
+            "frac_of_measured_read": achieved / probes["read_gbs"]}
 
 
 def _graph(fn):

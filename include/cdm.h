@@ -352,6 +352,16 @@ int32_t cdm_plan_timings(const cdm_plan* plan, double* out_ms, int32_t n, int32_
  * src, dst: device, 16-byte aligned, non-overlapping. */
 int32_t cdm_stream_copy(const void* src, void* dst, int64_t bytes, void* stream);
 
+/* Measurement utility (not part of the method): a read-only stream over `bytes` bytes (a
+ * multiple of 16) with the library's own kernel, the achievable HBM read rate that the
+ * read-dominated sweep kernels are compared with.  Every 16-byte word of src is read
+ * once; out receives CDM_STREAM_READ_SLOTS partial XORs of 16 bytes each (every slot is
+ * written), whose XOR is the XOR of all words of src.
+ * src: device, 16-byte aligned.  out: device, CDM_STREAM_READ_SLOTS * 16 bytes,
+ * caller-owned.  Errors: CDM_EINVAL (NULL, bytes < 0 or not a multiple of 16), CDM_EHIP. */
+#define CDM_STREAM_READ_SLOTS 8192
+int32_t cdm_stream_read(const void* src, int64_t bytes, void* out, void* stream);
+
 /* ---- solve without allocation -------------------------------------------------------
  * For callers that cannot allocate device memory: code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc.  The same solve as cdm_create +

@@ -56,7 +56,7 @@ assert INFO_DTYPE.itemsize == 32
 
 EXPORTS = ["cdm_version", "cdm_status_string", "cdm_last_error", "cdm_create", "cdm_solve",
            "cdm_create_batched", "cdm_batched_offsets", "cdm_solve_batched", "cdm_residual",
-           "cdm_plan_describe", "cdm_plan_timings", "cdm_stream_copy", "cdm_csr_transpose", "cdm_quantized_copy", "cdm_batched_features", "cdm_mlp_create",
+           "cdm_plan_describe", "cdm_plan_timings", "cdm_stream_copy", "cdm_stream_read", "cdm_csr_transpose", "cdm_quantized_copy", "cdm_batched_features", "cdm_mlp_create",
            "cdm_mlp_param_count", "cdm_mlp_set_weights", "cdm_mlp_get_weights", "cdm_mlp_forward",
            "cdm_mlp_gradients", "cdm_mlp_train_step", "cdm_mlp_predict", "cdm_mlp_destroy", "cdm_destroy",
            "cdm_detect_batch", "cdm_precode_batch", "cdm_solve_noalloc"]
@@ -97,6 +97,8 @@ def lib():
         L.cdm_plan_timings.restype = i32
         L.cdm_stream_copy.argtypes = [P, P, i64, P]
         L.cdm_stream_copy.restype = i32
+        L.cdm_stream_read.argtypes = [P, i64, P, P]
+        L.cdm_stream_read.restype = i32
         L.cdm_csr_transpose.argtypes = [P, P, P, P, P, P, P, P]
         L.cdm_csr_transpose.restype = i32
         L.cdm_quantized_copy.argtypes = [P, P, i64, P, P, P, P]
@@ -333,6 +335,17 @@ def stream_copy(src, dst, stream=None):
     nbytes = src.numel() * src.element_size()
     assert dst.numel() * dst.element_size() == nbytes
     _check(lib().cdm_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)), "cdm_stream_copy")
+
+
+STREAM_READ_SLOTS = 8192
+
+
+def stream_read(src, out, stream=None):
+    """Library read-only stream (measurement utility): out (STREAM_READ_SLOTS x 16 bytes
+    on the device) receives partial XORs whose XOR is that of every 16-byte word of src."""
+    nbytes = src.numel() * src.element_size()
+    assert out.numel() * out.element_size() == 16 * STREAM_READ_SLOTS
+    _check(lib().cdm_stream_read(_ptr(src), int(nbytes), _ptr(out), _stream(stream)), "cdm_stream_read")
 
 
 class BatchedPlan:

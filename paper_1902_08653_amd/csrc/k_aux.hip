@@ -294,6 +294,54 @@ __global__ void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
+// Read-only stream: every 16-byte word of src is loaded once (four independent loads in
+// flight per thread); workgroup b stores the XOR of the words it read in slot b of out, so
+// that no load can be dropped and no two workgroups write the same place.
+__global__ __launch_bounds__(256) void k_stream_read(const uint4* __restrict__ src, int64_t n, uint4* out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const uint4 v0 = src[i], v1 = src[i + stride], v2 = src[i + 2 * stride], v3 = src[i + 3 * stride];
+        acc.x ^= v0.x ^ v1.x ^ v2.x ^ v3.x;
+        acc.y ^= v0.y ^ v1.y ^ v2.y ^ v3.y;
+        acc.z ^= v0.z ^ v1.z ^ v2.z ^ v3.z;
+        acc.w ^= v0.w ^ v1.w ^ v2.w ^ v3.w;
+    }
+    for (; i < n; i += stride) {
+        const uint4 v = src[i];
+        acc.x ^= v.x;
+        acc.y ^= v.y;
+        acc.z ^= v.z;
+        acc.w ^= v.w;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        acc.x ^= __shfl_xor(acc.x, o);
+        acc.y ^= __shfl_xor(acc.y, o);
+        acc.z ^= __shfl_xor(acc.z, o);
+        acc.w ^= __shfl_xor(acc.w, o);
+    }
+    __shared__ uint4 wsum[4];
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint4 s = wsum[0];
+        for (int k = 1; k < 4; ++k) {
+            s.x ^= wsum[k].x;
+            s.y ^= wsum[k].y;
+            s.z ^= wsum[k].z;
+            s.w ^= wsum[k].w;
+        }
+        out[blockIdx.x] = s;
+    }
+}
+// a fixed grid of CDM_STREAM_READ_SLOTS workgroups: every slot is written, also where
+// src is too short to give each workgroup a word (their slots get 0)
+hipError_t launch_stream_read(const void* src, int64_t bytes, void* out, hipStream_t st) {
+    const int64_t n = bytes / 16;
+    hipLaunchKernelGGL(k_stream_read, dim3(CDM_STREAM_READ_SLOTS), dim3(256), 0, st, (const uint4*)src, n, (uint4*)out);
+    return hipGetLastError();
+}
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t st) {
     const int64_t n = bytes / 16;
     if (n == 0) return hipSuccess;

@@ -298,6 +298,7 @@ hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t st);
 hipError_t launch_finalize(const void* x, int U, bool c128, const uint32_t* status, cdm_info* info,
                            hipStream_t st);
 hipError_t launch_copy_resid(const double* src, cdm_info* info, int count, hipStream_t st);
+hipError_t launch_stream_read(const void* src, int64_t bytes, void* out, hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
 // Fill n reals (double if c128 else float) with scale * (u - 1/2), u a hash of (seed, i) in
 // [0, 1): stand-in values for timing runs.

@@ -1378,6 +1378,12 @@ int32_t cdm_stream_copy(const void* src, void* dst, int64_t bytes, void* stream)
     return CDM_OK;
 }
 
+int32_t cdm_stream_read(const void* src, int64_t bytes, void* out, void* stream) {
+    if (!src || !out || bytes < 0 || (bytes & 15)) return CDM_EINVAL;
+    HIP_TRY(launch_stream_read(src, bytes, out, (hipStream_t)stream));
+    return CDM_OK;
+}
+
 int32_t cdm_destroy(cdm_plan* p) {
     if (!p) return CDM_OK;
     for (int i = 0; i < 5; ++i)

@@ -110,6 +110,10 @@ def test_null_arguments(lib):
     m = np.array([4], np.int32)
     assert lib.cdm_create_batched(C.byref(_desc()), 0, m.ctypes.data, m.ctypes.data,
                                   C.byref(C.c_void_p())) == -1
+    # measurement utilities: NULL pointers and sizes that are not whole 16-byte words
+    assert lib.cdm_stream_read(None, 16, None, None) == -1
+    assert lib.cdm_stream_read(C.c_void_p(16), 24, C.c_void_p(16), None) == -1
+    assert lib.cdm_stream_copy(C.c_void_p(16), C.c_void_p(32), -16, None) == -1
 
 
 @pytest.mark.parametrize("kw,status", [
