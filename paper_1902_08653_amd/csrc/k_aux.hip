@@ -294,22 +294,34 @@ __global__ void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
-// Read-only stream: every 16-byte word of src is loaded once (four independent loads in
-// flight per thread); workgroup b stores the XOR of the words it read in slot b of out, so
-// that no load can be dropped and no two workgroups write the same place.
+// Read-only stream: every 16-byte word of src is loaded once, streaming (non-temporal),
+// eight independent loads in flight per thread; workgroup b stores the XOR of the words it
+// read in slot b of out, so that no load can be dropped and no two workgroups write the
+// same place.
+typedef uint32_t u4v_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld_stream(const uint4* p) {
+    const u4v_t v = __builtin_nontemporal_load(reinterpret_cast<const u4v_t*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
 __global__ __launch_bounds__(256) void k_stream_read(const uint4* __restrict__ src, int64_t n, uint4* out) {
+    constexpr int NL = 8;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     uint4 acc = make_uint4(0u, 0u, 0u, 0u);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        const uint4 v0 = src[i], v1 = src[i + stride], v2 = src[i + 2 * stride], v3 = src[i + 3 * stride];
-        acc.x ^= v0.x ^ v1.x ^ v2.x ^ v3.x;
-        acc.y ^= v0.y ^ v1.y ^ v2.y ^ v3.y;
-        acc.z ^= v0.z ^ v1.z ^ v2.z ^ v3.z;
-        acc.w ^= v0.w ^ v1.w ^ v2.w ^ v3.w;
+    for (; i + (NL - 1) * stride < n; i += NL * stride) {
+        uint4 v[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) v[k] = ld_stream(src + i + k * stride);
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            acc.x ^= v[k].x;
+            acc.y ^= v[k].y;
+            acc.z ^= v[k].z;
+            acc.w ^= v[k].w;
+        }
     }
     for (; i < n; i += stride) {
-        const uint4 v = src[i];
+        const uint4 v = ld_stream(src + i);
         acc.x ^= v.x;
         acc.y ^= v.y;
         acc.z ^= v.z;

@@ -462,9 +462,11 @@ static int32_t solve_mixed(cdm_plan* p, const void* H, int64_t ldh, const void* 
     }
     HIP_TRY(launch_mixed_finish(M, st));
     ev_record(p, 3, st);
-    int32_t s2 = run_resid(p, H, ldh, y, lambda, x, p->res_out, st);
-    if (s2) return s2;
-    HIP_TRY(launch_copy_resid(p->res_out, inf, 1, st));
+    if (d.flags & CDM_F_RESIDUAL) {   // as for the plain precisions: only when asked
+        int32_t s2 = run_resid(p, H, ldh, y, lambda, x, p->res_out, st);
+        if (s2) return s2;
+        HIP_TRY(launch_copy_resid(p->res_out, inf, 1, st));
+    }
     ev_record(p, 4, st);
     return CDM_OK;
 }

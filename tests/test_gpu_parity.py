@@ -296,7 +296,7 @@ def test_mixed_refinement_reaches_fp64_oracle(dev, orc, kind):
     from paper_1902_08653_amd import cdm
     B, U = 2048, 1000
     inst = inputs.dense_uplink(B, U, seed=21)
-    plan = cdm.Plan(B, U, precision=kind, T_max=40, tol=1e-12)
+    plan = cdm.Plan(B, U, precision=kind, T_max=40, tol=1e-12, residual=True)
     Hd, yd = to_dev(inst.H, inst.y, "c128", dev)
     x, info = plan.solve(Hd, yd, N0=0.1)
     torch.cuda.synchronize()
