@@ -5,8 +5,9 @@ Workload (default): one dense uplink instance, B = 16384 antennas x U = 8192 use
 complex128, H ~ CN(0, 1/16384), y ~ CN(0, 1), seed 1, lambda = N0/Ex = 0.1;
 iterate until the relative step sqrt(sum |delta_u|^2)/||x|| <= 1e-11 (cap 200
 sweeps), which puts the result within 1e-10 of the FP64 oracle's.  The mixed
-precisions (--precision bf16 | fp8) cap the refinement at 25 outer steps of 8
-low-precision sweeps each: the same 200-sweep cap, counted in sweeps over the copy.  One step = one
+precisions (--precision bf16 | fp8) cap the refinement at ceil(200 / k) outer steps of
+k low-precision sweeps each (k = 12 for BF16, 5 for FP8): the same 200-sweep cap,
+counted in sweeps over the copy.  One step = one
 complete solve through the C ABI: column energies and panel Gram inverses, init,
 all sweeps, finalisation.  Inputs are resident in HBM before timing starts.
 
@@ -126,8 +127,10 @@ def main():
     y = torch.from_numpy(inst.y.astype(npdt)).to(dev)
     print("[bench] inputs ready in %.1fs" % (time.time() - t0), file=sys.stderr, flush=True)
 
-    # the mixed precisions' T_max counts outer refinement steps (8 inner sweeps each)
-    cap = 25 if prec in ("bf16", "fp8") else 200
+    # the mixed precisions' T_max counts outer refinement steps of k inner sweeps each:
+    # the same cap of 200 sweeps, counted over the low-precision copy
+    inner = cdm.MIXED_INNER_SWEEPS.get(prec, 0)
+    cap = -(-200 // inner) if inner else 200
     plan = cdm.Plan(a.B, a.U, precision=prec, T_max=cap, tol=tol, timing=True,
                     lookahead={"one": True, "deep": "deep", "none": False}[a.lookahead])
     stream = torch.cuda.current_stream()
@@ -170,7 +173,7 @@ def main():
         # one outer step reads the complex128 H twice (residual, gradient) and runs the
         # inner sweeps over the 4-byte (BF16) or 2-byte (FP8) planar copy
         qb = 4.0 if prec == "bf16" else 2.0
-        h_bytes = float(a.B) * a.U * (2 * 16 + 8 * qb)
+        h_bytes = float(a.B) * a.U * (2 * 16 + inner * qb)
     desc = json.loads(plan.describe())
     sweep_kernel = "k_cd_panel_la" if desc.get("schedule") == "lookahead" else (
         "k_cd_panel" if desc.get("engine") == "panel" else "k_cd_wg")
@@ -224,7 +227,7 @@ def main():
         "config": {"workload": "dense uplink L-MMSE CD (Algorithm 1), B=%d antennas x U=%d users, "
                                "%s, CN(0,1/B) channel, seed %d, lambda=%g, rel-step tol %g, %s"
                                % (a.B, a.U, prec, a.seed, a.lam, tol,
-                                  "cap 25 outer steps x 8 inner sweeps" if cap == 25 else "cap 200"),
+                                  "cap %d outer steps x %d inner sweeps" % (cap, inner) if inner else "cap 200"),
                    "B": a.B, "U": a.U, "precision": prec, "tol": tol, "eps": eps,
                    "engine": json.loads(plan.describe())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

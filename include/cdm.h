@@ -178,9 +178,19 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan);
  * Mixed precisions run the outer FP64 refinement loop: residual r = y - H x in
  * FP64, inner CD sweeps on the correction problem from the low-precision copy of
  * H, x += d, until ||d|| <= tol ||x|| (tol > 0 required) or T_max outer steps.
+ * Each outer step runs CDM_MIXED_INNER_SWEEPS_BF16 (BF16 copy) or
+ * CDM_MIXED_INNER_SWEEPS_FP8 (FP8 copy) inner sweeps; the solve enqueues all T_max
+ * outer steps, and those after convergence return at once, so keep T_max near the
+ * expected count (a cap of S sweeps over the copy is T_max = ceil(S / inner sweeps)).
  * Errors: CDM_EINVAL (NULL pointer, lambda < 0, lambda_c given for a downlink or
  * C = 1 plan), CDM_ESHAPE (ldh < B), CDM_EINFEASIBLE (lambda = 0 and some B_c < U),
  * CDM_EHIP. */
+/* Inner sweeps per outer refinement step of a single mixed-precision solve: set where
+ * one more inner sweep stops paying for itself against one more outer step (two FP64
+ * passes over H); the FP8 copy's rounding bounds the gain of an outer step sooner. */
+#define CDM_MIXED_INNER_SWEEPS_BF16 12
+#define CDM_MIXED_INNER_SWEEPS_FP8 5
+
 int32_t cdm_solve(cdm_plan* plan, const void* H, int64_t ldh, const int32_t* rowptr,
                   const int32_t* colidx, const void* rhs, double N0, double Ex, double rho,
                   const void* x0, const double* lambda_c, void* x, void* info, void* stream);

@@ -338,6 +338,9 @@ def stream_copy(src, dst, stream=None):
 
 
 STREAM_READ_SLOTS = 8192
+# inner sweeps per outer refinement step of a single mixed-precision solve
+# (CDM_MIXED_INNER_SWEEPS_BF16 / _FP8)
+MIXED_INNER_SWEEPS = {"bf16": 12, "fp8": 5}
 
 
 def stream_read(src, out, stream=None):

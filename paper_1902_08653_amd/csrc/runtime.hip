@@ -341,7 +341,10 @@ static int32_t run_sparse(cdm_plan* p, const void* val, const int32_t* rowptr, c
     return CDM_OK;
 }
 
-static constexpr int kInnerSweeps = 8;   // low-precision CD sweeps per outer refinement step
+// low-precision CD sweeps per outer refinement step of a single mixed solve
+static int inner_sweeps_for(int src_kind) {
+    return src_kind == SRC_FP8 ? CDM_MIXED_INNER_SWEEPS_FP8 : CDM_MIXED_INNER_SWEEPS_BF16;
+}
 
 // The panel sweep launch.  The look-ahead schedule's exchange buffers carry sequence
 // tags and start each launch cleared (a fill kernel, so the solve stays capturable).
@@ -396,7 +399,7 @@ static int32_t solve_mixed(cdm_plan* p, const void* H, int64_t ldh, const void* 
     M.info = inf;
     M.lambda = lambda;
     M.tol = d.tol;
-    M.inner_sweeps = kInnerSweeps;
+    M.inner_sweeps = inner_sweeps_for(p->src_kind);
     ev_record(p, 0, st);
     HIP_TRY(launch_zero_u32(p->ctr, kCtrWords, st));
     HIP_TRY(launch_quantize(M, st));
@@ -451,7 +454,7 @@ static int32_t solve_mixed(cdm_plan* p, const void* H, int64_t ldh, const void* 
     L.gbuf = p->gbuf;
     L.ctr = p->ctr;
     L.lambda = lambda;
-    L.T_max = kInnerSweeps;
+    L.T_max = inner_sweeps_for(p->src_kind);
     L.tol = 0.0;
     L.timeout_ticks = p->timeout_ticks;
     L.info = (cdm_info*)((char*)p->mx_done + 32);   // the inner launches' own record (unused)
@@ -731,10 +734,10 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         snprintf(buf, sizeof(buf),
                  "{\"engine\": \"panel\", \"schedule\": \"%s\", \"lookahead_panels\": %d, \"precision\": \"%s\", "
                  "\"B\": %d, \"U\": %d, \"panel\": %d, \"rpl\": %d, \"workgroups\": %d, \"npanels\": %d, "
-                 "\"gram_splits\": %d, \"workspace\": %zu}",
+                 "\"gram_splits\": %d, \"inner_sweeps\": %d, \"workspace\": %zu}",
                  p->la ? "lookahead" : "two-hop", p->deep ? 2 : (p->la ? 1 : 0),
                  mixed ? (p->src_kind == SRC_BF16 ? "mixed-bf16" : "mixed-fp8") : (p->c128 ? "c128" : "c64"), d.B, d.U,
-                 p->kp, p->rpl, p->P, p->npanels, p->nsplit, p->ws_bytes);
+                 p->kp, p->rpl, p->P, p->npanels, p->nsplit, mixed ? inner_sweeps_for(p->src_kind) : 0, p->ws_bytes);
     p->text = buf;
     st = setup_timing(p);
     if (st) {

@@ -5,6 +5,8 @@ output vector) at the same sweep count; complex64 runs agree to 1e-5 relative wi
 the oracle run on the same FP32-rounded inputs; integer outputs (sweep counts,
 flags) are exact.
 """
+import json
+
 import numpy as np
 import pytest
 
@@ -307,7 +309,9 @@ def test_mixed_refinement_reaches_fp64_oracle(dev, orc, kind):
     assert rec["flags"] == 0 and rec["rel_step"] <= 1e-12
     assert err <= 1e-10
     assert rec["resid"] <= 1e-11
-    assert 1 <= rec["sweeps"] <= 40 and rec["reserved"] == 8 * rec["sweeps"]
+    k = json.loads(plan.describe())["inner_sweeps"]
+    assert k == cdm.MIXED_INNER_SWEEPS[kind]
+    assert 1 <= rec["sweeps"] <= 40 and rec["reserved"] == k * rec["sweeps"]
 
 
 @pytest.mark.parametrize("kind", ["bf16", "fp8"])
