@@ -1,0 +1,246 @@
+// k_gram_lp.hip -- Gram blocks of the low-precision copies of H (BF16, FP8-e4m3) on
+// gfx950's matrix cores.
+//
+// The mixed-precision refinement runs its inner sweeps on a BF16 or FP8 copy of H, so
+// the panel inverses M_K = (D + L)^-1 and the look-ahead cross blocks come from the
+// Gram blocks of that copy (the inner problem's own matrix, Alg. 1 applied to the
+// correction).  A Gram block is a dense contraction over the B rows:
+//
+//     G_uv = sum_rows conj(A_u) B_v
+//          = (Ar^T Br + Ai^T Bi)_uv + i (Ar^T Bi - Ai^T Br)_uv,
+//
+// four real products of BF16 or FP8 operands with FP32 accumulation.  Products of two
+// BF16 or two FP8 values are exact in FP32, so this is the arithmetic of the FP32
+// vector form in another summation order; the MFMA instructions do it at matrix-core
+// rate:
+//   BF16: v_mfma_f32_16x16x32_bf16   (K = 32 rows per instruction),
+//   FP8:  v_mfma_scale_f32_16x16x128_f8f6f4 with format 0 (OCP E4M3) and unit
+//         scales (K = 128 rows); the per-128-column block scales s of the copy
+//         factor out of the sum over rows, G_uv = s_u s_v (codes product sum).
+//
+// Workgroup: one 64x64 sub-block of one panel's block over one split of the rows
+// (the grid and the partial layout of the FP32/FP64 vector kernel: gpart[split][K]
+// [u][v], row-major, summed over splits downstream).  Four waves, each a 32x32
+// quadrant (2x2 MFMA tiles, real and imaginary accumulators).  Per step of KS rows
+// the workgroup stages the two 64-column tiles (Re and Im planes) in LDS, column by
+// column with the rows contiguous, so that a lane's fragment (8 or 32 consecutive
+// rows of one column) is one contiguous LDS read.  The k order inside a fragment is
+// the same for both operands, so the sum over rows does not depend on how the
+// hardware orders k within a fragment.
+#include <type_traits>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace cdm {
+
+namespace {
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef int i32x8_t __attribute__((ext_vector_type(8)));
+
+template <int FMT> struct LpFmt;
+template <> struct LpFmt<SRC_BF16> {
+    using E = uint16_t;
+    static constexpr int KS = 32;    // rows per MFMA step
+    static constexpr int VEC = 8;    // elements per 16-byte chunk
+    static constexpr int PADK = 40;  // LDS elements per staged column (80 B: conflict-free fragment reads)
+};
+template <> struct LpFmt<SRC_FP8> {
+    using E = uint8_t;
+    static constexpr int KS = 128;
+    static constexpr int VEC = 16;
+    static constexpr int PADK = 144;  // 144 B per column
+};
+
+// one fragment: this lane's 8 (BF16) or 32 (FP8) consecutive rows of one staged column
+struct FragBF16 {
+    bf16x8_t v;
+};
+struct FragFP8 {
+    i32x8_t v;
+};
+__device__ __forceinline__ FragBF16 load_frag(const uint16_t* p, FragBF16*) {
+    FragBF16 f;
+    f.v = *reinterpret_cast<const bf16x8_t*>(p);
+    return f;
+}
+__device__ __forceinline__ FragFP8 load_frag(const uint8_t* p, FragFP8*) {
+    FragFP8 f;
+    f.v = *reinterpret_cast<const i32x8_t*>(p);
+    return f;
+}
+// sign flip of every element (BF16: bit 15 of each half; E4M3: bit 7 of each byte)
+__device__ __forceinline__ FragBF16 negate(FragBF16 f) {
+    u32x4_t u = __builtin_bit_cast(u32x4_t, f.v);
+    u ^= 0x80008000u;
+    f.v = __builtin_bit_cast(bf16x8_t, u);
+    return f;
+}
+__device__ __forceinline__ FragFP8 negate(FragFP8 f) {
+    f.v ^= (int)0x80808080u;
+    return f;
+}
+__device__ __forceinline__ f32x4_t mma(const FragBF16& a, const FragBF16& b, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4_t mma(const FragFP8& a, const FragFP8& b, f32x4_t c) {
+    // A and B format 0 (FP8 E4M3), E8M0 scales 127 (2^0)
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a.v, b.v, c, 0, 0, 0, 127, 0, 127);
+}
+
+}  // namespace
+
+template <int FMT, bool CROSS>
+__global__ __launch_bounds__(256) void k_gram_lp(const typename LpFmt<FMT>::E* __restrict__ re,
+                                                 const typename LpFmt<FMT>::E* __restrict__ im,
+                                                 const float* __restrict__ scale, int64_t ld, int B, int U, int kp,
+                                                 int nsub, int rows_per_split, float2* __restrict__ gpart,
+                                                 int npanels, int dist, int vec_ok) {
+    using F = LpFmt<FMT>;
+    using E = typename F::E;
+    using Frag = typename std::conditional<FMT == SRC_BF16, FragBF16, FragFP8>::type;
+    constexpr int KS = F::KS, VEC = F::VEC, PADK = F::PADK;
+    constexpr int CHUNKS = 64 * KS / VEC;                    // 16-byte chunks per staged tile
+    __shared__ __attribute__((aligned(16))) E tile[4][64 * PADK];   // A re, A im, B re, B im
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int K = blockIdx.x / nsub;
+    int sb = blockIdx.x % nsub;
+    int bi = 0, bj = 0;
+    if (CROSS) {
+        bi = sb / (kp / 64);
+        bj = sb % (kp / 64);
+    } else {
+        while (sb > bi) {   // sub-block (bi, bj), bi >= bj, row by row of the lower triangle
+            sb -= bi + 1;
+            ++bi;
+        }
+        bj = sb;
+    }
+    const int split = blockIdx.y;
+    const int r_lo = split * rows_per_split;
+    const int r_hi = min(B, r_lo + rows_per_split);
+    const int colA0 = K * kp + bi * 64;
+    const int colB0 = (CROSS ? (K + npanels - dist % npanels) % npanels : K) * kp + bj * 64;
+    const bool same = colA0 == colB0;   // a diagonal sub-block: one tile serves as both operands
+
+    // stage the KS rows from r0 of 64 columns from c0 (Re plane into t[0], Im into t[1])
+    auto stage = [&](E* tr, E* ti, int c0, int r0) {
+        for (int c = tid; c < CHUNKS; c += 256) {
+            const int cl = c / (KS / VEC);
+            const int row = r0 + (c % (KS / VEC)) * VEC;
+            const int col = c0 + cl;
+            E* dr = tr + cl * PADK + (row - r0);
+            E* di = ti + cl * PADK + (row - r0);
+            if (vec_ok && col < U && row + VEC <= r_hi) {
+                const int64_t off = (int64_t)col * ld + row;
+                *reinterpret_cast<uint4*>(dr) = *reinterpret_cast<const uint4*>(re + off);
+                *reinterpret_cast<uint4*>(di) = *reinterpret_cast<const uint4*>(im + off);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const bool in = col < U && row + e < r_hi;
+                    const int64_t off = (int64_t)min(col, U - 1) * ld + min(row + e, B - 1);
+                    dr[e] = in ? re[off] : (E)0;
+                    di[e] = in ? im[off] : (E)0;
+                }
+            }
+        }
+    };
+
+    const int qi = wv >> 1, qj = wv & 1;   // this wave's 32x32 quadrant
+    f32x4_t accr[2][2], acci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            accr[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+            acci[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        }
+    const int fk = (lane >> 4) * (KS / 4);   // first row of this lane's fragment
+    const E* Bre = same ? tile[0] : tile[2];
+    const E* Bim = same ? tile[1] : tile[3];
+    for (int r0 = r_lo; r0 < r_hi; r0 += KS) {
+        stage(tile[0], tile[1], colA0, r0);
+        if (!same) stage(tile[2], tile[3], colB0, r0);
+        __syncthreads();
+        Frag ar[2], ai[2], an[2], br[2], bim[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int cu = 32 * qi + 16 * i + (lane & 15);
+            ar[i] = load_frag(tile[0] + cu * PADK + fk, (Frag*)nullptr);
+            ai[i] = load_frag(tile[1] + cu * PADK + fk, (Frag*)nullptr);
+            an[i] = negate(ai[i]);
+            const int cv_ = 32 * qj + 16 * i + (lane & 15);
+            br[i] = load_frag(Bre + cv_ * PADK + fk, (Frag*)nullptr);
+            bim[i] = load_frag(Bim + cv_ * PADK + fk, (Frag*)nullptr);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                accr[i][j] = mma(ar[i], br[j], accr[i][j]);
+                accr[i][j] = mma(ai[i], bim[j], accr[i][j]);
+                acci[i][j] = mma(ar[i], bim[j], acci[i][j]);
+                acci[i][j] = mma(an[i], br[j], acci[i][j]);
+            }
+        __syncthreads();
+    }
+
+    // D[16 x 16]: lane holds rows 4 (lane >> 4) .. + 3 of column lane & 15
+    float2* out = gpart + ((int64_t)split * npanels + K) * kp * kp;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int v = 32 * qj + 16 * j + (lane & 15);
+            float sv = 1.f;
+            if (FMT == SRC_FP8) sv = scale[min(colB0 + v, U - 1) >> 7];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int u = 32 * qi + 16 * i + 4 * (lane >> 4) + e;
+                float s = 1.f;
+                if (FMT == SRC_FP8) s = scale[min(colA0 + u, U - 1) >> 7] * sv;
+                out[(int64_t)(bi * 64 + u) * kp + bj * 64 + v] = make_float2(accr[i][j][e] * s, acci[i][j][e] * s);
+            }
+        }
+}
+
+// Partial Gram blocks of the BF16 or FP8 copy into L.gpart: the diagonal blocks
+// (lower sub-blocks, cross = false) or the cross blocks H_K^H H_{K-dist}.
+hipError_t launch_gram_lp(const GramLaunch& L, bool cross, int dist, hipStream_t st) {
+    if (L.src_kind != SRC_BF16 && L.src_kind != SRC_FP8) return hipErrorInvalidValue;
+    if (L.kp % 64 != 0 || L.nsplit < 1) return hipErrorInvalidValue;
+    const int nb = L.kp / 64;
+    const int nsub = cross ? nb * nb : nb * (nb + 1) / 2;
+    const int ks = L.src_kind == SRC_BF16 ? LpFmt<SRC_BF16>::KS : LpFmt<SRC_FP8>::KS;
+    const int vec = L.src_kind == SRC_BF16 ? LpFmt<SRC_BF16>::VEC : LpFmt<SRC_FP8>::VEC;
+    int rps = (L.B + L.nsplit - 1) / L.nsplit;
+    rps = (rps + ks - 1) / ks * ks;
+    const int vec_ok = (L.ld % vec) == 0;
+    const dim3 grid(L.npanels * nsub, L.nsplit);
+    float2* gp = (float2*)L.gpart;
+    if (L.src_kind == SRC_BF16) {
+        if (cross)
+            hipLaunchKernelGGL((k_gram_lp<SRC_BF16, true>), grid, dim3(256), 0, st, L.q_re16, L.q_im16, nullptr, L.ld,
+                               L.B, L.U, L.kp, nsub, rps, gp, L.npanels, dist, vec_ok);
+        else
+            hipLaunchKernelGGL((k_gram_lp<SRC_BF16, false>), grid, dim3(256), 0, st, L.q_re16, L.q_im16, nullptr, L.ld,
+                               L.B, L.U, L.kp, nsub, rps, gp, L.npanels, dist, vec_ok);
+    } else {
+        if (cross)
+            hipLaunchKernelGGL((k_gram_lp<SRC_FP8, true>), grid, dim3(256), 0, st, L.q_re8, L.q_im8, L.q_scale, L.ld,
+                               L.B, L.U, L.kp, nsub, rps, gp, L.npanels, dist, vec_ok);
+        else
+            hipLaunchKernelGGL((k_gram_lp<SRC_FP8, false>), grid, dim3(256), 0, st, L.q_re8, L.q_im8, L.q_scale, L.ld,
+                               L.B, L.U, L.kp, nsub, rps, gp, L.npanels, dist, vec_ok);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cdm

@@ -547,16 +547,14 @@ template <typename T> static hipError_t launch_gram_t(const GramLaunch& L, hipSt
     const int nsub = nb * (nb + 1) / 2;
     int rps = (L.B + L.nsplit - 1) / L.nsplit;
     rps = (rps + 31) / 32 * 32;
-    if (L.src_kind == SRC_BF16) {
-        if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL((k_gram_partial<T, SrcBF16>), dim3(L.npanels * nsub, L.nsplit), dim3(256), 0, st,
-                               SrcBF16{L.q_re16, L.q_im16}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart,
-                               L.npanels);
-    } else if (L.src_kind == SRC_FP8) {
-        if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL((k_gram_partial<T, SrcFP8>), dim3(L.npanels * nsub, L.nsplit), dim3(256), 0, st,
-                               SrcFP8{L.q_re8, L.q_im8, L.q_scale}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart,
-                               L.npanels);
+    if (L.src_kind == SRC_BF16 || L.src_kind == SRC_FP8) {
+        // the low-precision copies: matrix cores (FP32 partials, same layout)
+        if constexpr (sizeof(T) == 4) {
+            hipError_t e = launch_gram_lp(L, false, 1, st);
+            if (e != hipSuccess) return e;
+        } else {
+            return hipErrorInvalidValue;
+        }
     } else {
         hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>>), dim3(L.npanels * nsub, L.nsplit), dim3(256), 0, st,
                            SrcC<T>{(const cv<T>*)L.H}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels);
@@ -640,15 +638,13 @@ static hipError_t launch_gram_cross_t(const GramLaunch& L, void* X, hipStream_t 
     int rps = (L.B + L.nsplit - 1) / L.nsplit;
     rps = (rps + 31) / 32 * 32;
     const dim3 grid(L.npanels * nsub, L.nsplit);
-    if (L.src_kind == SRC_BF16) {
-        if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL((k_gram_partial<T, SrcBF16, true>), grid, dim3(256), 0, st, SrcBF16{L.q_re16, L.q_im16},
-                               L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels, dist);
-    } else if (L.src_kind == SRC_FP8) {
-        if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL((k_gram_partial<T, SrcFP8, true>), grid, dim3(256), 0, st,
-                               SrcFP8{L.q_re8, L.q_im8, L.q_scale}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart,
-                               L.npanels, dist);
+    if (L.src_kind == SRC_BF16 || L.src_kind == SRC_FP8) {
+        if constexpr (sizeof(T) == 4) {
+            hipError_t e = launch_gram_lp(L, true, dist, st);
+            if (e != hipSuccess) return e;
+        } else {
+            return hipErrorInvalidValue;
+        }
     } else {
         hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>, true>), grid, dim3(256), 0, st, SrcC<T>{(const cv<T>*)L.H},
                            L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels, dist);

@@ -165,6 +165,10 @@ struct GramLaunch {
     double lambda;
 };
 hipError_t launch_gram(const GramLaunch& L, hipStream_t st);
+// Partial Gram blocks of the BF16 or FP8 copy on the matrix cores, into L.gpart (the
+// layout of the vector kernel's partials): diagonal blocks (lower sub-blocks) or, with
+// cross, the blocks H_K^H H_{K-dist mod npanels}.
+hipError_t launch_gram_lp(const GramLaunch& L, bool cross, int dist, hipStream_t st);
 // Cross blocks X_K = H_K^H H_{K-1 mod npanels} (full kp x kp, transposed) into X,
 // using gpart as split scratch (call after launch_gram: its contents are consumed,
 // and M is read).  For complex128 with 64-column panels X receives -M_K X_K
