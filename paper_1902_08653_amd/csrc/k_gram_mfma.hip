@@ -1,5 +1,5 @@
-// k_gram_lp.hip -- Gram blocks of the low-precision copies of H (BF16, FP8-e4m3) on
-// gfx950's matrix cores.
+// k_gram_mfma.hip -- panel Gram blocks on gfx950's matrix cores: the low-precision
+// copies of H (BF16, FP8-e4m3) of the mixed-precision refinement, and complex128 H.
 //
 // The mixed-precision refinement runs its inner sweeps on a BF16 or FP8 copy of H, so
 // the panel inverses M_K = (D + L)^-1 and the look-ahead cross blocks come from the
@@ -129,27 +129,42 @@ __global__ __launch_bounds__(256) void k_gram_lp(const typename LpFmt<FMT>::E* _
     const int colB0 = (CROSS ? (K + npanels - dist % npanels) % npanels : K) * kp + bj * 64;
     const bool same = colA0 == colB0;   // a diagonal sub-block: one tile serves as both operands
 
-    // stage the KS rows from r0 of 64 columns from c0 (Re plane into t[0], Im into t[1])
-    auto stage = [&](E* tr, E* ti, int c0, int r0) {
-        for (int c = tid; c < CHUNKS; c += 256) {
+    // The KS rows from r0 of 64 columns from c0, as 16-byte chunks (CPT per thread, Re and
+    // Im): fetched into registers a step ahead, then put into LDS (Re plane, Im plane).
+    constexpr int CPT = CHUNKS / 256;
+    union Chunk {
+        uint4 q;
+        E e[VEC];
+    };
+    auto fetch = [&](Chunk (&vr)[CPT], Chunk (&vi)[CPT], int c0, int r0) {
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            const int c = tid + 256 * m;
             const int cl = c / (KS / VEC);
             const int row = r0 + (c % (KS / VEC)) * VEC;
             const int col = c0 + cl;
-            E* dr = tr + cl * PADK + (row - r0);
-            E* di = ti + cl * PADK + (row - r0);
             if (vec_ok && col < U && row + VEC <= r_hi) {
                 const int64_t off = (int64_t)col * ld + row;
-                *reinterpret_cast<uint4*>(dr) = *reinterpret_cast<const uint4*>(re + off);
-                *reinterpret_cast<uint4*>(di) = *reinterpret_cast<const uint4*>(im + off);
+                vr[m].q = *reinterpret_cast<const uint4*>(re + off);
+                vi[m].q = *reinterpret_cast<const uint4*>(im + off);
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
                     const bool in = col < U && row + e < r_hi;
                     const int64_t off = (int64_t)min(col, U - 1) * ld + min(row + e, B - 1);
-                    dr[e] = in ? re[off] : (E)0;
-                    di[e] = in ? im[off] : (E)0;
+                    vr[m].e[e] = in ? re[off] : (E)0;
+                    vi[m].e[e] = in ? im[off] : (E)0;
                 }
             }
+        }
+    };
+    auto put = [&](const Chunk (&vr)[CPT], const Chunk (&vi)[CPT], E* tr, E* ti) {
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            const int c = tid + 256 * m;
+            const int o = (c / (KS / VEC)) * PADK + (c % (KS / VEC)) * VEC;
+            *reinterpret_cast<uint4*>(tr + o) = vr[m].q;
+            *reinterpret_cast<uint4*>(ti + o) = vi[m].q;
         }
     };
 
@@ -165,10 +180,19 @@ __global__ __launch_bounds__(256) void k_gram_lp(const typename LpFmt<FMT>::E* _
     const int fk = (lane >> 4) * (KS / 4);   // first row of this lane's fragment
     const E* Bre = same ? tile[0] : tile[2];
     const E* Bim = same ? tile[1] : tile[3];
+    Chunk ar_[CPT], ai_[CPT], br_[CPT], bi_[CPT];
+    if (r_lo < r_hi) {
+        fetch(ar_, ai_, colA0, r_lo);
+        if (!same) fetch(br_, bi_, colB0, r_lo);
+    }
     for (int r0 = r_lo; r0 < r_hi; r0 += KS) {
-        stage(tile[0], tile[1], colA0, r0);
-        if (!same) stage(tile[2], tile[3], colB0, r0);
+        put(ar_, ai_, tile[0], tile[1]);
+        if (!same) put(br_, bi_, tile[2], tile[3]);
         __syncthreads();
+        if (r0 + KS < r_hi) {   // in flight during this step's products
+            fetch(ar_, ai_, colA0, r0 + KS);
+            if (!same) fetch(br_, bi_, colB0, r0 + KS);
+        }
         Frag ar[2], ai[2], an[2], br[2], bim[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -240,6 +264,146 @@ hipError_t launch_gram_lp(const GramLaunch& L, bool cross, int dist, hipStream_t
             hipLaunchKernelGGL((k_gram_lp<SRC_FP8, false>), grid, dim3(256), 0, st, L.q_re8, L.q_im8, L.q_scale, L.ld,
                                L.B, L.U, L.kp, nsub, rps, gp, L.npanels, dist, vec_ok);
     }
+    return hipGetLastError();
+}
+
+// ---- complex128 -------------------------------------------------------------------
+// The same block partials for complex128 H on v_mfma_f64_16x16x4_f64 (four rows per
+// instruction, FP64 FMA).  gfx950's FP64 matrix rate equals its FP64 vector rate, so
+// this gains by issue: one instruction does the work of sixteen wave-wide FMAs, from
+// four 8-byte operands per lane.  Staging: 32 rows of two 64-column tiles per step, split
+// into Re and Im planes, column by column with a pitch of 34 doubles: the staging writes
+// (consecutive rows) and the fragment reads (16 columns x 2 rows per half-wave) are then
+// conflict-free.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+constexpr int G64_KS = 32, G64_PITCH = 34;
+
+template <bool CROSS>
+__global__ __launch_bounds__(256) void k_gram_f64(const double2* __restrict__ H, int64_t ld, int B, int U, int kp,
+                                                  int nsub, int rows_per_split, double2* __restrict__ gpart,
+                                                  int npanels, int dist) {
+    __shared__ double tile[4][64 * G64_PITCH];   // A re, A im, B re, B im
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int K = blockIdx.x / nsub;
+    int sb = blockIdx.x % nsub;
+    int bi = 0, bj = 0;
+    if (CROSS) {
+        bi = sb / (kp / 64);
+        bj = sb % (kp / 64);
+    } else {
+        while (sb > bi) {
+            sb -= bi + 1;
+            ++bi;
+        }
+        bj = sb;
+    }
+    const int split = blockIdx.y;
+    const int r_lo = split * rows_per_split;
+    const int r_hi = min(B, r_lo + rows_per_split);
+    const int colA0 = K * kp + bi * 64;
+    const int colB0 = (CROSS ? (K + npanels - dist % npanels) % npanels : K) * kp + bj * 64;
+    const bool same = colA0 == colB0;
+
+    // thread -> row r0 + (tid & 31), columns (tid >> 5) + 8 k of a tile; the next step's
+    // values are loaded into registers while this step computes
+    auto fetch = [&](double2 (&v)[8], int c0, int r0) {
+        const int row = r0 + (tid & 31);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int col = c0 + (tid >> 5) + 8 * k;
+            v[k] = (row < r_hi && col < U) ? ld_nt(H + (int64_t)col * ld + row) : make_double2(0.0, 0.0);
+        }
+    };
+    auto put = [&](const double2 (&v)[8], double* tr, double* ti) {
+        const int i = tid & 31;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int cl = (tid >> 5) + 8 * k;
+            tr[cl * G64_PITCH + i] = v[k].x;
+            ti[cl * G64_PITCH + i] = v[k].y;
+        }
+    };
+
+    const int qi = wv >> 1, qj = wv & 1;
+    f64x4_t accr[2][2], acci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            accr[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+            acci[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+        }
+    const double* Bre = same ? tile[0] : tile[2];
+    const double* Bim = same ? tile[1] : tile[3];
+    double2 va[8], vb[8];
+    if (r_lo < r_hi) {
+        fetch(va, colA0, r_lo);
+        if (!same) fetch(vb, colB0, r_lo);
+    }
+    for (int r0 = r_lo; r0 < r_hi; r0 += G64_KS) {
+        put(va, tile[0], tile[1]);
+        if (!same) put(vb, tile[2], tile[3]);
+        __syncthreads();
+        if (r0 + G64_KS < r_hi) {   // in flight during this step's products
+            fetch(va, colA0, r0 + G64_KS);
+            if (!same) fetch(vb, colB0, r0 + G64_KS);
+        }
+#pragma unroll 2
+        for (int k0 = 0; k0 < G64_KS; k0 += 4) {
+            const int rk = k0 + (lane >> 4);   // this lane's row of the 4-row step
+            double ar[2], ai[2], br[2], bm[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int cu = 32 * qi + 16 * i + (lane & 15);
+                const int cv_ = 32 * qj + 16 * i + (lane & 15);
+                ar[i] = tile[0][cu * G64_PITCH + rk];
+                ai[i] = tile[1][cu * G64_PITCH + rk];
+                br[i] = Bre[cv_ * G64_PITCH + rk];
+                bm[i] = Bim[cv_ * G64_PITCH + rk];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
+                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bm[j], accr[i][j], 0, 0, 0);
+                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bm[j], acci[i][j], 0, 0, 0);
+                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], br[j], acci[i][j], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    // D[16 x 16] of the FP64 form: lane holds rows (lane >> 4) + 4 e, e = 0..3, of column
+    // lane & 15 (interleaved, unlike the 4 consecutive rows of the FP32-output forms)
+    double2* out = gpart + ((int64_t)split * npanels + K) * kp * kp;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int v = 32 * qj + 16 * j + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int u = 32 * qi + 16 * i + (lane >> 4) + 4 * e;
+                out[(int64_t)(bi * 64 + u) * kp + bj * 64 + v] = make_double2(accr[i][j][e], acci[i][j][e]);
+            }
+        }
+}
+
+hipError_t launch_gram_f64(const GramLaunch& L, bool cross, int dist, hipStream_t st) {
+    if (!L.c128 || L.src_kind != SRC_COMPLEX || L.kp % 64 != 0 || L.nsplit < 1) return hipErrorInvalidValue;
+    const int nb = L.kp / 64;
+    const int nsub = cross ? nb * nb : nb * (nb + 1) / 2;
+    int rps = (L.B + L.nsplit - 1) / L.nsplit;
+    rps = (rps + G64_KS - 1) / G64_KS * G64_KS;
+    const dim3 grid(L.npanels * nsub, L.nsplit);
+    if (cross)
+        hipLaunchKernelGGL((k_gram_f64<true>), grid, dim3(256), 0, st, (const double2*)L.H, L.ld, L.B, L.U, L.kp, nsub,
+                           rps, (double2*)L.gpart, L.npanels, dist);
+    else
+        hipLaunchKernelGGL((k_gram_f64<false>), grid, dim3(256), 0, st, (const double2*)L.H, L.ld, L.B, L.U, L.kp,
+                           nsub, rps, (double2*)L.gpart, L.npanels, dist);
     return hipGetLastError();
 }
 

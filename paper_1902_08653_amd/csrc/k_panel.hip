@@ -555,6 +555,10 @@ template <typename T> static hipError_t launch_gram_t(const GramLaunch& L, hipSt
         } else {
             return hipErrorInvalidValue;
         }
+    } else if (sizeof(T) == 8) {
+        // complex128: FP64 matrix cores
+        hipError_t e = launch_gram_f64(L, false, 1, st);
+        if (e != hipSuccess) return e;
     } else {
         hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>>), dim3(L.npanels * nsub, L.nsplit), dim3(256), 0, st,
                            SrcC<T>{(const cv<T>*)L.H}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels);
@@ -645,6 +649,9 @@ static hipError_t launch_gram_cross_t(const GramLaunch& L, void* X, hipStream_t 
         } else {
             return hipErrorInvalidValue;
         }
+    } else if (sizeof(T) == 8) {
+        hipError_t e = launch_gram_f64(L, true, dist, st);
+        if (e != hipSuccess) return e;
     } else {
         hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>, true>), grid, dim3(256), 0, st, SrcC<T>{(const cv<T>*)L.H},
                            L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels, dist);
