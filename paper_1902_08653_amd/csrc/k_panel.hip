@@ -478,12 +478,16 @@ __global__ __launch_bounds__(256) void k_gram_partial(Src src, int64_t ld, int B
 // Sum the split partials, form D + L (lambda on the diagonal; inactive coordinates
 // with ||h_u||^2 + lambda == 0 decoupled), and invert it row by row:
 //   M_uc = ([u == c] - sum_{c <= v < u} A_uv M_vc) / A_uu.
-// One workgroup of kp threads per panel; thread c owns column c of M.
+// One workgroup of kp threads per panel; thread c owns column c of M.  The rows of M
+// the recurrence reads back live in LDS (dynamic, kp * kp values) where they fit, else in
+// the global scratch Mrow.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram_invert(cv<T>* __restrict__ gpart, int nsplit, int npanels, int kp, int U,
                                                      double lambda, cv<T>* __restrict__ Mcm, cv<T>* __restrict__ Mrow,
-                                                     double* __restrict__ e_out, uint32_t* __restrict__ status) {
+                                                     double* __restrict__ e_out, uint32_t* __restrict__ status,
+                                                     int m_in_lds) {
     using V = cv<T>;
+    extern __shared__ __attribute__((aligned(16))) char inv_dyn[];
     const int K = blockIdx.x;
     const int c = threadIdx.x;
     const int64_t pstride = (int64_t)npanels * kp * kp;
@@ -517,7 +521,7 @@ __global__ __launch_bounds__(256) void k_gram_invert(cv<T>* __restrict__ gpart, 
     }
     __syncthreads();
     // 3. inverse of (D + L), row by row
-    V* Mr = Mrow + (int64_t)K * kp * kp;
+    V* Mr = m_in_lds ? reinterpret_cast<V*>(inv_dyn) : Mrow + (int64_t)K * kp * kp;
     V* Mp = Mcm + (int64_t)K * (kp * (kp + 1) / 2);
     for (int u = 0; u < kp; ++u) {
         if (c < u) {
@@ -540,6 +544,24 @@ __global__ __launch_bounds__(256) void k_gram_invert(cv<T>* __restrict__ gpart, 
         }
         __syncthreads();
     }
+}
+
+// the row-major M of one panel in LDS where it fits (128 KB at most: complex64 k = 128,
+// complex128 k = 64), else the global scratch
+template <typename T>
+static hipError_t launch_invert_t(cv<T>* gpart, int nsplit, int npanels, int kp, int U, double lambda, cv<T>* M,
+                                  cv<T>* Mrow, double* e, uint32_t* status, hipStream_t st) {
+    const size_t mb = (size_t)kp * kp * sizeof(cv<T>);
+    int in_lds = mb <= (size_t)128 * 1024;
+    if (in_lds && mb > 64 * 1024 &&
+        hipFuncSetAttribute((const void*)k_gram_invert<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mb) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        in_lds = 0;
+    }
+    hipLaunchKernelGGL(k_gram_invert<T>, dim3(npanels), dim3(kp), in_lds ? mb : 0, st, gpart, nsplit, npanels, kp, U,
+                       lambda, M, Mrow, e, status, in_lds);
+    return hipGetLastError();
 }
 
 template <typename T> static hipError_t launch_gram_t(const GramLaunch& L, hipStream_t st) {
@@ -569,23 +591,20 @@ template <typename T> static hipError_t launch_gram_t(const GramLaunch& L, hipSt
     // recurrence reads its own earlier rows); the row-major copy lives in the
     // split-1 slot of gpart when nsplit > 1, else right after M.
     cv<T>* Mrow = (cv<T>*)L.gpart + (int64_t)L.npanels * L.kp * L.kp;
-    hipLaunchKernelGGL(k_gram_invert<T>, dim3(L.npanels), dim3(L.kp), 0, st, (cv<T>*)L.gpart, L.nsplit, L.npanels,
-                       L.kp, L.U, L.lambda, (cv<T>*)L.M, Mrow, L.e, L.status);
-    return hipGetLastError();
+    return launch_invert_t<T>((cv<T>*)L.gpart, L.nsplit, L.npanels, L.kp, L.U, L.lambda, (cv<T>*)L.M, Mrow, L.e,
+                              L.status, st);
 }
 
 hipError_t launch_gram_invert(bool c128, void* gpart, int nsplit, int npanels, int kp, int U, double lambda, void* M,
                               double* e, uint32_t* status, hipStream_t st) {
     if (c128) {
         using V = cv<double>;
-        hipLaunchKernelGGL(k_gram_invert<double>, dim3(npanels), dim3(kp), 0, st, (V*)gpart, nsplit, npanels, kp, U,
-                           lambda, (V*)M, (V*)gpart + (int64_t)npanels * kp * kp, e, status);
-    } else {
-        using V = cv<float>;
-        hipLaunchKernelGGL(k_gram_invert<float>, dim3(npanels), dim3(kp), 0, st, (V*)gpart, nsplit, npanels, kp, U,
-                           lambda, (V*)M, (V*)gpart + (int64_t)npanels * kp * kp, e, status);
+        return launch_invert_t<double>((V*)gpart, nsplit, npanels, kp, U, lambda, (V*)M,
+                                       (V*)gpart + (int64_t)npanels * kp * kp, e, status, st);
     }
-    return hipGetLastError();
+    using V = cv<float>;
+    return launch_invert_t<float>((V*)gpart, nsplit, npanels, kp, U, lambda, (V*)M,
+                                  (V*)gpart + (int64_t)npanels * kp * kp, e, status, st);
 }
 
 hipError_t launch_gram(const GramLaunch& L, hipStream_t st) {
