@@ -7,8 +7,9 @@
 //     delta_u = (b_u - sum_{v<u, v in K} G_uv delta_v) / (||h_u||^2 + lambda),
 // i.e. (D + L) delta_K = b_K: exactly the same numbers, in exact arithmetic, as
 // running the u-loop of Algorithm 1 one coordinate at a time.  Here
-// M_K = (D + L)^-1 is formed once per solve (k_gram_partial + k_gram_invert, a
-// small dense contraction per panel), and every sweep applies
+// M_K = (D + L)^-1 is formed once per solve (the panel Gram blocks -- on the matrix
+// cores for complex128 and the low-precision copies, k_gram_mfma.hip; k_gram_partial
+// for complex64 -- then k_gram_invert), and every sweep applies
 //     delta_K = M_K b_K,   x_K += delta_K,   r -= H_K delta_K.
 //
 // k_cd_panel runs all sweeps in one cooperative launch.  Workgroup w owns rows
@@ -396,7 +397,8 @@ int panel_max_coresident(bool c128, int kp, int rpl) {
 }
 
 // ============================================================================
-// Panel Gram blocks G_K = H_K^H H_K (lower 64x64 sub-blocks) over a row split.
+// Panel Gram blocks G_K = H_K^H H_K (lower 64x64 sub-blocks) over a row split, on the
+// vector units (complex64 H; complex128 and the BF16/FP8 copies use the matrix cores).
 // grid.x = npanels * nsub, grid.y = nsplit; 256 threads as a 16 x 16 grid, each
 // accumulating a 4 x 4 complex tile; rows stream through LDS 32 at a time.
 // ============================================================================
@@ -577,13 +579,15 @@ template <typename T> static hipError_t launch_gram_t(const GramLaunch& L, hipSt
         } else {
             return hipErrorInvalidValue;
         }
-    } else if (sizeof(T) == 8) {
-        // complex128: FP64 matrix cores
-        hipError_t e = launch_gram_f64(L, false, 1, st);
-        if (e != hipSuccess) return e;
     } else {
-        hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>>), dim3(L.npanels * nsub, L.nsplit), dim3(256), 0, st,
-                           SrcC<T>{(const cv<T>*)L.H}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels);
+        if constexpr (sizeof(T) == 8) {   // complex128: FP64 matrix cores
+            hipError_t e = launch_gram_f64(L, false, 1, st);
+            if (e != hipSuccess) return e;
+        } else {
+            hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>>), dim3(L.npanels * nsub, L.nsplit), dim3(256), 0, st,
+                               SrcC<T>{(const cv<T>*)L.H}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart,
+                               L.npanels);
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -668,12 +672,14 @@ static hipError_t launch_gram_cross_t(const GramLaunch& L, void* X, hipStream_t 
         } else {
             return hipErrorInvalidValue;
         }
-    } else if (sizeof(T) == 8) {
-        hipError_t e = launch_gram_f64(L, true, dist, st);
-        if (e != hipSuccess) return e;
     } else {
-        hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>, true>), grid, dim3(256), 0, st, SrcC<T>{(const cv<T>*)L.H},
-                           L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels, dist);
+        if constexpr (sizeof(T) == 8) {
+            hipError_t e = launch_gram_f64(L, true, dist, st);
+            if (e != hipSuccess) return e;
+        } else {
+            hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>, true>), grid, dim3(256), 0, st, SrcC<T>{(const cv<T>*)L.H},
+                               L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels, dist);
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
