@@ -15,8 +15,13 @@
 // delta_{K+1}, which its own tile waves have formed by then, and publishes
 //     q_{K+3} = p_{K+3} - X2_{K+3} delta_{K+1} - lambda x_{K+3};
 // every workgroup forms delta_{K+3} = M_{K+3} q_{K+3} + (-Y_{K+3}) delta_{K+2} itself
-// (-Y = -M X in LDS), as in the shallower schedule.  In exact arithmetic every delta
+// (-Y = -M X in LDS), as in the one-panel schedule.  In exact arithmetic every delta
 // equals the sequential sweep's.
+//
+// Opt-in (CDM_F_DEEP_LOOKAHEAD): each tile is read twice per sweep here (for its
+// partials, and three steps later for its update), and the exchange's loads return
+// behind that doubled stream, so on the devices measured the one-panel schedule is the
+// faster one.
 //
 // Workgroup: 8 tile waves, one control wave, one X-staging wave (640 threads, one per
 // CU, 64 rows each).

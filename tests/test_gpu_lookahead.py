@@ -161,7 +161,7 @@ def test_two_panel_lookahead_warm_start_and_tolerance(dev, orc):
     assert relerr(x, at["x"]) <= 1e-10
 
 
-def test_one_or_two_panels_stay_shallow(dev, orc):
+def test_one_or_two_panels_keep_the_one_panel_schedule(dev, orc):
     for U in (64, 128):
         inst = inputs.dense_uplink(4096, U, U)
         x, rec, desc = solve(dev, inst.H, inst.y, "c128", 3, lookahead="deep")
