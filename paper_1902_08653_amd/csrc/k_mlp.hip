@@ -42,7 +42,8 @@ constexpr int GK = 32;
 __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, int64_t sam, int64_t sak,
                                                    const float* __restrict__ Bm, int64_t sbk, int64_t sbn,
                                                    float* __restrict__ C, int64_t ldc, int M, int N, int K,
-                                                   const float* __restrict__ bias, int beta, int kc, int64_t zc) {
+                                                   const float* __restrict__ bias, int beta, int kc, int64_t zc,
+                                                   int relu, const float* __restrict__ mask) {
     // split along K: workgroup z takes K range [z kc, z kc + kc) into C + z zc
     {
         const int z = blockIdx.z;
@@ -101,6 +102,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, 
                 if (gm < M && gn < N) {
                     float v = acc[i][j][r];
                     if (bias) v += bias[gn];
+                    if (relu) v = v > 0.f ? v : 0.f;
+                    if (mask) v = mask[(int64_t)gm * ldc + gn] > 0.f ? v : 0.f;
                     float* cp = &C[(int64_t)gm * ldc + gn];
                     *cp = beta ? (*cp + v) : v;
                 }
@@ -118,7 +121,8 @@ template <bool AK, bool BN>
 __global__ __launch_bounds__(256) void k_gemm2_bf16(const float* __restrict__ A, int64_t lda,
                                                     const float* __restrict__ Bm, int64_t ldb,
                                                     float* __restrict__ C, int64_t ldc, int M, int N, int K,
-                                                    const float* __restrict__ bias, int beta, int kc, int64_t zc) {
+                                                    const float* __restrict__ bias, int beta, int kc, int64_t zc,
+                                                    int relu, const float* __restrict__ mask) {
     // split along K: workgroup z takes K range [z kc, z kc + kc) into C + z zc
     {
         const int z = blockIdx.z;
@@ -236,6 +240,8 @@ __global__ __launch_bounds__(256) void k_gemm2_bf16(const float* __restrict__ A,
                 if (gm < M && gn < N) {
                     float v = acc[i][j][r];
                     if (bias) v += bias[gn];
+                    if (relu) v = v > 0.f ? v : 0.f;
+                    if (mask) v = mask[(int64_t)gm * ldc + gn] > 0.f ? v : 0.f;
                     float* cp = &C[(int64_t)gm * ldc + gn];
                     *cp = beta ? (*cp + v) : v;
                 }
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(256) void k_gemm2_bf16(const float* __restrict__ A,
 // S > 1: S splits of K (chunks of kc, a multiple of 32) side by side, split z writing C + z zc
 static hipError_t gemm_bf16_one(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk, int64_t sbn,
                                 float* C, int64_t ldc, int M, int N, int K, const float* bias, int beta, hipStream_t st,
-                                int S = 1, int kc = 0, int64_t zc = 0) {
+                                int S = 1, int kc = 0, int64_t zc = 0, int relu = 0, const float* mask = nullptr) {
     if (S == 1) kc = K;
     // the tiled kernel: large products whose operands are contiguous along one dimension,
     // with 16-B aligned rows (K, M, N multiples of 4 where they are contiguous)
@@ -256,27 +262,31 @@ static hipError_t gemm_bf16_one(const float* A, int64_t sam, int64_t sak, const 
         const int64_t lda = ak ? sam : sak, ldb = bn ? sbk : sbn;
         if (al(A, lda) && al(B, ldb)) {
             const dim3 g((N + G2T - 1) / G2T, (M + G2T - 1) / G2T, S);
-            if (ak && bn) hipLaunchKernelGGL((k_gemm2_bf16<true, true>), g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias, beta, kc, zc);
-            else if (ak) hipLaunchKernelGGL((k_gemm2_bf16<true, false>), g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias, beta, kc, zc);
-            else if (bn) hipLaunchKernelGGL((k_gemm2_bf16<false, true>), g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias, beta, kc, zc);
-            else hipLaunchKernelGGL((k_gemm2_bf16<false, false>), g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias, beta, kc, zc);
+            if (ak && bn) hipLaunchKernelGGL((k_gemm2_bf16<true, true>), g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias, beta, kc, zc, relu, mask);
+            else if (ak) hipLaunchKernelGGL((k_gemm2_bf16<true, false>), g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias, beta, kc, zc, relu, mask);
+            else if (bn) hipLaunchKernelGGL((k_gemm2_bf16<false, true>), g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias, beta, kc, zc, relu, mask);
+            else hipLaunchKernelGGL((k_gemm2_bf16<false, false>), g, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias, beta, kc, zc, relu, mask);
             return hipGetLastError();
         }
     }
     dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, S);
-    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, beta, kc, zc);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, beta, kc, zc,
+                       relu, mask);
     return hipGetLastError();
 }
 
-// split-K finish: C = sum_s part[s] (fixed order) (+ bias) (+ C if beta)
+// split-K finish: C = sum_s part[s] (fixed order) (+ bias), then relu or the mask
+// [mask > 0] (leading dimension ldc) where given, (+ C if beta)
 __global__ void k_splitk_sum(const float* __restrict__ part, int S, int M, int N, float* __restrict__ C, int64_t ldc,
-                             const float* __restrict__ bias, int beta) {
+                             const float* __restrict__ bias, int beta, int relu, const float* __restrict__ mask) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)M * N) return;
     const int m = (int)(e / N), n = (int)(e % N);
     float v = 0.f;
     for (int k = 0; k < S; ++k) v += part[(int64_t)k * M * N + e];
     if (bias) v += bias[n];
+    if (relu) v = v > 0.f ? v : 0.f;
+    if (mask) v = mask[(int64_t)m * ldc + n] > 0.f ? v : 0.f;
     float* cp = &C[(int64_t)m * ldc + n];
     *cp = beta ? (*cp + v) : v;
 }
@@ -286,21 +296,21 @@ __global__ void k_splitk_sum(const float* __restrict__ part, int S, int M, int N
 // `splitk` (S * M * N floats), then summed in chunk order.
 hipError_t launch_gemm_bf16(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk, int64_t sbn, float* C,
                             int64_t ldc, int M, int N, int K, const float* bias, int beta, hipStream_t st,
-                            float* splitk, int64_t splitk_floats) {
+                            float* splitk, int64_t splitk_floats, int relu = 0, const float* mask = nullptr) {
     const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
     int S = 1;
     if (splitk && K >= 4096 && tiles < 256) {
         S = (int)std::min<int64_t>(std::min<int64_t>(64, K / 256), splitk_floats / ((int64_t)M * N));
         S = std::max(S, 1);
     }
-    if (S == 1) return gemm_bf16_one(A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, beta, st);
+    if (S == 1) return gemm_bf16_one(A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, beta, st, 1, 0, 0, relu, mask);
     const int chunk = ((K + S - 1) / S + 31) / 32 * 32;   // multiple of the tiled kernel's K chunk
     const int s = (K + chunk - 1) / chunk;
     hipError_t e = gemm_bf16_one(A, sam, sak, B, sbk, sbn, splitk, N, M, N, K, nullptr, 0, st, s, chunk, (int64_t)M * N);
     if (e != hipSuccess) return e;
     const int64_t mn = (int64_t)M * N;
     hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, (const float*)splitk, s, M,
-                       N, C, ldc, bias, beta);
+                       N, C, ldc, bias, beta, relu, mask);
     return hipGetLastError();
 }
 
@@ -394,6 +404,158 @@ hipError_t launch_adam(float* w, const float* g, float* m1, float* m2, int64_t n
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, g, m1, m2, n, lr, b1, b2, eps,
                        c1, c2);
     return hipGetLastError();
+}
+
+// ---- the narrow layers (nin <= 16 inputs, nout <= 4 outputs) on VALU -------------
+// A GEMM of inner dimension 8 or output width 2 leaves the matrix cores idle and is
+// bound by the activations it reads or writes, so these layers are plain loops with the
+// tile GEMMs' arithmetic (BF16 operands, FP32 accumulation), fused with the ReLU, the
+// ReLU mask of the backward pass and the bias gradients (FP32, as the column sums).
+constexpr int NL_MAXIN = 16, NL_MAXOUT = 4, NL_RB = 32;
+// the value of x rounded to BF16 (nearest even, the conversion the tile GEMMs use): every
+// product operand is rounded as in the matrix-core layers, and the product of two BF16
+// values is exact in FP32
+__device__ __forceinline__ float bfr(float x) { return __uint_as_float((uint32_t)f32_to_bf16(x) << 16); }
+
+// A1 = relu(X W1 + b1): workgroup -> 64 columns x NL_RB rows; thread -> column c0 + (tid
+// & 63), rows q, q + 4, ... of the block (q = tid >> 6); the block's rows of X in LDS
+__global__ __launch_bounds__(256) void k_nl_in_fwd(const float* __restrict__ X, const float* __restrict__ W1,
+                                                   const float* __restrict__ b1, float* __restrict__ A1, int rows,
+                                                   int nin, int h1) {
+    __shared__ float xs[NL_RB][NL_MAXIN];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
+    const int rb = blockIdx.y * NL_RB;
+    for (int e = threadIdx.x; e < NL_RB * NL_MAXIN; e += 256) {
+        const int r = e / NL_MAXIN, k = e % NL_MAXIN;
+        xs[r][k] = (rb + r < rows && k < nin) ? bfr(X[(int64_t)(rb + r) * nin + k]) : 0.f;
+    }
+    __syncthreads();
+    if (c >= h1) return;
+    float w[NL_MAXIN];
+#pragma unroll
+    for (int k = 0; k < NL_MAXIN; ++k) w[k] = k < nin ? bfr(W1[(int64_t)k * h1 + c]) : 0.f;
+    const float b = b1[c];
+    for (int r = q; r < NL_RB && rb + r < rows; r += 4) {
+        float v = b;
+#pragma unroll
+        for (int k = 0; k < NL_MAXIN; ++k) v += xs[r][k] * w[k];
+        A1[(int64_t)(rb + r) * h1 + c] = v > 0.f ? v : 0.f;
+    }
+}
+// O = A2 W3 + b3: one wave per row, lanes striding the hidden units
+__global__ __launch_bounds__(256) void k_nl_out_fwd(const float* __restrict__ A2, const float* __restrict__ W3,
+                                                    const float* __restrict__ b3, float* __restrict__ O, int rows,
+                                                    int h2, int nout) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (r >= rows) return;
+    float acc[NL_MAXOUT] = {0.f, 0.f, 0.f, 0.f};
+    for (int i = lane; i < h2; i += 64) {
+        const float a = bfr(A2[(int64_t)r * h2 + i]);
+#pragma unroll
+        for (int j = 0; j < NL_MAXOUT; ++j)
+            if (j < nout) acc[j] += a * bfr(W3[(int64_t)i * nout + j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NL_MAXOUT; ++j) {
+        float v = acc[j];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (j < nout && lane == 0) O[(int64_t)r * nout + j] = v + b3[j];
+    }
+}
+// Output layer backward: dZ2 = (dO W3^T) * [A2 > 0].  Workgroup (bx, by): hidden units
+// 64 bx .. 64 bx + 63 over row split `by`; thread -> unit i = 64 bx + (tid & 63) and rows
+// q, q + 4, ... of the split (q = tid >> 6).  The four row groups' sums of A2^T dO are
+// combined in order in LDS into part[by][i][j]; the column sums of dO (bias gradient) of
+// the split go to part[nsplit * h2 * nout + by * nout + j] from the workgroup bx = 0.
+__global__ __launch_bounds__(256) void k_nl_out_bwd(const float* __restrict__ A2, const float* __restrict__ dO,
+                                                    const float* __restrict__ W3, float* __restrict__ dZ2,
+                                                    float* __restrict__ part, int rows, int h2, int nout, int rps) {
+    __shared__ float red[4][64][NL_MAXOUT];
+    __shared__ float redb[4][64][NL_MAXOUT];
+    const int lc = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lc, by = blockIdx.y, nsplit = gridDim.y;
+    const bool on = i < h2;
+    float w[NL_MAXOUT], aw[NL_MAXOUT] = {0.f, 0.f, 0.f, 0.f}, ab[NL_MAXOUT] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < NL_MAXOUT; ++j) w[j] = (on && j < nout) ? bfr(W3[(int64_t)i * nout + j]) : 0.f;
+    const int r0 = by * rps, r1 = min(rows, r0 + rps);
+    for (int r = r0 + q; r < r1; r += 4) {
+        const float a = on ? A2[(int64_t)r * h2 + i] : 0.f, a16 = bfr(a);
+        float d = 0.f;
+#pragma unroll
+        for (int j = 0; j < NL_MAXOUT; ++j)
+            if (j < nout) {
+                const float o = dO[(int64_t)r * nout + j], o16 = bfr(o);
+                d += o16 * w[j];
+                aw[j] += a16 * o16;
+                ab[j] += o;
+            }
+        if (on) dZ2[(int64_t)r * h2 + i] = a > 0.f ? d : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < NL_MAXOUT; ++j) {
+        red[q][lc][j] = aw[j];
+        redb[q][lc][j] = ab[j];
+    }
+    __syncthreads();
+    if (q == 0 && on) {
+#pragma unroll
+        for (int j = 0; j < NL_MAXOUT; ++j)
+            if (j < nout) {
+                part[((int64_t)by * h2 + i) * nout + j] = ((red[0][lc][j] + red[1][lc][j]) + red[2][lc][j]) + red[3][lc][j];
+                if (i == 0)
+                    part[(int64_t)nsplit * h2 * nout + by * nout + j] =
+                        ((redb[0][lc][j] + redb[1][lc][j]) + redb[2][lc][j]) + redb[3][lc][j];
+            }
+    }
+}
+// Input layer backward: X^T dZ1 (nin x h1) and the column sums of dZ1, per row split, into
+// part[by][k][c] (k = nin: the bias row).  Workgroup (bx, by): hidden units 64 bx .. + 63;
+// thread -> unit c and rows q, q + 4, ... of the split, combined in order in LDS.
+__global__ __launch_bounds__(256) void k_nl_in_bwd(const float* __restrict__ X, const float* __restrict__ dZ1,
+                                                   float* __restrict__ part, int rows, int nin, int h1, int rps) {
+    __shared__ float red[4][NL_MAXIN + 1][64];
+    const int lc = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lc, by = blockIdx.y;
+    const bool on = c < h1;
+    float acc[NL_MAXIN + 1];
+#pragma unroll
+    for (int k = 0; k <= NL_MAXIN; ++k) acc[k] = 0.f;
+    const int r0 = by * rps, r1 = min(rows, r0 + rps);
+    for (int r = r0 + q; r < r1; r += 4) {
+        const float d = on ? dZ1[(int64_t)r * h1 + c] : 0.f, d16 = bfr(d);
+#pragma unroll
+        for (int k = 0; k < NL_MAXIN; ++k)
+            if (k < nin) acc[k] += bfr(X[(int64_t)r * nin + k]) * d16;
+        acc[NL_MAXIN] += d;
+    }
+#pragma unroll
+    for (int k = 0; k <= NL_MAXIN; ++k) red[q][k][lc] = acc[k];
+    __syncthreads();
+    if (q != 0 || !on) return;
+    float* pb = part + (int64_t)by * (nin + 1) * h1;
+#pragma unroll
+    for (int k = 0; k <= NL_MAXIN; ++k) {
+        const int kk = k < nin ? k : (k == NL_MAXIN ? nin : -1);
+        if (kk >= 0) pb[(int64_t)kk * h1 + c] = ((red[0][k][lc] + red[1][k][lc]) + red[2][k][lc]) + red[3][k][lc];
+    }
+}
+// out[e] = sum over the nsplit partial copies (stride n) of part, in a fixed order: four
+// thread groups take copies q, q + 4, ... (q = tid >> 6) of 64 consecutive elements,
+// combined in order in LDS
+__global__ __launch_bounds__(256) void k_nl_sum(const float* __restrict__ part, int nsplit, int64_t n,
+                                                float* __restrict__ out) {
+    __shared__ float red[4][64];
+    const int lc = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t e = (int64_t)blockIdx.x * 64 + lc;
+    float v = 0.f;
+    if (e < n) {
+#pragma unroll 8
+        for (int k = q; k < nsplit; k += 4) v += part[(int64_t)k * n + e];
+    }
+    red[q][lc] = v;
+    __syncthreads();
+    if (q == 0 && e < n) out[e] = ((red[0][lc] + red[1][lc]) + red[2][lc]) + red[3][lc];
 }
 
 // ---- per-coordinate features of a packed uneven batch --------------------------
@@ -698,9 +860,33 @@ using namespace cdm;
         }                                                                                   \
     } while (0)
 
+// The narrow-layer path (nin <= 16, nout <= 4): the input and output layers on the
+// kernels above, the hidden layer's ReLU in its GEMM's epilogue, and the ReLU masks of
+// the backward pass taken from the activations (A > 0 exactly where Z > 0), so Z1 and Z2
+// are not formed; their buffers hold the split partials of the weight gradients.
+static bool mlp_narrow(const cdm_mlp* n) { return n->nin <= NL_MAXIN && n->nout <= NL_MAXOUT; }
+static int mlp_splits(int rows, int64_t per_split, int64_t cap) {
+    // row splits for the gradient partials (64 rows each, at most 256), within `cap`
+    // floats of scratch
+    int64_t s = std::min<int64_t>(256, std::max<int64_t>(1, rows / 64));
+    s = std::min<int64_t>(s, std::max<int64_t>(1, cap / per_split));
+    return (int)s;
+}
+
 static hipError_t mlp_forward(cdm_mlp* n, const float* X, int rows, hipStream_t st) {
     hipError_t e;
     float* w = n->w;
+    if (mlp_narrow(n)) {
+        hipLaunchKernelGGL(k_nl_in_fwd, dim3((n->h1 + 63) / 64, (rows + NL_RB - 1) / NL_RB), dim3(256), 0, st, X,
+                           (const float*)(w + n->oW1), (const float*)(w + n->ob1), n->A1, rows, n->nin, n->h1);
+        if ((e = hipGetLastError())) return e;
+        if ((e = launch_gemm_bf16(n->A1, n->h1, 1, w + n->oW2, n->h2, 1, n->A2, n->h2, rows, n->h2, n->h1, w + n->ob2, 0, st,
+                                  n->splitk, n->splitk_floats, 1, nullptr)))
+            return e;
+        hipLaunchKernelGGL(k_nl_out_fwd, dim3((rows + 3) / 4), dim3(256), 0, st, (const float*)n->A2,
+                           (const float*)(w + n->oW3), (const float*)(w + n->ob3), n->O, rows, n->h2, n->nout);
+        return hipGetLastError();
+    }
     if ((e = launch_gemm_bf16(X, n->nin, 1, w + n->oW1, n->h1, 1, n->Z1, n->h1, rows, n->h1, n->nin, w + n->ob1, 0, st, n->splitk, n->splitk_floats)))
         return e;
     if ((e = launch_relu(n->Z1, n->A1, (int64_t)rows * n->h1, st))) return e;
@@ -718,6 +904,39 @@ static hipError_t mlp_backward(cdm_mlp* n, const float* X, const float* T, int r
     float* g = n->g;
     const int64_t no = (int64_t)rows * n->nout;
     if ((e = launch_mse(n->O, T, n->dO, no, 1.f / (float)no, n->part, st))) return e;
+    if (mlp_narrow(n)) {
+        const int64_t cap3 = (int64_t)n->max_rows * n->h2, cap1 = (int64_t)n->max_rows * n->h1;
+        // layer 3: dZ2, the weight and bias gradient partials (scratch: Z2)
+        const int s3 = mlp_splits(rows, (int64_t)n->h2 * n->nout + n->nout, cap3);
+        const int rps3 = (rows + s3 - 1) / s3;
+        hipLaunchKernelGGL(k_nl_out_bwd, dim3((n->h2 + 63) / 64, s3), dim3(256), 0, st, (const float*)n->A2,
+                           (const float*)n->dO, (const float*)(w + n->oW3), n->dZ2, n->Z2, rows, n->h2, n->nout, rps3);
+        if ((e = hipGetLastError())) return e;
+        const int64_t n3 = (int64_t)n->h2 * n->nout;
+        hipLaunchKernelGGL(k_nl_sum, dim3((unsigned)((n3 + 63) / 64)), dim3(256), 0, st, (const float*)n->Z2, s3, n3,
+                           g + n->oW3);
+        hipLaunchKernelGGL(k_nl_sum, dim3(1), dim3(256), 0, st, (const float*)(n->Z2 + (int64_t)s3 * n3), s3,
+                           (int64_t)n->nout, g + n->ob3);
+        if ((e = hipGetLastError())) return e;
+        // layer 2 (matrix cores): weight gradient, bias gradient, dZ1 = (dZ2 W2^T) * [A1 > 0]
+        if ((e = launch_gemm_bf16(n->A1, 1, n->h1, n->dZ2, n->h2, 1, g + n->oW2, n->h2, n->h1, n->h2, rows, nullptr, 0, st,
+                                  n->splitk, n->splitk_floats)))
+            return e;
+        if ((e = launch_colsum(n->dZ2, rows, n->h2, g + n->ob2, n->cpart, st))) return e;
+        if ((e = launch_gemm_bf16(n->dZ2, n->h2, 1, w + n->oW2, 1, n->h2, n->dZ1, n->h1, rows, n->h1, n->h2, nullptr, 0, st,
+                                  n->splitk, n->splitk_floats, 0, n->A1)))
+            return e;
+        // layer 1: weight and bias gradient partials (scratch: Z1)
+        const int s1 = mlp_splits(rows, (int64_t)(n->nin + 1) * n->h1, cap1);
+        const int rps1 = (rows + s1 - 1) / s1;
+        hipLaunchKernelGGL(k_nl_in_bwd, dim3((n->h1 + 63) / 64, s1), dim3(256), 0, st, X, (const float*)n->dZ1, n->Z1,
+                           rows, n->nin, n->h1, rps1);
+        if ((e = hipGetLastError())) return e;
+        const int64_t n1 = (int64_t)(n->nin + 1) * n->h1;   // W1 (nin x h1) then b1 (h1): contiguous in g
+        hipLaunchKernelGGL(k_nl_sum, dim3((unsigned)((n1 + 63) / 64)), dim3(256), 0, st, (const float*)n->Z1, s1, n1,
+                           g + n->oW1);
+        return hipGetLastError();
+    }
     // layer 3
     if ((e = launch_gemm_bf16(n->A2, 1, n->h2, n->dO, n->nout, 1, g + n->oW3, n->nout, n->h2, n->nout, rows, nullptr, 0, st, n->splitk, n->splitk_floats)))
         return e;
