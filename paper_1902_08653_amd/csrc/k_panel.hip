@@ -639,22 +639,26 @@ __global__ void k_sum_splits(const V* __restrict__ part, int nsplit, int64_t n, 
 // look-ahead schedule then forms delta_K = M_K q_K + (-Y_K) delta_{K-1} in one product
 // instead of correcting b first).  One workgroup per panel; M_K (packed lower, column
 // by column) and X_K (column-major) are read into LDS before any result is written.
-template <int KP>
-__global__ __launch_bounds__(256) void k_fold_mx(const double2* __restrict__ M, double2* __restrict__ X) {
+template <typename V, int KP>
+__global__ __launch_bounds__(256) void k_fold_mx(const V* __restrict__ M, V* __restrict__ X) {
     constexpr int NE = KP * (KP + 1) / 2;
-    __shared__ double2 Ms[NE];
-    __shared__ double2 Xs[KP * KP];
+    __shared__ V Ms[NE];
+    __shared__ V Xs[KP * KP];
     const int64_t K = blockIdx.x;
-    const double2* Mk = M + K * NE;
-    double2* Xk = X + K * KP * KP;
+    const V* Mk = M + K * NE;
+    V* Xk = X + K * KP * KP;
     for (int i = threadIdx.x; i < NE; i += 256) Ms[i] = Mk[i];
     for (int i = threadIdx.x; i < KP * KP; i += 256) Xs[i] = Xk[i];
     __syncthreads();
     for (int i = threadIdx.x; i < KP * KP; i += 256) {
         const int v = i / KP, j = i % KP;   // element (j, v), stored at v * KP + j
-        double2 acc = make_double2(0.0, 0.0);
+        V acc;
+        acc.x = 0;
+        acc.y = 0;
         for (int u = 0; u <= j; ++u) cfma(acc, Ms[u * KP - (u * (u - 1)) / 2 + (j - u)], Xs[v * KP + u]);
-        Xk[i] = make_double2(-acc.x, -acc.y);
+        acc.x = -acc.x;
+        acc.y = -acc.y;
+        Xk[i] = acc;
     }
 }
 
@@ -688,11 +692,9 @@ static hipError_t launch_gram_cross_t(const GramLaunch& L, void* X, hipStream_t 
                        (const cv<T>*)L.gpart, L.nsplit, n, L.kp, (cv<T>*)X);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if constexpr (sizeof(T) == 8) {
-        if (fold && L.kp == 64) {   // the configuration whose look-ahead forms b locally
-            hipLaunchKernelGGL(k_fold_mx<64>, dim3(L.npanels), dim3(256), 0, st, (const double2*)L.M, (double2*)X);
-            e = hipGetLastError();
-        }
+    if (fold && L.kp == 64) {   // the configurations whose look-ahead forms b locally
+        hipLaunchKernelGGL((k_fold_mx<cv<T>, 64>), dim3(L.npanels), dim3(256), 0, st, (const cv<T>*)L.M, (cv<T>*)X);
+        e = hipGetLastError();
     }
     return e;
 }

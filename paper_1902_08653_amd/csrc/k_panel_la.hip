@@ -679,19 +679,21 @@ static int la_coresident_t() {
     return per * ncu;
 }
 
-// Look-ahead configurations: complex128 with 64-column panels, complex64 (and the
-// FP32 inner solve of the mixed path) with 128-column panels; one 64-row block per
-// workgroup.
+// Look-ahead configurations, one 64-row block per workgroup: complex128 and complex64
+// with 64-column panels (b formed locally), the FP32 inner solve of the mixed path with
+// 128-column panels (correction at the reducers).
 hipError_t launch_panel_la(const PanelLaunch& L, hipStream_t st) {
     if (L.rpl != 1) return hipErrorInvalidValue;
     if (L.c128 && L.kp == 64) return launch_la_t<double, 64, 1>(L, st);
     if (!L.c128 && L.kp == 128) return launch_la_t<float, 128, 1>(L, st);
+    if (!L.c128 && L.kp == 64) return launch_la_t<float, 64, 1>(L, st);
     return hipErrorInvalidValue;
 }
 
 int panel_la_max_coresident(bool c128, int kp) {
     if (c128 && kp == 64) return la_coresident_t<double, 64, 1>();
     if (!c128 && kp == 128) return la_coresident_t<float, 128, 1>();
+    if (!c128 && kp == 64) return la_coresident_t<float, 64, 1>();
     return 0;
 }
 

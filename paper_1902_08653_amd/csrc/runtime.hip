@@ -588,7 +588,10 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         bool found = false;
         if (!(d.flags & CDM_F_NO_LOOKAHEAD)) {
             // look-ahead schedule: 64-row blocks, one reducer workgroup per panel column
-            const int kp = p->c128 ? 64 : 128;
+            // 64-column panels with b formed locally (complex128, complex64); the mixed
+            // path's FP32 inner solve over a 2- or 1-byte copy takes 128-column panels,
+            // whose chain steps are as fast and half as many
+            const int kp = mixed ? 128 : 64;
             const int P = (d.B + 63) / 64;
             if ((!d.panel || d.panel == kp) && P >= kp && P <= 256 && P <= panel_la_max_coresident(p->c128, kp) &&
                 16 + P + kp <= kCtrWords) {
