@@ -102,6 +102,63 @@ template <int N> __device__ __forceinline__ double row_shl(double x) {
 template <int N> __device__ __forceinline__ float row_shl(float x) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x100 | N, 0xF, 0xF, true));
 }
+// v of lane (i + N) mod 16 within the lane's row of 16: DPP row_ror
+template <int N> __device__ __forceinline__ double row_ror(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x120 | N, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x120 | N, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int N> __device__ __forceinline__ float row_ror(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x120 | N, 0xF, 0xF, false));
+}
+// Rows of 16 (G = 16) or halves of the wave (G = 32) exchanged by gfx950's permlane
+// swaps: with both operands v, the first result holds the even rows (lower half) in
+// both places and the second the odd rows (upper half), so their sum is the same in
+// every lane.
+template <int G> __device__ __forceinline__ void swap_pair(uint32_t v, uint32_t& a, uint32_t& b) {
+    if constexpr (G == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        a = r[0];
+        b = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        a = r[0];
+        b = r[1];
+    }
+}
+template <int G> __device__ __forceinline__ double swap_add(double x) {
+    uint32_t al, bl, ah, bh;
+    swap_pair<G>((uint32_t)__double2loint(x), al, bl);
+    swap_pair<G>((uint32_t)__double2hiint(x), ah, bh);
+    return __hiloint2double((int)ah, (int)al) + __hiloint2double((int)bh, (int)bl);
+}
+template <int G> __device__ __forceinline__ float swap_add(float x) {
+    uint32_t a, b;
+    swap_pair<G>(__float_as_uint(x), a, b);
+    return __uint_as_float(a) + __uint_as_float(b);
+}
+// Sum over the lanes that agree in their low log2(G) bits (G a power of two): rotations
+// within rows of 16, then the row and half-wave swaps.  Every lane of a group ends with
+// the same value (each step adds the same two operands in every lane of a pair).
+template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
+    if constexpr (G < 16) {
+        v += row_ror<G>(v);
+        return group_sum<2 * G>(v);
+    } else if constexpr (G < 64) {
+        return group_sum<2 * G>(swap_add<G>(v));
+    } else {
+        return v;
+    }
+}
+// value of lane l (uniform l) in every lane
+__device__ __forceinline__ double lane_value(double x, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+__device__ __forceinline__ float lane_value(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
 // Transpose-reduce of 4 values per lane (as wave_transpose_sum<T, 4>): the two exchange
 // levels across half- and quarter-waves, then the sum over each row of 16 lanes by DPP
 // shifts into the row's first lane (lanes 0, 16, 32, 48 hold the four sums)
