@@ -102,9 +102,21 @@ __global__ void k_mx_rows(const double2* __restrict__ H, int64_t ld, int B, int 
     const int u0 = blockIdx.y * cols_per_chunk;
     const int u1 = min(U, u0 + cols_per_chunk);
     if (row >= B) return;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int u = u0; u < u1; ++u) cfma(acc, H[(int64_t)u * ld + row], x[u]);
-    rpart[(int64_t)blockIdx.y * B + row] = acc;
+    // eight columns per round: their loads are in flight together
+    double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
+    int u = u0;
+    for (; u + 8 <= u1; u += 8) {
+        double2 h[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) h[k] = H[(int64_t)(u + k) * ld + row];
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) {
+            cfma(a0, h[k], x[u + k]);
+            cfma(a1, h[k + 1], x[u + k + 1]);
+        }
+    }
+    for (; u < u1; ++u) cfma(a0, H[(int64_t)u * ld + row], x[u]);
+    rpart[(int64_t)blockIdx.y * B + row] = make_double2(a0.x + a1.x, a0.y + a1.y);
 }
 
 // r = y - sum of the chunk partials (fixed order)

@@ -114,13 +114,14 @@ def test_lookahead_tolerance_mode(dev, orc, prec):
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 def test_lookahead_mixed_refinement(dev, orc, prec):
-    """Mixed precision on the look-ahead inner solves reaches the FP64 solution."""
+    """Mixed precision on the look-ahead inner solves reaches the FP64 solution, to the
+    1e-10 bar of the full-size mixed forms."""
     inst = inputs.dense_uplink(8192, 1000, 21)
-    x, rec, desc = solve(dev, inst.H, inst.y, prec, 60, tol=1e-11)
+    x, rec, desc = solve(dev, inst.H, inst.y, prec, 60, tol=1e-12)
     assert '"schedule": "lookahead"' in desc, desc
     ref = orc.local_cd(inst.H, inst.y, 0.1, 2000, tol=1e-14)
-    assert rec["flags"] == 0
-    assert relerr(x, ref["x"]) <= 1e-9
+    assert rec["flags"] == 0 and rec["rel_step"] <= 1e-12
+    assert relerr(x, ref["x"]) <= 1e-10
 
 
 # complex128, two panels ahead: three panels, a ragged fourth, many panels
