@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # kernel hash to the recorded value.
 TRAFFIC = {
     ("k_cd_panel_la", "c128 16384x8192 tol 1e-11"): {
-        "sources": ['paper_1902_08653_amd/csrc/k_panel_la.hip', 'paper_1902_08653_amd/csrc/la_common.hpp', 'paper_1902_08653_amd/csrc/panel.hpp', 'paper_1902_08653_amd/csrc/common.hpp'], "sha256_16": "83ca0521931cc281", "bytes": 143080384512.0},
+        "sources": ['paper_1902_08653_amd/csrc/k_panel_la.hip', 'paper_1902_08653_amd/csrc/la_common.hpp', 'paper_1902_08653_amd/csrc/panel.hpp', 'paper_1902_08653_amd/csrc/common.hpp'], "sha256_16": "7c6f7e01785c5fb6", "bytes": 143080384512.0},
     ("k_cd_wg", "c64 batch 4096 tol 1e-06"): {
         "sources": ['paper_1902_08653_amd/csrc/k_wg.hip', 'paper_1902_08653_amd/csrc/common.hpp', 'paper_1902_08653_amd/csrc/wg.hpp'], "sha256_16": "0250e54ccc4fc8b0", "bytes": 713278845676.0},
     ("k_cd_sparse", "c128 16384x8192 0.01 tol 1e-11"): {

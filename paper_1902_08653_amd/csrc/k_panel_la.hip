@@ -8,29 +8,37 @@
 //     X_{K+1} = H_{K+1}^H H_K  (formed once per solve, next to M).
 // The exchange of panel K+1's partials thereby overlaps the wait for panel K's
 // reduced b.  In exact arithmetic every delta equals the sequential sweep's.
-// Where X_K fits the LDS next to M (complex128, 64-column panels) the reducers publish
+// Where X_K fits the LDS next to M (64-column panels) the reducers publish
 // q_K = H_K^H r - lambda x_K as soon as the partials are in, and every workgroup forms
 // delta_K = M_K (q_K - X_K delta_{K-1}) = M_K q_K - Y_K delta_{K-1} itself, in one
 // product, from -Y_K = -M_K X_K (formed once per solve in place of X_K) staged in LDS:
 // the chain from one panel's delta to the next panel's then stays inside the
 // workgroup, and the cross-workgroup exchange runs a panel ahead of it.  Otherwise
-// (64 KB of X_K would not fit) the reducers apply the correction and publish b_K.
+// (X_K would not fit: 128-column FP32 panels) the reducers apply the correction and
+// publish b_K.
 //
-// Workgroup: 8 tile waves, one control wave and (complex128) one X-staging wave,
+// Workgroup: 8 tile waves, one control wave and (local b) one X-staging wave,
 // decoupled.
 //  * Tile waves own the rows (lane = row) and NC panel columns each.  They keep
 //    three panels in registers (K for the update, K+1 already reduced, K+2 for the
 //    next look-ahead partials) and stream a fourth behind them; they touch global
 //    memory only to stream H.  Per step: wait for b_K in LDS, delta_K = M_K b_K,
 //    r -= H_K delta_K, prefetch panel K+3, partials of panel K+2 from the new r.
+//    FP32 panels: each wave forms the delta of its own columns, summed across its
+//    lanes; complex128: each wave forms a slice of every column's delta, the slices
+//    summed through LDS.
 //  * The control wave does every cross-workgroup exchange: it publishes the tile
 //    waves' partials, gathers b_K into LDS (with M_K, staged by LDS-direct loads),
 //    keeps the stop statistics, and in the reducer workgroups (w < KP; reducer w
 //    owns panel column j = w) sums the P partials of its column and publishes b.
-//  * The X-staging wave (complex128) moves -Y_K of the next step into LDS with
-//    LDS-direct loads as soon as the tile waves have read the current one.  A wave
-//    that issues such loads waits for them to land before its next LDS access, so
-//    they are kept out of the control wave's loop.
+//    complex128: b_K and M_K at the top of step K, after the previous partials are
+//    out; FP32 panels: during the step before, in one attempt once half of the tile
+//    waves have their partials (the tile waves then go on without waiting for the
+//    control wave to publish them).
+//  * The X-staging wave moves -Y_K of the next step into LDS with LDS-direct loads
+//    as soon as the tile waves have read the current one.  A wave that issues such
+//    loads waits for them to land before its next LDS access, so they are kept out
+//    of the control wave's loop.
 //  * The waves meet only through LDS words (sequence counters), never at a
 //    workgroup barrier, so a reducer's wait for partials does not hold back its own
 //    tile waves.  The tile waves synchronise among themselves with an LDS arrival
