@@ -64,8 +64,10 @@ def oracle_in(H, y, prec):
 
 # (B, U): the look-ahead needs B >= 64 * panel width: 64 * 64 for complex128 and complex64
 # (64-column panels), 64 * 128 for the mixed forms' FP32 inner solve (128-column panels)
+# (complex64 and the mixed forms' inner solve gather b of the next step during the step, with
+# their own paths for one panel, whose next b needs this step's x, and for two panels)
 CASES = [("c128", 4096, 1000), ("c128", 4160, 64), ("c128", 4096, 37), ("c64", 8192, 1000), ("c64", 8192, 200),
-         ("c64", 4096, 700)]
+         ("c64", 4096, 700), ("c64", 4096, 64), ("c64", 4160, 37), ("c64", 4096, 100)]
 
 
 @pytest.mark.parametrize("prec,B,U", CASES)
@@ -117,6 +119,18 @@ def test_lookahead_mixed_refinement(dev, orc, prec):
     """Mixed precision on the look-ahead inner solves reaches the FP64 solution, to the
     1e-10 bar of the full-size mixed forms."""
     inst = inputs.dense_uplink(8192, 1000, 21)
+    x, rec, desc = solve(dev, inst.H, inst.y, prec, 60, tol=1e-12)
+    assert '"schedule": "lookahead"' in desc, desc
+    ref = orc.local_cd(inst.H, inst.y, 0.1, 2000, tol=1e-14)
+    assert rec["flags"] == 0 and rec["rel_step"] <= 1e-12
+    assert relerr(x, ref["x"]) <= 1e-10
+
+
+@pytest.mark.parametrize("prec,U", [("bf16", 100), ("fp8", 128), ("bf16", 200), ("fp8", 250)])
+def test_lookahead_mixed_one_or_two_panels(dev, orc, prec, U):
+    """The mixed forms' inner solve (128-column FP32 panels) with one panel (ragged and
+    full) and two panels (the second ragged), to the FP64 solution at the 1e-10 bar."""
+    inst = inputs.dense_uplink(8192, U, 31 + U)
     x, rec, desc = solve(dev, inst.H, inst.y, prec, 60, tol=1e-12)
     assert '"schedule": "lookahead"' in desc, desc
     ref = orc.local_cd(inst.H, inst.y, 0.1, 2000, tol=1e-14)
