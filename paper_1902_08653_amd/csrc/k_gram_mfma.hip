@@ -267,22 +267,41 @@ hipError_t launch_gram_lp(const GramLaunch& L, bool cross, int dist, hipStream_t
     return hipGetLastError();
 }
 
-// ---- complex128 -------------------------------------------------------------------
-// The same block partials for complex128 H on v_mfma_f64_16x16x4_f64 (four rows per
-// instruction, FP64 FMA).  gfx950's FP64 matrix rate equals its FP64 vector rate, so
-// this gains by issue: one instruction does the work of sixteen wave-wide FMAs, from
-// four 8-byte operands per lane.  Staging: 32 rows of two 64-column tiles per step, split
-// into Re and Im planes, column by column with a pitch of 34 doubles: the staging writes
-// (consecutive rows) and the fragment reads (16 columns x 2 rows per half-wave) are then
-// conflict-free.
-typedef double f64x4_t __attribute__((ext_vector_type(4)));
+// ---- complex128 and complex64 -------------------------------------------------------
+// The same block partials for complex H on v_mfma_f64_16x16x4_f64 (complex128) or
+// v_mfma_f32_16x16x4_f32 (complex64): four rows per instruction, FMA in the element's
+// precision.  gfx950's FP64 and FP32 matrix rates equal their vector rates, so this gains
+// by issue: one instruction does the work of sixteen wave-wide FMAs, from four operands
+// per lane.  Staging: 32 rows of two 64-column tiles per step, split into Re and Im
+// planes, column by column with a pitch of 34 elements: the staging writes (consecutive
+// rows) and the fragment reads (16 columns x 2 rows per half-wave) are then
+// conflict-free.  The two forms differ only in where the output rows sit: lane l holds
+// rows (l >> 4) + 4 e of column l & 15 in the FP64 form, and rows 4 (l >> 4) + e in the
+// FP32 one.
+template <typename T> struct CxMfma;
+template <> struct CxMfma<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int e) { return (lane >> 4) + 4 * e; }
+};
+template <> struct CxMfma<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int e) { return 4 * (lane >> 4) + e; }
+};
 constexpr int G64_KS = 32, G64_PITCH = 34;
 
-template <bool CROSS>
-__global__ __launch_bounds__(256) void k_gram_f64(const double2* __restrict__ H, int64_t ld, int B, int U, int kp,
-                                                  int nsub, int rows_per_split, double2* __restrict__ gpart,
-                                                  int npanels, int dist) {
-    __shared__ double tile[4][64 * G64_PITCH];   // A re, A im, B re, B im
+template <typename T, bool CROSS>
+__device__ __forceinline__ void gram_cx(const cv<T>* __restrict__ H, int64_t ld, int B, int U, int kp, int nsub,
+                                        int rows_per_split, cv<T>* __restrict__ gpart, int npanels, int dist) {
+    using V = cv<T>;
+    using MM = CxMfma<T>;
+    using acc_t = typename MM::acc_t;
+    __shared__ T tile[4][64 * G64_PITCH];   // A re, A im, B re, B im
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
@@ -308,15 +327,15 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double2* __restrict__ H,
 
     // thread -> row r0 + (tid & 31), columns (tid >> 5) + 8 k of a tile; the next step's
     // values are loaded into registers while this step computes
-    auto fetch = [&](double2 (&v)[8], int c0, int r0) {
+    auto fetch = [&](V (&v)[8], int c0, int r0) {
         const int row = r0 + (tid & 31);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int col = c0 + (tid >> 5) + 8 * k;
-            v[k] = (row < r_hi && col < U) ? ld_nt(H + (int64_t)col * ld + row) : make_double2(0.0, 0.0);
+            v[k] = (row < r_hi && col < U) ? ld_nt(H + (int64_t)col * ld + row) : czero<T>();
         }
     };
-    auto put = [&](const double2 (&v)[8], double* tr, double* ti) {
+    auto put = [&](const V (&v)[8], T* tr, T* ti) {
         const int i = tid & 31;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -327,17 +346,17 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double2* __restrict__ H,
     };
 
     const int qi = wv >> 1, qj = wv & 1;
-    f64x4_t accr[2][2], acci[2][2];
+    acc_t accr[2][2], acci[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            accr[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
-            acci[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+            accr[i][j] = acc_t{T(0), T(0), T(0), T(0)};
+            acci[i][j] = acc_t{T(0), T(0), T(0), T(0)};
         }
-    const double* Bre = same ? tile[0] : tile[2];
-    const double* Bim = same ? tile[1] : tile[3];
-    double2 va[8], vb[8];
+    const T* Bre = same ? tile[0] : tile[2];
+    const T* Bim = same ? tile[1] : tile[3];
+    V va[8], vb[8];
     if (r_lo < r_hi) {
         fetch(va, colA0, r_lo);
         if (!same) fetch(vb, colB0, r_lo);
@@ -353,7 +372,7 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double2* __restrict__ H,
 #pragma unroll 2
         for (int k0 = 0; k0 < G64_KS; k0 += 4) {
             const int rk = k0 + (lane >> 4);   // this lane's row of the 4-row step
-            double ar[2], ai[2], br[2], bm[2];
+            T ar[2], ai[2], br[2], bm[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const int cu = 32 * qi + 16 * i + (lane & 15);
@@ -367,17 +386,15 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double2* __restrict__ H,
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
-                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bm[j], accr[i][j], 0, 0, 0);
-                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bm[j], acci[i][j], 0, 0, 0);
-                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], br[j], acci[i][j], 0, 0, 0);
+                    accr[i][j] = MM::mma(ar[i], br[j], accr[i][j]);
+                    accr[i][j] = MM::mma(ai[i], bm[j], accr[i][j]);
+                    acci[i][j] = MM::mma(ar[i], bm[j], acci[i][j]);
+                    acci[i][j] = MM::mma(-ai[i], br[j], acci[i][j]);
                 }
         }
         __syncthreads();
     }
-    // D[16 x 16] of the FP64 form: lane holds rows (lane >> 4) + 4 e, e = 0..3, of column
-    // lane & 15 (interleaved, unlike the 4 consecutive rows of the FP32-output forms)
-    double2* out = gpart + ((int64_t)split * npanels + K) * kp * kp;
+    V* out = gpart + ((int64_t)split * npanels + K) * kp * kp;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -385,25 +402,47 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double2* __restrict__ H,
             const int v = 32 * qj + 16 * j + (lane & 15);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int u = 32 * qi + 16 * i + (lane >> 4) + 4 * e;
-                out[(int64_t)(bi * 64 + u) * kp + bj * 64 + v] = make_double2(accr[i][j][e], acci[i][j][e]);
+                const int u = 32 * qi + 16 * i + MM::row(lane, e);
+                out[(int64_t)(bi * 64 + u) * kp + bj * 64 + v] = cmake<T>(accr[i][j][e], acci[i][j][e]);
             }
         }
 }
 
-hipError_t launch_gram_f64(const GramLaunch& L, bool cross, int dist, hipStream_t st) {
-    if (!L.c128 || L.src_kind != SRC_COMPLEX || L.kp % 64 != 0 || L.nsplit < 1) return hipErrorInvalidValue;
+template <bool CROSS>
+__global__ __launch_bounds__(256) void k_gram_f64(const double2* __restrict__ H, int64_t ld, int B, int U, int kp,
+                                                  int nsub, int rows_per_split, double2* __restrict__ gpart,
+                                                  int npanels, int dist) {
+    gram_cx<double, CROSS>(H, ld, B, U, kp, nsub, rows_per_split, gpart, npanels, dist);
+}
+template <bool CROSS>
+__global__ __launch_bounds__(256) void k_gram_f32(const float2* __restrict__ H, int64_t ld, int B, int U, int kp,
+                                                  int nsub, int rows_per_split, float2* __restrict__ gpart,
+                                                  int npanels, int dist) {
+    gram_cx<float, CROSS>(H, ld, B, U, kp, nsub, rows_per_split, gpart, npanels, dist);
+}
+
+hipError_t launch_gram_cx(const GramLaunch& L, bool cross, int dist, hipStream_t st) {
+    if (L.src_kind != SRC_COMPLEX || L.kp % 64 != 0 || L.nsplit < 1) return hipErrorInvalidValue;
     const int nb = L.kp / 64;
     const int nsub = cross ? nb * nb : nb * (nb + 1) / 2;
     int rps = (L.B + L.nsplit - 1) / L.nsplit;
     rps = (rps + G64_KS - 1) / G64_KS * G64_KS;
     const dim3 grid(L.npanels * nsub, L.nsplit);
-    if (cross)
-        hipLaunchKernelGGL((k_gram_f64<true>), grid, dim3(256), 0, st, (const double2*)L.H, L.ld, L.B, L.U, L.kp, nsub,
-                           rps, (double2*)L.gpart, L.npanels, dist);
-    else
-        hipLaunchKernelGGL((k_gram_f64<false>), grid, dim3(256), 0, st, (const double2*)L.H, L.ld, L.B, L.U, L.kp,
-                           nsub, rps, (double2*)L.gpart, L.npanels, dist);
+    if (L.c128) {
+        if (cross)
+            hipLaunchKernelGGL((k_gram_f64<true>), grid, dim3(256), 0, st, (const double2*)L.H, L.ld, L.B, L.U, L.kp,
+                               nsub, rps, (double2*)L.gpart, L.npanels, dist);
+        else
+            hipLaunchKernelGGL((k_gram_f64<false>), grid, dim3(256), 0, st, (const double2*)L.H, L.ld, L.B, L.U, L.kp,
+                               nsub, rps, (double2*)L.gpart, L.npanels, dist);
+    } else {
+        if (cross)
+            hipLaunchKernelGGL((k_gram_f32<true>), grid, dim3(256), 0, st, (const float2*)L.H, L.ld, L.B, L.U, L.kp,
+                               nsub, rps, (float2*)L.gpart, L.npanels, dist);
+        else
+            hipLaunchKernelGGL((k_gram_f32<false>), grid, dim3(256), 0, st, (const float2*)L.H, L.ld, L.B, L.U, L.kp,
+                               nsub, rps, (float2*)L.gpart, L.npanels, dist);
+    }
     return hipGetLastError();
 }
 

@@ -7,9 +7,8 @@
 //     delta_u = (b_u - sum_{v<u, v in K} G_uv delta_v) / (||h_u||^2 + lambda),
 // i.e. (D + L) delta_K = b_K: exactly the same numbers, in exact arithmetic, as
 // running the u-loop of Algorithm 1 one coordinate at a time.  Here
-// M_K = (D + L)^-1 is formed once per solve (the panel Gram blocks -- on the matrix
-// cores for complex128 and the low-precision copies, k_gram_mfma.hip; k_gram_partial
-// for complex64 -- then k_gram_invert), and every sweep applies
+// M_K = (D + L)^-1 is formed once per solve (the panel Gram blocks on the matrix
+// cores, k_gram_mfma.hip, then k_gram_invert), and every sweep applies
 //     delta_K = M_K b_K,   x_K += delta_K,   r -= H_K delta_K.
 //
 // k_cd_panel runs all sweeps in one cooperative launch.  Workgroup w owns rows
@@ -396,87 +395,6 @@ int panel_max_coresident(bool c128, int kp, int rpl) {
     return 0;
 }
 
-// ============================================================================
-// Panel Gram blocks G_K = H_K^H H_K (lower 64x64 sub-blocks) over a row split, on the
-// vector units (complex64 H; complex128 and the BF16/FP8 copies use the matrix cores).
-// grid.x = npanels * nsub, grid.y = nsplit; 256 threads as a 16 x 16 grid, each
-// accumulating a 4 x 4 complex tile; rows stream through LDS 32 at a time.
-// ============================================================================
-// CROSS: the full block H_K^H H_{K-dist mod npanels} instead (nsub = (kp/64)^2 sub-blocks).
-template <typename T, class Src, bool CROSS = false>
-__global__ __launch_bounds__(256) void k_gram_partial(Src src, int64_t ld, int B, int U, int kp,
-                                                      int nsub, int rows_per_split, cv<T>* __restrict__ gpart,
-                                                      int npanels, int dist = 1) {
-    using V = cv<T>;
-    __shared__ V As[32][64 + 1];
-    __shared__ V Bs[32][64 + 1];
-    const int tid = threadIdx.x;
-    const int K = blockIdx.x / nsub;
-    int sb = blockIdx.x % nsub;
-    int bi = 0, bj = 0;
-    if (CROSS) {
-        bi = sb / (kp / 64);
-        bj = sb % (kp / 64);
-    } else {
-        // sub-block (bi, bj), bi >= bj, enumerated row by row of the lower triangle
-        while (sb > bi) {
-            sb -= bi + 1;
-            ++bi;
-        }
-        bj = sb;
-    }
-    const int split = blockIdx.y;
-    const int r_lo = split * rows_per_split;
-    const int r_hi = min(B, r_lo + rows_per_split);
-    const int ty = tid >> 4, tx = tid & 15;
-    V acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = czero<T>();
-    const int colA0 = K * kp + bi * 64;
-    const int colB0 = (CROSS ? (K + npanels - dist % npanels) % npanels : K) * kp + bj * 64;
-    // a diagonal sub-block multiplies a tile by itself: load it once
-    const bool same = colA0 == colB0;
-    V(*Bp)[64 + 1] = same ? As : Bs;
-    for (int rb = r_lo; rb < r_hi; rb += 32) {
-        // fill: thread -> (row i = tid & 31, column group tid >> 5, + 8 per step)
-        const int i = tid & 31;
-        const int row = rb + i;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int c = (tid >> 5) + 8 * k;
-            const int ca = colA0 + c, cb = colB0 + c;
-            As[i][c] = (row < r_hi && ca < U) ? src.load((int64_t)ca * ld + row, ca) : czero<T>();
-            if (!same) Bs[i][c] = (row < r_hi && cb < U) ? src.load((int64_t)cb * ld + row, cb) : czero<T>();
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int ii = 0; ii < 32; ++ii) {
-            V av[4], bv[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                av[k] = As[ii][ty * 4 + k];
-                bv[k] = Bp[ii][tx * 4 + k];
-            }
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) cfma_conj(acc[p][q], av[p], bv[q]);
-        }
-        __syncthreads();
-    }
-    V* out = gpart + ((int64_t)split * npanels + K) * kp * kp;
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int u = bi * 64 + ty * 4 + p;
-            const int v = bj * 64 + tx * 4 + q;
-            out[(int64_t)u * kp + v] = acc[p][q];
-        }
-}
-
 // Sum the split partials, form D + L (lambda on the diagonal; inactive coordinates
 // with ||h_u||^2 + lambda == 0 decoupled), and invert it row by row:
 //   M_uc = ([u == c] - sum_{c <= v < u} A_uv M_vc) / A_uu.
@@ -567,10 +485,6 @@ static hipError_t launch_invert_t(cv<T>* gpart, int nsplit, int npanels, int kp,
 }
 
 template <typename T> static hipError_t launch_gram_t(const GramLaunch& L, hipStream_t st) {
-    const int nb = L.kp / 64;
-    const int nsub = nb * (nb + 1) / 2;
-    int rps = (L.B + L.nsplit - 1) / L.nsplit;
-    rps = (rps + 31) / 32 * 32;
     if (L.src_kind == SRC_BF16 || L.src_kind == SRC_FP8) {
         // the low-precision copies: matrix cores (FP32 partials, same layout)
         if constexpr (sizeof(T) == 4) {
@@ -579,15 +493,9 @@ template <typename T> static hipError_t launch_gram_t(const GramLaunch& L, hipSt
         } else {
             return hipErrorInvalidValue;
         }
-    } else {
-        if constexpr (sizeof(T) == 8) {   // complex128: FP64 matrix cores
-            hipError_t e = launch_gram_f64(L, false, 1, st);
-            if (e != hipSuccess) return e;
-        } else {
-            hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>>), dim3(L.npanels * nsub, L.nsplit), dim3(256), 0, st,
-                               SrcC<T>{(const cv<T>*)L.H}, L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart,
-                               L.npanels);
-        }
+    } else {   // complex H: FP64 (complex128) or FP32 (complex64) matrix cores
+        hipError_t e = launch_gram_cx(L, false, 1, st);
+        if (e != hipSuccess) return e;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -664,11 +572,6 @@ __global__ __launch_bounds__(256) void k_fold_mx(const V* __restrict__ M, V* __r
 
 template <typename T>
 static hipError_t launch_gram_cross_t(const GramLaunch& L, void* X, hipStream_t st, int dist = 1, bool fold = true) {
-    const int nb = L.kp / 64;
-    const int nsub = nb * nb;
-    int rps = (L.B + L.nsplit - 1) / L.nsplit;
-    rps = (rps + 31) / 32 * 32;
-    const dim3 grid(L.npanels * nsub, L.nsplit);
     if (L.src_kind == SRC_BF16 || L.src_kind == SRC_FP8) {
         if constexpr (sizeof(T) == 4) {
             hipError_t e = launch_gram_lp(L, true, dist, st);
@@ -677,13 +580,8 @@ static hipError_t launch_gram_cross_t(const GramLaunch& L, void* X, hipStream_t 
             return hipErrorInvalidValue;
         }
     } else {
-        if constexpr (sizeof(T) == 8) {
-            hipError_t e = launch_gram_f64(L, true, dist, st);
-            if (e != hipSuccess) return e;
-        } else {
-            hipLaunchKernelGGL((k_gram_partial<T, SrcC<T>, true>), grid, dim3(256), 0, st, SrcC<T>{(const cv<T>*)L.H},
-                               L.ld, L.B, L.U, L.kp, nsub, rps, (cv<T>*)L.gpart, L.npanels, dist);
-        }
+        hipError_t e = launch_gram_cx(L, true, dist, st);
+        if (e != hipSuccess) return e;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

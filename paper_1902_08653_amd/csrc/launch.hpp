@@ -169,8 +169,8 @@ hipError_t launch_gram(const GramLaunch& L, hipStream_t st);
 // layout of the vector kernel's partials): diagonal blocks (lower sub-blocks) or, with
 // cross, the blocks H_K^H H_{K-dist mod npanels}.
 hipError_t launch_gram_lp(const GramLaunch& L, bool cross, int dist, hipStream_t st);
-// The same for complex128 H on the FP64 matrix cores.
-hipError_t launch_gram_f64(const GramLaunch& L, bool cross, int dist, hipStream_t st);
+// The same for complex H (complex128 on the FP64, complex64 on the FP32 matrix cores).
+hipError_t launch_gram_cx(const GramLaunch& L, bool cross, int dist, hipStream_t st);
 // Cross blocks X_K = H_K^H H_{K-1 mod npanels} (full kp x kp, transposed) into X,
 // using gpart as split scratch (call after launch_gram: its contents are consumed,
 // and M is read).  For complex128 with 64-column panels X receives -M_K X_K
