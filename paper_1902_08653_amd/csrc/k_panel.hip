@@ -101,10 +101,12 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T, Src> a) {
 #pragma unroll
         for (int c0 = 0; c0 < PER; c0 += CH) {
             V buf[CH];
+            // every load in range (clamped): a buffer filled under a per-thread condition
+            // would be kept in scratch memory
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
                 const int e = (c0 + k) * PANEL_NT + tid;
-                if (c0 + k < PER && e < NE) buf[k] = src[e];
+                if (c0 + k < PER) buf[k] = src[min(e, NE - 1)];
             }
 #pragma unroll
             for (int k = 0; k < CH; ++k) {

@@ -34,13 +34,13 @@ def relerr(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-def solve(dev, H, y, prec, T, tol=0.0, lookahead=True, x0=None, lam=0.1):
+def solve(dev, H, y, prec, T, tol=0.0, lookahead=True, x0=None, lam=0.1, panel=0):
     """lookahead: True (one panel ahead), "deep" (two panels ahead where complex128 with
     64-column panels has at least three panels, else one) or False (the two-hop
     schedule)."""
     from paper_1902_08653_amd import cdm
     B, U = H.shape
-    plan = cdm.Plan(B, U, precision=prec, T_max=T, tol=tol, engine="panel", lookahead=lookahead)
+    plan = cdm.Plan(B, U, precision=prec, T_max=T, tol=tol, engine="panel", lookahead=lookahead, panel=panel)
     desc = plan.describe()
     dt = DT.get(prec, np.complex128)
     Hd = torch.from_numpy(np.ascontiguousarray(H.T).astype(dt)).to(dev)
@@ -90,6 +90,20 @@ def test_lookahead_equals_two_hop(dev, prec, B, U):
     assert '"schedule": "lookahead"' in da and '"schedule": "two-hop"' in db
     assert ra["sweeps"] == rb["sweeps"] == 4
     assert relerr(xa, xb) <= TOL[prec]
+
+
+@pytest.mark.parametrize("B,U", [(4096, 1000), (16448, 700)])
+def test_two_hop_64_column_panels(dev, orc, B, U):
+    """The two-hop schedule on 64-column complex128 panels (two rows per lane, the planner's
+    only 64-column two-hop form; its M_K staging goes through registers), with a ragged last
+    row block at B = 16448."""
+    rpl = 2
+    inst = inputs.dense_uplink(B, U, 17 + U)
+    x, rec, desc = solve(dev, inst.H, inst.y, "c128", 3, lookahead=False, panel=64)
+    assert '"schedule": "two-hop"' in desc and '"panel": 64' in desc and '"rpl": %d' % rpl in desc, desc
+    ref = orc.local_cd(inst.H, inst.y, 0.1, 3)
+    assert rec["sweeps"] == 3 and rec["flags"] == 0
+    assert relerr(x, ref["x"]) <= 1e-10
 
 
 def test_lookahead_warm_start(dev, orc):
