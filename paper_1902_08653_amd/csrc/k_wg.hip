@@ -413,6 +413,8 @@ template <typename T, int NT, int RMAX> static int occ_t(size_t bytes) {
     return per;
 }
 
+// complex128 runs on at most 512 threads (the planner's choice: its 8-rows-per-thread tile
+// does not fit the register budget of a 1024-thread workgroup), so no such form is built
 #define CDM_WG_DISPATCH_R(FN, c128, nt, rmax, ...)                                             \
     do {                                                                                       \
         if (rmax <= 4) {                                                                       \
@@ -420,7 +422,6 @@ template <typename T, int NT, int RMAX> static int occ_t(size_t bytes) {
                 if (nt == 128) return FN<double, 128, 4>(__VA_ARGS__);                         \
                 if (nt == 256) return FN<double, 256, 4>(__VA_ARGS__);                         \
                 if (nt == 512) return FN<double, 512, 4>(__VA_ARGS__);                         \
-                if (nt == 1024) return FN<double, 1024, 4>(__VA_ARGS__);                       \
             } else {                                                                           \
                 if (nt == 128) return FN<float, 128, 4>(__VA_ARGS__);                          \
                 if (nt == 256) return FN<float, 256, 4>(__VA_ARGS__);                          \
@@ -432,7 +433,6 @@ template <typename T, int NT, int RMAX> static int occ_t(size_t bytes) {
                 if (nt == 128) return FN<double, 128, 8>(__VA_ARGS__);                         \
                 if (nt == 256) return FN<double, 256, 8>(__VA_ARGS__);                         \
                 if (nt == 512) return FN<double, 512, 8>(__VA_ARGS__);                         \
-                if (nt == 1024) return FN<double, 1024, 8>(__VA_ARGS__);                       \
             } else {                                                                           \
                 if (nt == 128) return FN<float, 128, 8>(__VA_ARGS__);                          \
                 if (nt == 256) return FN<float, 256, 8>(__VA_ARGS__);                          \
@@ -448,7 +448,6 @@ template <typename T, int NT, int RMAX> static int occ_t(size_t bytes) {
             if (nt == 128) return FN<double, 128>(__VA_ARGS__);              \
             if (nt == 256) return FN<double, 256>(__VA_ARGS__);              \
             if (nt == 512) return FN<double, 512>(__VA_ARGS__);              \
-            if (nt == 1024) return FN<double, 1024>(__VA_ARGS__);            \
         } else {                                                             \
             if (nt == 128) return FN<float, 128>(__VA_ARGS__);               \
             if (nt == 256) return FN<float, 256>(__VA_ARGS__);               \
