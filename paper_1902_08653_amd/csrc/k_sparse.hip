@@ -117,30 +117,16 @@ __global__ __launch_bounds__(256) void k_csc_sort(const int32_t* __restrict__ co
             rs[wid][k] = rowidx[e0 + k];
             vs[wid][k] = cval[e0 + k];
         }
-        // rank sort: each entry's position = number of smaller rows (rows are unique)
+        // rank sort: each entry's position = number of smaller rows (rows are unique).
+        // The column is in LDS, so each entry goes to its place in global memory at once.
         __builtin_amdgcn_wave_barrier();
-        int32_t myr[CAP / 64];
-        cv<T> myv[CAP / 64];
-        int myp[CAP / 64];
-#pragma unroll
-        for (int q = 0; q < CAP / 64; ++q) {
-            const int k = lane + 64 * q;
-            myp[q] = -1;
-            if (k < len) {
-                const int32_t rk = rs[wid][k];
-                int p = 0;
-                for (int j = 0; j < len; ++j) p += rs[wid][j] < rk ? 1 : 0;
-                myr[q] = rk;
-                myv[q] = vs[wid][k];
-                myp[q] = p;
-            }
+        for (int k = lane; k < len; k += 64) {
+            const int32_t rk = rs[wid][k];
+            int p = 0;
+            for (int j = 0; j < len; ++j) p += rs[wid][j] < rk ? 1 : 0;
+            rowidx[e0 + p] = rk;
+            cval[e0 + p] = vs[wid][k];
         }
-#pragma unroll
-        for (int q = 0; q < CAP / 64; ++q)
-            if (myp[q] >= 0) {
-                rowidx[e0 + myp[q]] = myr[q];
-                cval[e0 + myp[q]] = myv[q];
-            }
     } else if (lane == 0) {
         // long column: in-place insertion sort by one lane
         for (int32_t a = e0 + 1; a < e1; ++a) {
