@@ -64,9 +64,11 @@ typedef enum cdm_precision {
 
 typedef enum cdm_layout { CDM_DENSE = 0, CDM_CSR = 1 } cdm_layout;
 
-/* Engine selection: AUTO lets the plan choose from the shape.
+/* Engine selection: AUTO lets the plan choose from the shape: PANEL for a single instance
+ * (C = 1) with B >= 256 and either U >= 128 or B * U >= 2^18, WG otherwise (several
+ * clusters, narrow or small instances, the downlink).
  * WG    - one workgroup per instance (cluster), residual held in registers.
- * PANEL - one cooperative launch over all CUs for one large instance; columns are
+ * PANEL - one cooperative launch over all CUs for one single instance; columns are
  *         processed in panels of `panel` users whose coupling is resolved exactly
  *         (block form of the cyclic sweep, identical to U sequential updates). */
 typedef enum cdm_engine { CDM_ENGINE_AUTO = 0, CDM_ENGINE_WG = 1, CDM_ENGINE_PANEL = 2 } cdm_engine;

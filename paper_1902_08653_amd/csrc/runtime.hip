@@ -549,10 +549,16 @@ int32_t cdm_create(const cdm_desc* desc, cdm_plan** plan) {
         return CDM_ENOTIMPL;
     }
 
-    // engine choice: one cooperative launch for a single large instance, else WG
+    // engine choice: the panel engine (one cooperative launch, a workgroup per 64-row block)
+    // for a single instance, unless it is narrow; the per-instance engine (one workgroup per
+    // instance or cluster) otherwise.  Measured single-instance solves: the panel engine is
+    // ahead from U = 128 at every B >= 256 (256 x 128 complex128: 3.4 against 5.7 ms; 2048 x
+    // 512: 3.1 against 18.9 ms), behind at U = 64 up to B = 2048 (complex64 0.83 against 0.47
+    // ms), and even or ahead from B * U = 2^18 at U = 64
     int engine = d.engine;
     const double elems = (double)d.B * d.U;
-    if (engine == CDM_ENGINE_AUTO) engine = (d.C == 1 && d.B >= 2048 && elems >= 4.0e6) ? CDM_ENGINE_PANEL : CDM_ENGINE_WG;
+    if (engine == CDM_ENGINE_AUTO)
+        engine = (d.C == 1 && d.B >= 256 && (d.U >= 128 || elems >= 262144.0)) ? CDM_ENGINE_PANEL : CDM_ENGINE_WG;
     if (mixed) engine = CDM_ENGINE_PANEL;
     if (d.problem == CDM_DOWNLINK_ZF) engine = CDM_ENGINE_WG;
     if (engine == CDM_ENGINE_PANEL && d.C != 1) engine = CDM_ENGINE_WG;
