@@ -55,7 +55,6 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T, Src> a) {
     __shared__ V scr[SCR];
     V(*dpart)[KP] = reinterpret_cast<V(*)[KP]>(scr);
     V(*axs)[RPL][64] = reinterpret_cast<V(*)[RPL][64]>(scr);
-    __shared__ T red_s[PANEL_NWV][2];
     __shared__ uint32_t flag_s;
 
     // ctr layout: [2] abort, [3] status, [16, 16+P) partial-arrival flags,
@@ -161,38 +160,31 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T, Src> a) {
             }
             wg_publish(flagsA, w, seq + 1);
             const int Kn = (K + 1 < a.npanels) ? K + 1 : 0;
+            // with a single panel, M_0 and the tile stay in LDS and registers after the first step
+            const bool one = a.npanels == 1;
             if (!reducer) {
                 // M_K first: waiting for its loads must not wait for the tile stream
                 // (vector loads complete in issue order)
-                stage_M(K);
-                load_panel(Kn);
+                if (!one || seq == 0) stage_M(K);
+                if (!one) load_panel(Kn);
             }
 
-            // 2. reducers: g_j = sum of the P partials (fixed order), b_j = g_j - lambda x_j
+            // 2. reducers: g_j = sum of the P partials (fixed order: lane l adds p = l, l + 64,
+            //    ..., then a fixed butterfly), b_j = g_j - lambda x_j.  One wave per column, so
+            //    a reducer's columns are summed side by side with no workgroup barrier.
             if (reducer) {
                 ok = wg_wait_flags(flagsA, P, seq + 1, abort_flag, a.timeout_ticks, &flag_s);
                 if (ok) {
-                    for (int j = w; j < KP; j += P) {
-                        V acc = czero<T>();
-                        for (int p = tid; p < P; p += PANEL_NT) {
+                    for (int j = w + P * wid; j < KP; j += P * PANEL_NWV) {
+                        V g = czero<T>();
+                        for (int p = lane; p < P; p += 64) {
                             const V v = ld_dev(&a.part[((int64_t)par * KP + j) * P + p]);
-                            acc.x += v.x;
-                            acc.y += v.y;
+                            g.x += v.x;
+                            g.y += v.y;
                         }
-                        acc.x = wave_allsum(acc.x);
-                        acc.y = wave_allsum(acc.y);
+                        g.x = wave_allsum(g.x);
+                        g.y = wave_allsum(g.y);
                         if (lane == 0) {
-                            red_s[wid][0] = acc.x;
-                            red_s[wid][1] = acc.y;
-                        }
-                        __syncthreads();
-                        if (tid == 0) {
-                            V g = czero<T>();
-#pragma unroll
-                            for (int v = 0; v < PANEL_NWV; ++v) {
-                                g.x += red_s[v][0];
-                                g.y += red_s[v][1];
-                            }
                             const int u = K * KP + j;
                             const V xo = (u < U) ? a.x[u] : czero<T>();
                             if (a.bias && u < U) {
@@ -206,12 +198,11 @@ __global__ __launch_bounds__(PANEL_NT, 1) void k_cd_panel(PanelArgs<T, Src> a) {
                             st_dev(&a.gbuf[((int64_t)par * KP + j) * 2 + 0], b);
                             st_dev(&a.gbuf[((int64_t)par * KP + j) * 2 + 1], xo);
                         }
-                        __syncthreads();
                     }
                 }
-                wg_publish(flagsB, w, seq + 1);
-                stage_M(K);
-                load_panel(Kn);
+                wg_publish(flagsB, w, seq + 1);   // after every wave's stores (drain + barrier)
+                if (!one || seq == 0) stage_M(K);
+                if (!one) load_panel(Kn);
             }
             if (!ok) break;
 
