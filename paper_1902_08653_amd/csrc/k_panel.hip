@@ -445,7 +445,19 @@ __global__ __launch_bounds__(256) void k_gram_invert(cv<T>* __restrict__ gpart, 
         if (c < kp) {
             V s = (u == c) ? cmake<T>(T(1), T(0)) : czero<T>();
             if (c < u) {
-                for (int v = c; v < u; ++v) cfms(s, arow[v], Mr[(int64_t)v * kp + c]);
+                // four accumulators over v = c, c+1, ... (the chain of dependent FMAs is the
+                // kernel's critical path), added in a fixed order at the end
+                V s1 = czero<T>(), s2 = czero<T>(), s3 = czero<T>();
+                int v = c;
+                for (; v + 3 < u; v += 4) {
+                    cfms(s, arow[v], Mr[(int64_t)v * kp + c]);
+                    cfms(s1, arow[v + 1], Mr[(int64_t)(v + 1) * kp + c]);
+                    cfms(s2, arow[v + 2], Mr[(int64_t)(v + 2) * kp + c]);
+                    cfms(s3, arow[v + 3], Mr[(int64_t)(v + 3) * kp + c]);
+                }
+                for (; v < u; ++v) cfms(s, arow[v], Mr[(int64_t)v * kp + c]);
+                s.x = (s.x + s1.x) + (s2.x + s3.x);
+                s.y = (s.y + s1.y) + (s2.y + s3.y);
             }
             V m = czero<T>();
             if (c <= u && act[u]) {
