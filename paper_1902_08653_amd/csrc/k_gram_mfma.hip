@@ -294,25 +294,32 @@ template <> struct CxMfma<float> {
     static __device__ __forceinline__ int row(int lane, int e) { return 4 * (lane >> 4) + e; }
 };
 constexpr int G64_KS = 32, G64_PITCH = 34;
+// which 64x64 sub-blocks a launch covers: the cross blocks H_K^H H_{K-dist}; the diagonal
+// blocks H_K^H H_K of 64-column panels (lower 16x16 tiles only); every sub-block on or below
+// the diagonal of wider diagonal blocks (whole sub-blocks, one launch)
+enum { GK_CROSS = 0, GK_DIAG = 1, GK_LOWER = 2 };
 
-template <typename T, bool CROSS>
+template <typename T, int KIND>
 __device__ __forceinline__ void gram_cx(const cv<T>* __restrict__ H, int64_t ld, int B, int U, int kp, int nsub,
                                         int rows_per_split, cv<T>* __restrict__ gpart, int npanels, int dist) {
     using V = cv<T>;
     using MM = CxMfma<T>;
     using acc_t = typename MM::acc_t;
-    __shared__ T tile[4][64 * G64_PITCH];   // A re, A im, B re, B im
+    // A re, A im, B re, B im; a diagonal sub-block has one tile for both operands
+    constexpr int NTL = KIND == GK_DIAG ? 2 : 4;
+    __shared__ T tile[NTL][64 * G64_PITCH];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
     const int K = blockIdx.x / nsub;
     int sb = blockIdx.x % nsub;
+    constexpr bool CROSS = KIND == GK_CROSS;
     int bi = 0, bj = 0;
     if (CROSS) {
         bi = sb / (kp / 64);
         bj = sb % (kp / 64);
-    } else {
-        while (sb > bi) {
+    } else if (KIND == GK_LOWER) {
+        while (sb > bi) {   // (bi, bj), bi >= bj, row by row of the lower triangle
             sb -= bi + 1;
             ++bi;
         }
@@ -354,8 +361,27 @@ __device__ __forceinline__ void gram_cx(const cv<T>* __restrict__ H, int64_t ld,
             accr[i][j] = acc_t{T(0), T(0), T(0), T(0)};
             acci[i][j] = acc_t{T(0), T(0), T(0), T(0)};
         }
-    const T* Bre = same ? tile[0] : tile[2];
-    const T* Bim = same ? tile[1] : tile[3];
+    const T* Bre = same ? tile[0] : tile[NTL - 2];
+    const T* Bim = same ? tile[1] : tile[NTL - 1];
+    // The diagonal block of a 64-column panel is Hermitian, and only its lower triangle
+    // (u >= v) is read downstream: its 10 lower 16x16 tiles go to the four waves as 3, 3, 2
+    // and 2 tiles, instead of 4 each.  Neighbouring workgroups take the lists in reverse
+    // wave order, so that the waves sharing a SIMD even out.
+    constexpr bool tri = KIND == GK_DIAG;
+    int tti[3] = {0, 0, 0}, ttj[3] = {0, 0, 0}, nt = 0;
+    if (tri) {
+        const int ws = ((blockIdx.x + blockIdx.y) & 1) ? 3 - wv : wv;
+        // wave lists: (3,0)(3,1)(3,2) | (2,0)(2,1)(3,3) | (1,0)(2,2) | (0,0)(1,1)
+        if (ws == 0) {
+            tti[0] = 3; ttj[0] = 0; tti[1] = 3; ttj[1] = 1; tti[2] = 3; ttj[2] = 2; nt = 3;
+        } else if (ws == 1) {
+            tti[0] = 2; ttj[0] = 0; tti[1] = 2; ttj[1] = 1; tti[2] = 3; ttj[2] = 3; nt = 3;
+        } else if (ws == 2) {
+            tti[0] = 1; ttj[0] = 0; tti[1] = 2; ttj[1] = 2; nt = 2;
+        } else {
+            tti[0] = 0; ttj[0] = 0; tti[1] = 1; ttj[1] = 1; nt = 2;
+        }
+    }
     V va[8], vb[8];
     if (r_lo < r_hi) {
         fetch(va, colA0, r_lo);
@@ -363,38 +389,75 @@ __device__ __forceinline__ void gram_cx(const cv<T>* __restrict__ H, int64_t ld,
     }
     for (int r0 = r_lo; r0 < r_hi; r0 += G64_KS) {
         put(va, tile[0], tile[1]);
-        if (!same) put(vb, tile[2], tile[3]);
+        if (!same) put(vb, tile[NTL - 2], tile[NTL - 1]);
         __syncthreads();
         if (r0 + G64_KS < r_hi) {   // in flight during this step's products
             fetch(va, colA0, r0 + G64_KS);
             if (!same) fetch(vb, colB0, r0 + G64_KS);
         }
+        if constexpr (tri) {
 #pragma unroll 2
-        for (int k0 = 0; k0 < G64_KS; k0 += 4) {
-            const int rk = k0 + (lane >> 4);   // this lane's row of the 4-row step
-            T ar[2], ai[2], br[2], bm[2];
+            for (int k0 = 0; k0 < G64_KS; k0 += 4) {
+                const int rk = k0 + (lane >> 4);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int cu = 32 * qi + 16 * i + (lane & 15);
-                const int cv_ = 32 * qj + 16 * i + (lane & 15);
-                ar[i] = tile[0][cu * G64_PITCH + rk];
-                ai[i] = tile[1][cu * G64_PITCH + rk];
-                br[i] = Bre[cv_ * G64_PITCH + rk];
-                bm[i] = Bim[cv_ * G64_PITCH + rk];
-            }
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    accr[i][j] = MM::mma(ar[i], br[j], accr[i][j]);
-                    accr[i][j] = MM::mma(ai[i], bm[j], accr[i][j]);
-                    acci[i][j] = MM::mma(ar[i], bm[j], acci[i][j]);
-                    acci[i][j] = MM::mma(-ai[i], br[j], acci[i][j]);
+                for (int t = 0; t < 3; ++t) {
+                    if (t < nt) {   // nt is uniform across the wave
+                        const int cu = 16 * tti[t] + (lane & 15);
+                        const int cv_ = 16 * ttj[t] + (lane & 15);
+                        const T ar = tile[0][cu * G64_PITCH + rk], ai = tile[1][cu * G64_PITCH + rk];
+                        const T br = tile[0][cv_ * G64_PITCH + rk], bm = tile[1][cv_ * G64_PITCH + rk];
+                        auto& cr = accr[t >> 1][t & 1];
+                        auto& ci = acci[t >> 1][t & 1];
+                        cr = MM::mma(ar, br, cr);
+                        cr = MM::mma(ai, bm, cr);
+                        ci = MM::mma(ar, bm, ci);
+                        ci = MM::mma(-ai, br, ci);
+                    }
                 }
+            }
+        } else {
+#pragma unroll 2
+            for (int k0 = 0; k0 < G64_KS; k0 += 4) {
+                const int rk = k0 + (lane >> 4);   // this lane's row of the 4-row step
+                T ar[2], ai[2], br[2], bm[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const int cu = 32 * qi + 16 * i + (lane & 15);
+                    const int cv_ = 32 * qj + 16 * i + (lane & 15);
+                    ar[i] = tile[0][cu * G64_PITCH + rk];
+                    ai[i] = tile[1][cu * G64_PITCH + rk];
+                    br[i] = Bre[cv_ * G64_PITCH + rk];
+                    bm[i] = Bim[cv_ * G64_PITCH + rk];
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        accr[i][j] = MM::mma(ar[i], br[j], accr[i][j]);
+                        accr[i][j] = MM::mma(ai[i], bm[j], accr[i][j]);
+                        acci[i][j] = MM::mma(ar[i], bm[j], acci[i][j]);
+                        acci[i][j] = MM::mma(-ai[i], br[j], acci[i][j]);
+                    }
+            }
         }
         __syncthreads();
     }
     V* out = gpart + ((int64_t)split * npanels + K) * kp * kp;
+    if constexpr (tri) {   // the lower tiles only; the upper ones are left unwritten
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            if (t < nt) {
+                const int v = 16 * ttj[t] + (lane & 15);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int u = 16 * tti[t] + MM::row(lane, e);
+                    out[(int64_t)(bi * 64 + u) * kp + bj * 64 + v] =
+                        cmake<T>(accr[t >> 1][t & 1][e], acci[t >> 1][t & 1][e]);
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -408,41 +471,41 @@ __device__ __forceinline__ void gram_cx(const cv<T>* __restrict__ H, int64_t ld,
         }
 }
 
-template <bool CROSS>
+template <int KIND>
 __global__ __launch_bounds__(256) void k_gram_f64(const double2* __restrict__ H, int64_t ld, int B, int U, int kp,
                                                   int nsub, int rows_per_split, double2* __restrict__ gpart,
                                                   int npanels, int dist) {
-    gram_cx<double, CROSS>(H, ld, B, U, kp, nsub, rows_per_split, gpart, npanels, dist);
+    gram_cx<double, KIND>(H, ld, B, U, kp, nsub, rows_per_split, gpart, npanels, dist);
 }
-template <bool CROSS>
+template <int KIND>
 __global__ __launch_bounds__(256) void k_gram_f32(const float2* __restrict__ H, int64_t ld, int B, int U, int kp,
                                                   int nsub, int rows_per_split, float2* __restrict__ gpart,
                                                   int npanels, int dist) {
-    gram_cx<float, CROSS>(H, ld, B, U, kp, nsub, rows_per_split, gpart, npanels, dist);
+    gram_cx<float, KIND>(H, ld, B, U, kp, nsub, rows_per_split, gpart, npanels, dist);
+}
+
+template <int KIND>
+static void launch_gram_kind(const GramLaunch& L, int nsub, int rps, int dist, hipStream_t st) {
+    const dim3 grid(L.npanels * nsub, L.nsplit);
+    if (L.c128)
+        hipLaunchKernelGGL((k_gram_f64<KIND>), grid, dim3(256), 0, st, (const double2*)L.H, L.ld, L.B, L.U, L.kp,
+                           nsub, rps, (double2*)L.gpart, L.npanels, dist);
+    else
+        hipLaunchKernelGGL((k_gram_f32<KIND>), grid, dim3(256), 0, st, (const float2*)L.H, L.ld, L.B, L.U, L.kp,
+                           nsub, rps, (float2*)L.gpart, L.npanels, dist);
 }
 
 hipError_t launch_gram_cx(const GramLaunch& L, bool cross, int dist, hipStream_t st) {
     if (L.src_kind != SRC_COMPLEX || L.kp % 64 != 0 || L.nsplit < 1) return hipErrorInvalidValue;
     const int nb = L.kp / 64;
-    const int nsub = cross ? nb * nb : nb * (nb + 1) / 2;
     int rps = (L.B + L.nsplit - 1) / L.nsplit;
     rps = (rps + G64_KS - 1) / G64_KS * G64_KS;
-    const dim3 grid(L.npanels * nsub, L.nsplit);
-    if (L.c128) {
-        if (cross)
-            hipLaunchKernelGGL((k_gram_f64<true>), grid, dim3(256), 0, st, (const double2*)L.H, L.ld, L.B, L.U, L.kp,
-                               nsub, rps, (double2*)L.gpart, L.npanels, dist);
-        else
-            hipLaunchKernelGGL((k_gram_f64<false>), grid, dim3(256), 0, st, (const double2*)L.H, L.ld, L.B, L.U, L.kp,
-                               nsub, rps, (double2*)L.gpart, L.npanels, dist);
-    } else {
-        if (cross)
-            hipLaunchKernelGGL((k_gram_f32<true>), grid, dim3(256), 0, st, (const float2*)L.H, L.ld, L.B, L.U, L.kp,
-                               nsub, rps, (float2*)L.gpart, L.npanels, dist);
-        else
-            hipLaunchKernelGGL((k_gram_f32<false>), grid, dim3(256), 0, st, (const float2*)L.H, L.ld, L.B, L.U, L.kp,
-                               nsub, rps, (float2*)L.gpart, L.npanels, dist);
-    }
+    if (cross)
+        launch_gram_kind<GK_CROSS>(L, nb * nb, rps, dist, st);
+    else if (nb == 1)
+        launch_gram_kind<GK_DIAG>(L, 1, rps, dist, st);
+    else
+        launch_gram_kind<GK_LOWER>(L, nb * (nb + 1) / 2, rps, dist, st);
     return hipGetLastError();
 }
 
