@@ -394,11 +394,31 @@ int panel_max_coresident(bool c128, int kp, int rpl) {
 // One workgroup of kp threads per panel; thread c owns column c of M.  The rows of M
 // the recurrence reads back live in LDS (dynamic, kp * kp values) where they fit, else in
 // the global scratch Mrow.
-template <typename T>
+// Sum of the Gram partials over the row splits, in place into split 0, for the elements
+// with u >= v of every diagonal block (the only ones the inversion reads); the same fixed
+// order as the inversion's own sum.  One thread per element: the whole chip works on it.
+template <typename V>
+__global__ __launch_bounds__(256) void k_sum_lower(V* __restrict__ part, int nsplit, int64_t n, int kp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t rem = i % ((int64_t)kp * kp);
+    if (rem / kp < rem % kp) return;
+    V s = part[i];
+    for (int k = 1; k < nsplit; ++k) {
+        const V p = part[(int64_t)k * n + i];
+        s.x += p.x;
+        s.y += p.y;
+    }
+    part[i] = s;
+}
+
+// MLDS is a template argument so that the LDS form's accesses to Mr compile to LDS
+// instructions: behind a run-time choice they are generic (flat) accesses, and each one then
+// also waits for the thread's outstanding global loads and stores.
+template <typename T, bool MLDS>
 __global__ __launch_bounds__(256) void k_gram_invert(cv<T>* __restrict__ gpart, int nsplit, int npanels, int kp, int U,
                                                      double lambda, cv<T>* __restrict__ Mcm, cv<T>* __restrict__ Mrow,
-                                                     double* __restrict__ e_out, uint32_t* __restrict__ status,
-                                                     int m_in_lds) {
+                                                     double* __restrict__ e_out, uint32_t* __restrict__ status) {
     using V = cv<T>;
     extern __shared__ __attribute__((aligned(16))) char inv_dyn[];
     const int K = blockIdx.x;
@@ -408,17 +428,28 @@ __global__ __launch_bounds__(256) void k_gram_invert(cv<T>* __restrict__ gpart, 
     __shared__ V arow[256];
     __shared__ T dsh[256];
     __shared__ int act[256];
-    // 1. sum over splits (elements with u >= v), fixed order
-    for (int idx = c; idx < kp * kp; idx += blockDim.x) {
-        const int u = idx / kp, v = idx % kp;
-        if (u < v) continue;
-        V s = A[idx];
+    // 1. sum over splits (elements with u >= v), fixed order.  Thread c (blockDim == kp) owns
+    //    column v = c and is the only thread that reads these elements back below; four rows
+    //    at a time, so that four loads per split are in flight.  (The panel pre-pass sums the
+    //    splits beforehand with k_sum_lower and passes nsplit = 1.)
+    for (int u0 = c; nsplit > 1 && u0 < kp; u0 += 4) {
+        V s[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[i] = (u0 + i < kp) ? A[(int64_t)(u0 + i) * kp + c] : czero<T>();
         for (int sp = 1; sp < nsplit; ++sp) {
-            const V p = gpart[sp * pstride + (int64_t)K * kp * kp + idx];
-            s.x += p.x;
-            s.y += p.y;
+            const V* P = gpart + sp * pstride + (int64_t)K * kp * kp;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (u0 + i < kp) {
+                    const V p = P[(int64_t)(u0 + i) * kp + c];
+                    s[i].x += p.x;
+                    s[i].y += p.y;
+                }
+            }
         }
-        A[idx] = s;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (u0 + i < kp) A[(int64_t)(u0 + i) * kp + c] = s[i];
     }
     __syncthreads();
     // 2. diagonal: energies, activity
@@ -434,12 +465,15 @@ __global__ __launch_bounds__(256) void k_gram_invert(cv<T>* __restrict__ gpart, 
     }
     __syncthreads();
     // 3. inverse of (D + L), row by row
-    V* Mr = m_in_lds ? reinterpret_cast<V*>(inv_dyn) : Mrow + (int64_t)K * kp * kp;
+    V* Mr = MLDS ? reinterpret_cast<V*>(inv_dyn) : Mrow + (int64_t)K * kp * kp;
     V* Mp = Mcm + (int64_t)K * (kp * (kp + 1) / 2);
+    V an = czero<T>();   // this thread's element of the next row of A, loaded a row ahead
     for (int u = 0; u < kp; ++u) {
+        const V acur = an;
+        if (u + 1 < kp && c < u + 1) an = A[(int64_t)(u + 1) * kp + c];
         if (c < u) {
             const bool live = act[u] && act[c];
-            arow[c] = live ? A[(int64_t)u * kp + c] : czero<T>();
+            arow[c] = live ? acur : czero<T>();
         }
         __syncthreads();
         if (c < kp) {
@@ -447,13 +481,38 @@ __global__ __launch_bounds__(256) void k_gram_invert(cv<T>* __restrict__ gpart, 
             if (c < u) {
                 // four accumulators over v = c, c+1, ... (the chain of dependent FMAs is the
                 // kernel's critical path), added in a fixed order at the end
+                // groups of four v; with M in LDS each group's operands are loaded one group
+                // ahead, so that the loads overlap the FMAs (the same sums in the same order;
+                // the compiler may contract the products differently).  With M in global
+                // memory the plain loop measured faster.
                 V s1 = czero<T>(), s2 = czero<T>(), s3 = czero<T>();
                 int v = c;
-                for (; v + 3 < u; v += 4) {
-                    cfms(s, arow[v], Mr[(int64_t)v * kp + c]);
-                    cfms(s1, arow[v + 1], Mr[(int64_t)(v + 1) * kp + c]);
-                    cfms(s2, arow[v + 2], Mr[(int64_t)(v + 2) * kp + c]);
-                    cfms(s3, arow[v + 3], Mr[(int64_t)(v + 3) * kp + c]);
+                if (!MLDS) {
+                    for (; v + 3 < u; v += 4) {
+                        cfms(s, arow[v], Mr[(int64_t)v * kp + c]);
+                        cfms(s1, arow[v + 1], Mr[(int64_t)(v + 1) * kp + c]);
+                        cfms(s2, arow[v + 2], Mr[(int64_t)(v + 2) * kp + c]);
+                        cfms(s3, arow[v + 3], Mr[(int64_t)(v + 3) * kp + c]);
+                    }
+                } else if (v + 3 < u) {
+                    V a0 = arow[v], a1 = arow[v + 1], a2 = arow[v + 2], a3 = arow[v + 3];
+                    V m0 = Mr[(int64_t)v * kp + c], m1 = Mr[(int64_t)(v + 1) * kp + c];
+                    V m2 = Mr[(int64_t)(v + 2) * kp + c], m3 = Mr[(int64_t)(v + 3) * kp + c];
+                    for (v += 4; v + 3 < u; v += 4) {
+                        const V b0 = arow[v], b1 = arow[v + 1], b2 = arow[v + 2], b3 = arow[v + 3];
+                        const V n0 = Mr[(int64_t)v * kp + c], n1 = Mr[(int64_t)(v + 1) * kp + c];
+                        const V n2 = Mr[(int64_t)(v + 2) * kp + c], n3 = Mr[(int64_t)(v + 3) * kp + c];
+                        cfms(s, a0, m0);
+                        cfms(s1, a1, m1);
+                        cfms(s2, a2, m2);
+                        cfms(s3, a3, m3);
+                        a0 = b0; a1 = b1; a2 = b2; a3 = b3;
+                        m0 = n0; m1 = n1; m2 = n2; m3 = n3;
+                    }
+                    cfms(s, a0, m0);
+                    cfms(s1, a1, m1);
+                    cfms(s2, a2, m2);
+                    cfms(s3, a3, m3);
                 }
                 for (; v < u; ++v) cfms(s, arow[v], Mr[(int64_t)v * kp + c]);
                 s.x = (s.x + s1.x) + (s2.x + s3.x);
@@ -479,13 +538,17 @@ static hipError_t launch_invert_t(cv<T>* gpart, int nsplit, int npanels, int kp,
     const size_t mb = (size_t)kp * kp * sizeof(cv<T>);
     int in_lds = mb <= (size_t)128 * 1024;
     if (in_lds && mb > 64 * 1024 &&
-        hipFuncSetAttribute((const void*)k_gram_invert<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mb) !=
+        hipFuncSetAttribute((const void*)k_gram_invert<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mb) !=
             hipSuccess) {
         (void)hipGetLastError();
         in_lds = 0;
     }
-    hipLaunchKernelGGL(k_gram_invert<T>, dim3(npanels), dim3(kp), in_lds ? mb : 0, st, gpart, nsplit, npanels, kp, U,
-                       lambda, M, Mrow, e, status, in_lds);
+    if (in_lds)
+        hipLaunchKernelGGL((k_gram_invert<T, true>), dim3(npanels), dim3(kp), mb, st, gpart, nsplit, npanels, kp, U,
+                           lambda, M, Mrow, e, status);
+    else
+        hipLaunchKernelGGL((k_gram_invert<T, false>), dim3(npanels), dim3(kp), 0, st, gpart, nsplit, npanels, kp, U,
+                           lambda, M, Mrow, e, status);
     return hipGetLastError();
 }
 
@@ -506,10 +569,17 @@ template <typename T> static hipError_t launch_gram_t(const GramLaunch& L, hipSt
     if (e != hipSuccess) return e;
     // M is written twice: column-major (used by the sweep) and row-major (the
     // recurrence reads its own earlier rows); the row-major copy lives in the
-    // split-1 slot of gpart when nsplit > 1, else right after M.
+    // split-1 slot of gpart (at least two slots), free once the splits are summed.
     cv<T>* Mrow = (cv<T>*)L.gpart + (int64_t)L.npanels * L.kp * L.kp;
-    return launch_invert_t<T>((cv<T>*)L.gpart, L.nsplit, L.npanels, L.kp, L.U, L.lambda, (cv<T>*)L.M, Mrow, L.e,
-                              L.status, st);
+    if (L.nsplit > 1) {
+        const int64_t n = (int64_t)L.npanels * L.kp * L.kp;
+        hipLaunchKernelGGL(k_sum_lower<cv<T>>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (cv<T>*)L.gpart,
+                           L.nsplit, n, L.kp);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return launch_invert_t<T>((cv<T>*)L.gpart, 1, L.npanels, L.kp, L.U, L.lambda, (cv<T>*)L.M, Mrow, L.e, L.status,
+                              st);
 }
 
 hipError_t launch_gram_invert(bool c128, void* gpart, int nsplit, int npanels, int kp, int U, double lambda, void* M,
