@@ -145,15 +145,45 @@ __global__ __launch_bounds__(256) void k_csc_sort(const int32_t* __restrict__ co
 }
 
 // ---- sparse panel Gram: G_uv = sum over common rows of conj(h_u) h_v ---------
-// One workgroup per panel, one thread per (u >= v) pair, two-pointer merge of the
-// two sorted row lists.  Output row-major [npanels][kp][kp] (lower part).
+// SG_SPLIT workgroups per panel, one thread per (u >= v) pair, two-pointer merge of the
+// two sorted row lists.  The merge is a chain of dependent loads, so the panel's row
+// indices are staged in LDS first when they fit (SG_LDS entries, 64 KB); the values are
+// read from global memory on matches only.  Output row-major [npanels][kp][kp] (lower part).
+constexpr int SG_SPLIT = 4, SG_LDS = 16384;
 template <typename T>
 __global__ __launch_bounds__(256) void k_sparse_gram(const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
                                                      const cv<T>* __restrict__ cval, int U, int kp,
                                                      cv<T>* __restrict__ G) {
+    __shared__ int32_t rs[SG_LDS];
     const int K = blockIdx.x;
     const int npair = kp * (kp + 1) / 2;
-    for (int pidx = threadIdx.x; pidx < npair; pidx += blockDim.x) {
+    const int c0 = K * kp, c1 = min(U, c0 + kp);
+    const int32_t base = colptr[c0];
+    const int32_t cnt = colptr[c1] - base;
+    const bool staged = cnt <= SG_LDS;
+    if (staged)
+        for (int k = threadIdx.x; k < cnt; k += blockDim.x) rs[k] = rowidx[base + k];
+    __syncthreads();
+    // the merge of columns u and v, with the row index of entry k from ld(k)
+    auto merge = [&](int u, int v, auto ld, double& sr, double& si) {
+        int32_t i = colptr[u], ie = colptr[u + 1];
+        int32_t j = colptr[v], je = colptr[v + 1];
+        while (i < ie && j < je) {
+            const int32_t ri = ld(i), rj = ld(j);
+            if (ri == rj) {
+                const cv<T> hu = cval[i], hv = cval[j];
+                sr += (double)hu.x * hv.x + (double)hu.y * hv.y;
+                si += (double)hu.x * hv.y - (double)hu.y * hv.x;
+                ++i;
+                ++j;
+            } else if (ri < rj) {
+                ++i;
+            } else {
+                ++j;
+            }
+        }
+    };
+    for (int pidx = threadIdx.x + blockDim.x * blockIdx.y; pidx < npair; pidx += blockDim.x * SG_SPLIT) {
         // pair index -> (a >= b) in row-major lower order
         int a = 0, rem = pidx;
         while (rem > a) {
@@ -164,22 +194,10 @@ __global__ __launch_bounds__(256) void k_sparse_gram(const int32_t* __restrict__
         const int u = K * kp + a, v = K * kp + b;
         double sr = 0.0, si = 0.0;
         if (u < U && v < U) {
-            int32_t i = colptr[u], ie = colptr[u + 1];
-            int32_t j = colptr[v], je = colptr[v + 1];
-            while (i < ie && j < je) {
-                const int32_t ri = rowidx[i], rj = rowidx[j];
-                if (ri == rj) {
-                    const cv<T> hu = cval[i], hv = cval[j];
-                    sr += (double)hu.x * hv.x + (double)hu.y * hv.y;
-                    si += (double)hu.x * hv.y - (double)hu.y * hv.x;
-                    ++i;
-                    ++j;
-                } else if (ri < rj) {
-                    ++i;
-                } else {
-                    ++j;
-                }
-            }
+            if (staged)
+                merge(u, v, [&](int32_t k) { return rs[k - base]; }, sr, si);
+            else
+                merge(u, v, [&](int32_t k) { return rowidx[k]; }, sr, si);
         }
         G[((int64_t)K * kp + a) * kp + b] = cmake<T>((T)sr, (T)si);
     }
@@ -745,8 +763,8 @@ template <typename T> static hipError_t launch_sparse_t(const SparseLaunch& L, h
     e = hipGetLastError();
     if (e != hipSuccess || L.transpose_only) return e;
     // 2. panel Gram blocks and (D + L)^-1
-    hipLaunchKernelGGL((k_sparse_gram<T>), dim3(L.npanels), dim3(256), 0, st, L.colptr, L.rowidx, (const V*)L.cval,
-                       L.U, SR_KP, (V*)L.gpart);
+    hipLaunchKernelGGL((k_sparse_gram<T>), dim3(L.npanels, SG_SPLIT), dim3(256), 0, st, L.colptr, L.rowidx,
+                       (const V*)L.cval, L.U, SR_KP, (V*)L.gpart);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = launch_gram_invert(L.c128, L.gpart, 1, L.npanels, SR_KP, L.U, L.lambda, L.M, L.e, L.status, st);
