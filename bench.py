@@ -39,7 +39,7 @@ TRAFFIC = {
     ("k_cd_wg", "c64 batch 4096 tol 1e-06"): {
         "sources": ['paper_1902_08653_amd/csrc/k_wg.hip', 'paper_1902_08653_amd/csrc/common.hpp', 'paper_1902_08653_amd/csrc/wg.hpp'], "sha256_16": "247b0c159f0cd8bb", "bytes": 713278845676.0},
     ("k_cd_sparse", "c128 16384x8192 0.01 tol 1e-11"): {
-        "sources": ['paper_1902_08653_amd/csrc/k_sparse.hip', 'paper_1902_08653_amd/csrc/common.hpp', 'paper_1902_08653_amd/csrc/launch.hpp'], "sha256_16": "2c56dba87335ddb2", "bytes": 9869837984.0},
+        "sources": ['paper_1902_08653_amd/csrc/k_sparse.hip', 'paper_1902_08653_amd/csrc/common.hpp', 'paper_1902_08653_amd/csrc/launch.hpp'], "sha256_16": "3b4e73b3b5f40875", "bytes": 9869837984.0},
     ("k_bm_resid + k_bm_grad + k_bm_inner", "mixed-c64 batch 4096 tol 1e-08"): {
         "sources": ['paper_1902_08653_amd/csrc/k_wg_mixed.hip', 'paper_1902_08653_amd/csrc/common.hpp', 'paper_1902_08653_amd/csrc/wg.hpp', 'paper_1902_08653_amd/csrc/quant.hpp'], "sha256_16": "a27fee61a3afae15", "bytes": 1178767779708.0},
 }

@@ -88,12 +88,16 @@ __global__ __launch_bounds__(1024) void k_scan_inplace(int32_t* __restrict__ a, 
 }
 
 template <typename T>
-__global__ void k_csr_fill(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
-                           const cv<T>* __restrict__ val, int B, int32_t* __restrict__ fill,
-                           int32_t* __restrict__ rowidx, cv<T>* __restrict__ cval, const uint32_t* status) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_csr_fill(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                                  const cv<T>* __restrict__ val, int B, int32_t* __restrict__ fill,
+                                                  int32_t* __restrict__ rowidx, cv<T>* __restrict__ cval,
+                                                  const uint32_t* status) {
+    // one wave per row: the row's entries take their slots in parallel, one returning atomic
+    // each (the order within a column is arbitrary either way; k_csc_sort puts it in row order)
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (i >= B || csr_bad(status)) return;
-    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+    for (int32_t k = rowptr[i] + lane; k < rowptr[i + 1]; k += 64) {
         const int32_t pos = atomicAdd(&fill[colidx[k]], 1);
         rowidx[pos] = i;
         cval[pos] = val[k];
@@ -757,7 +761,7 @@ template <typename T> static hipError_t launch_sparse_t(const SparseLaunch& L, h
                            L.status);
     }
     hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, st, L.colptr, L.U + 1, L.fill);
-    hipLaunchKernelGGL((k_csr_fill<T>), dim3((L.B + 255) / 256), dim3(256), 0, st, L.rowptr, L.colidx,
+    hipLaunchKernelGGL((k_csr_fill<T>), dim3((L.B + 3) / 4), dim3(256), 0, st, L.rowptr, L.colidx,
                        (const V*)L.val, L.B, L.fill, L.rowidx, (V*)L.cval, L.status);
     hipLaunchKernelGGL((k_csc_sort<T>), dim3((L.U + 3) / 4), dim3(256), 0, st, L.colptr, L.U, L.rowidx, (V*)L.cval);
     e = hipGetLastError();
