@@ -180,19 +180,17 @@ __global__ __launch_bounds__(256) void k_gram_lp(const typename LpFmt<FMT>::E* _
     const int fk = (lane >> 4) * (KS / 4);   // first row of this lane's fragment
     const E* Bre = same ? tile[0] : tile[2];
     const E* Bim = same ? tile[1] : tile[3];
+    // BF16: two register sets, the rows of step n + 2 fetched while step n computes, so each
+    // step's loads have two steps' time to land before they are put into LDS.  FP8 (a
+    // fragment is twice the registers) keeps one set: two would halve its occupancy.
+    constexpr bool TWO = FMT == SRC_BF16;
     Chunk ar_[CPT], ai_[CPT], br_[CPT], bi_[CPT];
+    Chunk ar2[TWO ? CPT : 1], ai2[TWO ? CPT : 1], br2[TWO ? CPT : 1], bi2[TWO ? CPT : 1];
     if (r_lo < r_hi) {
         fetch(ar_, ai_, colA0, r_lo);
         if (!same) fetch(br_, bi_, colB0, r_lo);
     }
-    for (int r0 = r_lo; r0 < r_hi; r0 += KS) {
-        put(ar_, ai_, tile[0], tile[1]);
-        if (!same) put(br_, bi_, tile[2], tile[3]);
-        __syncthreads();
-        if (r0 + KS < r_hi) {   // in flight during this step's products
-            fetch(ar_, ai_, colA0, r0 + KS);
-            if (!same) fetch(br_, bi_, colB0, r0 + KS);
-        }
+    auto compute = [&]() {
         Frag ar[2], ai[2], an[2], br[2], bim[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -213,7 +211,45 @@ __global__ __launch_bounds__(256) void k_gram_lp(const typename LpFmt<FMT>::E* _
                 acci[i][j] = mma(ar[i], bim[j], acci[i][j]);
                 acci[i][j] = mma(an[i], br[j], acci[i][j]);
             }
+    };
+    if constexpr (!TWO) {
+        for (int r0 = r_lo; r0 < r_hi; r0 += KS) {
+            put(ar_, ai_, tile[0], tile[1]);
+            if (!same) put(br_, bi_, tile[2], tile[3]);
+            __syncthreads();
+            if (r0 + KS < r_hi) {   // in flight during this step's products
+                fetch(ar_, ai_, colA0, r0 + KS);
+                if (!same) fetch(br_, bi_, colB0, r0 + KS);
+            }
+            compute();
+            __syncthreads();
+        }
+    } else {
+    if (r_lo + KS < r_hi) {
+        fetch(ar2, ai2, colA0, r_lo + KS);
+        if (!same) fetch(br2, bi2, colB0, r_lo + KS);
+    }
+    for (int r0 = r_lo; r0 < r_hi; r0 += 2 * KS) {
+        put(ar_, ai_, tile[0], tile[1]);
+        if (!same) put(br_, bi_, tile[2], tile[3]);
         __syncthreads();
+        if (r0 + 2 * KS < r_hi) {
+            fetch(ar_, ai_, colA0, r0 + 2 * KS);
+            if (!same) fetch(br_, bi_, colB0, r0 + 2 * KS);
+        }
+        compute();
+        __syncthreads();
+        if (r0 + KS >= r_hi) break;   // uniform across the workgroup
+        put(ar2, ai2, tile[0], tile[1]);
+        if (!same) put(br2, bi2, tile[2], tile[3]);
+        __syncthreads();
+        if (r0 + 3 * KS < r_hi) {
+            fetch(ar2, ai2, colA0, r0 + 3 * KS);
+            if (!same) fetch(br2, bi2, colB0, r0 + 3 * KS);
+        }
+        compute();
+        __syncthreads();
+    }
     }
 
     // D[16 x 16]: lane holds rows 4 (lane >> 4) .. + 3 of column lane & 15
